@@ -1,0 +1,270 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched Galerkin assembly hot path on one MI355X.
+
+Workload: 3D Poisson with P1 tetrahedra on the unit cube, 64^3 grid, 6 Kuhn
+tets per cube (1,572,864 elements, 274,625 vertices), interior vertices
+jittered by U(-0.15h, 0.15h), a = exp(N(0,1)) and f = U(-1,1) per element
+(seed 0, synthetic).  One step = the whole hot path on resident inputs:
+FP64 assembly of K and F (one fused Map+Reduce kernel), Dirichlet elimination
+on all faces, and Jacobi-PCG to a relative residual of 1e-8.  The CSR
+pattern and routing are built once, before the timed region (timed apart).
+
+Before each step's assembly a 1 GiB read-modify-write of a scratch buffer
+evicts the 256 MB Infinity Cache, so the assembly reads its inputs from HBM
+(the "cold" protocol); warm numbers are reported beside it.
+
+Prints ONE JSON line.  `value` is assembled elements/s of the FP64 assembly
+kernel (mean duration over the timed steps, measured with HIP events on its
+stream); `ms_per_step` is the wall time of one whole step.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "assembled elements/s + HBM GB/s (FP64 vs FP32); p50/p99 assemble+solve latency"
+
+
+def source_hash() -> str:
+    """Hash of the kernel sources; a stored counter measurement is used only if it matches."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2602_05052_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel: str):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(kernel)
+    if not ent or ent.get("source_hash") != source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def p1_bytes(nv, dim, E, nnz, ndof, s, n_coef):
+    """Algorithmic bytes of one P1 assembly call: inputs and outputs (b_min) plus the routing (b_alg)."""
+    k = dim + 1
+    b_min = nv * dim * 8 + E * k * 4 + E * n_coef * s + nnz * s + ndof * s
+    routing = E * k * k * 4 + (nnz + 1) * 4 + E * k * 4 + (nv + 1) * 4
+    return b_min, b_min + routing
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=64, help="grid cells per axis (64 = the benchmark mesh)")
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (profiling runs)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle timing sample")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import meshgen
+    import paper_2602_05052_amd as tg
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+
+    # ---------------------------------------------------------------- inputs (resident in HBM)
+    d = meshgen.poisson_inputs(3, args.n, seed=0)
+    E, nv = d["conn"].shape[0], d["coords"].shape[0]
+    t0 = time.perf_counter()
+    pat = tg.Pattern(d["conn"], nv)
+    pattern_s = time.perf_counter() - t0
+    coords = torch.from_numpy(d["coords"]).to(dev)
+    a64 = torch.from_numpy(d["a"]).to(dev)
+    f64 = torch.from_numpy(d["f"]).to(dev)
+    a32, f32 = a64.float(), f64.float()
+    vals = torch.empty(pat.nnz, dtype=torch.float64, device=dev)
+    rhs = torch.empty(pat.n_dofs, dtype=torch.float64, device=dev)
+    vals32 = torch.empty(pat.nnz, dtype=torch.float32, device=dev)
+    rhs32 = torch.empty(pat.n_dofs, dtype=torch.float32, device=dev)
+    x = torch.empty(pat.n_dofs, dtype=torch.float64, device=dev)
+    flush = torch.zeros(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+    s = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize()
+
+    def assemble64():
+        tg.assemble(pat, tg.LAPLACE, coords, a64, f64, values=vals, rhs=rhs, stream=s)
+
+    def assemble32():
+        tg.assemble(pat, tg.LAPLACE, coords, a32, f32, values=vals32, rhs=rhs32, stream=s)
+
+    # ---------------------------------------------------------------- timed steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    iters, relres = [], []
+    print(f"# bench: E={E} nnz={pat.nnz} dofs={pat.n_dofs}; warmup {args.warmup}, steps {args.steps}", file=sys.stderr,
+          flush=True)
+    with torch.cuda.stream(s):
+        for w in range(args.warmup):
+            flush.add_(1.0)
+            assemble64()
+            tg.apply_dirichlet(pat, vals, rhs, stream=s)
+            tg.pcg(pat, vals, rhs, rtol=args.rtol, x=x, stream=s, check_every=25)
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        for k in range(args.steps):
+            flush.add_(1.0)
+            ev[k][0].record(s)
+            assemble64()
+            ev[k][1].record(s)
+            tg.apply_dirichlet(pat, vals, rhs, stream=s)
+            _, it, rr = tg.pcg(pat, vals, rhs, rtol=args.rtol, x=x, stream=s, check_every=25)
+            ev[k][2].record(s)
+            iters.append(it)
+            relres.append(rr)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+    print(f"# timed steps done: {wall:.3f} s", file=sys.stderr, flush=True)
+    t_asm = np.array([e[0].elapsed_time(e[1]) for e in ev]) * 1e-3  # s
+    t_step = np.array([e[0].elapsed_time(e[2]) for e in ev]) * 1e-3
+    t_solve = t_step - t_asm
+
+    # ---------------------------------------------------------------- side legs (outside the timed region)
+    def time_kernel(fn, reps, cold):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        with torch.cuda.stream(s):
+            fn()
+            for e0, e1 in evs:
+                if cold:
+                    flush.add_(1.0)
+                e0.record(s)
+                fn()
+                e1.record(s)
+        torch.cuda.synchronize()
+        return np.array([e0.elapsed_time(e1) for e0, e1 in evs]) * 1e-3
+
+    t64_warm = time_kernel(assemble64, 20, cold=False)
+    t32_cold = time_kernel(assemble32, 20, cold=True)
+    t32_warm = time_kernel(assemble32, 20, cold=False)
+    # bitwise repeatability of the FP64 assembly
+    ref_vals = vals.clone()
+    assemble64()
+    torch.cuda.synchronize()
+    bitwise = bool(torch.equal(ref_vals, vals))
+
+    bmin64, balg64 = p1_bytes(nv, 3, E, pat.nnz, pat.n_dofs, 8, 2)
+    bmin32, balg32 = p1_bytes(nv, 3, E, pat.nnz, pat.n_dofs, 4, 2)
+    mean_asm = float(t_asm.mean())
+    gbs = balg64 / mean_asm / 1e9
+    traffic = stored_traffic("p1_assemble_kernel<3,double,laplace>")
+
+    out = {
+        "metric": METRIC,
+        "value": E / mean_asm,
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"3D Poisson P1 tets, unit cube {args.n}^3 x 6 Kuhn tets, jitter 0.15h, a=exp(N(0,1)), "
+                        f"f=U(-1,1), seed 0; FP64 assembly + Dirichlet on all faces + Jacobi-PCG to {args.rtol:g}",
+            "elements": E, "vertices": nv, "nnz": pat.nnz, "dofs": pat.n_dofs,
+            "constrained_dofs": pat.n_constrained, "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": "p1_assemble_kernel<3,double,laplace>",
+            "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": balg64, "bytes_per_element": balg64 / E,
+            "b_min_bytes_per_launch": bmin64,
+        },
+        "assembly": {
+            "fp64_cold_us": {"mean": mean_asm * 1e6, "p50": float(np.median(t_asm)) * 1e6},
+            "fp64_warm_us": {"mean": float(t64_warm.mean()) * 1e6, "p50": float(np.median(t64_warm)) * 1e6},
+            "fp32_cold_us": {"mean": float(t32_cold.mean()) * 1e6, "p50": float(np.median(t32_cold)) * 1e6},
+            "fp32_warm_us": {"mean": float(t32_warm.mean()) * 1e6, "p50": float(np.median(t32_warm)) * 1e6},
+            "fp64_elements_per_s": E / mean_asm,
+            "fp32_elements_per_s": E / float(t32_cold.mean()),
+            "fp64_gbs_b_alg": gbs, "fp32_gbs_b_alg": balg32 / float(t32_cold.mean()) / 1e9,
+            "fp64_gbs_b_min": bmin64 / mean_asm / 1e9, "fp32_gbs_b_min": bmin32 / float(t32_cold.mean()) / 1e9,
+            "bitwise_repeatable": bitwise,
+            "pattern_build_s": pattern_s,
+        },
+        "solve": {
+            "pcg_iterations": int(np.median(iters)), "relres_max": float(max(relres)),
+            "solve_ms_p50": float(np.median(t_solve)) * 1e3,
+            "us_per_iteration": float(np.median(t_solve) / max(1, np.median(iters))) * 1e6,
+        },
+        "latency_ms": {"assemble_solve_p50": float(np.percentile(t_step, 50)) * 1e3,
+                       "assemble_solve_p99": float(np.percentile(t_step, 99)) * 1e3,
+                       "samples": int(len(t_step))},
+    }
+
+    # ---------------------------------------------------------------- CPU baseline (the oracle, as it stands)
+    if not args.no_cpu_baseline:
+        import oracle
+
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        rp, ci = oracle.csr_pattern(nv, d["conn"])
+        calls, t_cpu = 0, 0.0
+        ovals = orhs = None
+        while t_cpu < args.cpu_seconds or calls < 2:
+            c0 = time.perf_counter()
+            ovals, orhs = oracle.assemble_p1_values(d["coords"], d["conn"], d["a"], d["f"], rp, ci)
+            t_cpu += time.perf_counter() - c0
+            calls += 1
+        out["cpu_baseline"] = {
+            "value": calls * E / t_cpu, "unit": "elements/s", "cores": 1, "kind": "oracle",
+            "sample": f"{calls} full value+load assemblies of the same {E}-element mesh by the serial FP64 C oracle "
+                      f"(CSR pattern prebuilt, not timed), {t_cpu:.1f} s",
+            "cpu": _cpu_model(),
+        }
+        # error of the GPU results against the oracle (normwise, max abs row sum)
+        tg.assemble(pat, tg.LAPLACE, coords, a64, f64, values=vals, rhs=rhs)
+        assemble32()
+        torch.cuda.synchronize()
+        row = np.repeat(np.arange(pat.n_dofs), np.diff(rp))
+        den = np.bincount(row, np.abs(ovals)).max()
+        for name, v in (("fp64", vals), ("fp32", vals32)):
+            diff = np.abs(v.double().cpu().numpy() - ovals)
+            out["assembly"][f"{name}_err_vs_oracle"] = float(np.bincount(row, diff).max() / den)
+
+    print(json.dumps(out))
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip() + f" ({os.cpu_count()} logical CPUs visible)"
+    except OSError:
+        pass
+    return None
+
+
+if __name__ == "__main__":
+    main()

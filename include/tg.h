@@ -1,0 +1,234 @@
+/*
+ * tg.h -- C ABI of libtg: batched Galerkin assembly on unstructured simplicial
+ * meshes for AMD Instinct MI355X (gfx950), after TensorGalerkin
+ * (arXiv 2602.05052).
+ *
+ * The method (Sec. 2 "The TensorGalerkin Framework"):
+ *   Stage I, Batch-Map (Alg. 1, eq. kloc1): for every element e, the Jacobian J
+ *     of the affine map from the reference simplex, |det J|, the physical basis
+ *     gradients G = J^{-T} grad(phi_hat), and the quadrature-weighted local
+ *     matrix K_e and vector F_e.
+ *   Stage II, Sparse-Reduce (Alg. 2 and the two projections above it): the
+ *     global CSR values and right-hand side as fixed 0/1 routing applied to the
+ *     flattened local tensors, i.e. for every CSR entry the sum of the element
+ *     slots that map to it.  The routing depends only on the mesh topology and
+ *     is built once per mesh.
+ * Sums here are deterministic: each CSR entry adds its element contributions in
+ * ascending element order, with no atomics, so repeated calls give bitwise
+ * identical results on the same inputs.
+ *
+ * Conventions for every function:
+ *   - every function returns tg_status (0 = success, < 0 = error) and never
+ *     throws; on error tg_last_error() describes it;
+ *   - "host" pointers are CPU memory, read during the call only;
+ *   - "device" pointers are GPU memory owned by the caller (e.g. torch tensors)
+ *     that must stay alive until the work enqueued on `stream` has completed;
+ *   - `stream` is a hipStream_t (NULL = the default stream); kernels are
+ *     enqueued on it and the call returns without waiting unless stated;
+ *   - the library allocates device memory only in tg_pattern_create;
+ *   - all indices are 0-based int32; sizes are int64.
+ */
+#ifndef TG_H
+#define TG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TG_OK = 0,
+    TG_E_ARG = -1,        /* invalid argument (detected on the host, nothing enqueued) */
+    TG_E_DEGENERATE = -2, /* an element has det J == 0 (host-detected cases)          */
+    TG_E_NONFINITE = -3,  /* a non-finite value was found (host-detected cases)       */
+    TG_E_NOMEM = -4,      /* hipMalloc or host allocation failed                      */
+    TG_E_HIP = -5,        /* a HIP runtime call failed                                */
+    TG_E_NOCONV = -6,     /* tg_pcg reached max_iter without meeting rtol             */
+    TG_E_STATE = -7       /* object in the wrong state (e.g. host-only pattern)       */
+} tg_status;
+
+typedef enum { TG_F64 = 0, TG_F32 = 1 } tg_dtype;
+
+/*
+ * Bilinear/linear forms (Sec. 2 eq. pde1 with the examples of SM A.2, SM A.1
+ * and Sec. B.1.1):
+ *   TG_LAPLACE    K_ij = int a grad(phi_j).grad(phi_i), F_i = int f phi_i
+ *                 (P1, scalar; SM A.2)
+ *   TG_MASS       M_ij = int phi_j phi_i  (P1, scalar; the mass inner product
+ *                 of SM A.1); no right-hand side
+ *   TG_ELASTICITY K_(i,c),(j,c') = int lambda div(phi_j e_c') div(phi_i e_c)
+ *                 + 2 mu eps(phi_j e_c') : eps(phi_i e_c),  F_(i,c) = int b_c phi_i
+ *                 (P2 tetrahedra, Hooke's law of Sec. B.1.1); DoF = 3*node + c
+ */
+typedef enum { TG_LAPLACE = 0, TG_MASS = 1, TG_ELASTICITY = 2 } tg_form;
+
+typedef struct tg_pattern tg_pattern; /* opaque, library-owned */
+
+/* Pass as n_dirichlet (with dirichlet_vertices = NULL) to constrain every
+ * vertex of the topological boundary (faces that belong to one element). */
+#define TG_BOUNDARY_ALL (-1)
+
+/* Value a device status word must hold before tg_assemble (see there). */
+#define TG_STATUS_CLEAN INT32_MAX
+
+/* tg_pattern_create flag: build host arrays only (no GPU needed); such a
+ * pattern can be queried and copied out but not assembled or solved on. */
+#define TG_PATTERN_HOST_ONLY 1u
+
+typedef struct {
+    int32_t dim, order, ncomp;
+    int32_t nodes_per_element; /* k: 3 or 4 (P1), 10 (P2)                     */
+    int64_t n_vertices, n_elements;
+    int64_t n_nodes;           /* vertices (P1) or vertices + edges (P2)      */
+    int64_t n_dofs;            /* ncomp * n_nodes: rows of K, length of F     */
+    int64_t nnz;               /* scalar CSR entries (both triangles)         */
+    int64_t n_constrained;     /* Dirichlet DoFs                              */
+    int64_t n_blocks;          /* row blocks of the fused assembly kernel     */
+    const int32_t *d_row_ptr;  /* device [n_dofs + 1], NULL if host-only     */
+    const int32_t *d_col_idx;  /* device [nnz], NULL if host-only             */
+    size_t device_bytes;       /* device memory owned by the pattern          */
+} tg_pattern_info;
+
+/* Text of the last error on the calling thread; valid until its next tg_ call. */
+const char *tg_last_error(void);
+
+/* Library version string. */
+const char *tg_version(void);
+
+/*
+ * Build the CSR pattern and the routing of one mesh topology ("precompute
+ * sparse binary routing matrices based solely on mesh topology", Sec. 2
+ * Stage II).  Done once per mesh; every later call reuses it.
+ *
+ *   dim, order, ncomp : (2|3, 1, 1) for P1 scalar forms, (3, 2, 3) for P2
+ *                       elasticity; anything else is TG_E_ARG.
+ *   conn              : host [n_elements][dim+1] vertex ids of each simplex
+ *                       (any orientation; |det J| is used, Sec. 2 eq. kloc1).
+ *   dirichlet_vertices: host [n_dirichlet] constrained vertex ids, or NULL with
+ *                       n_dirichlet = 0 (none) or TG_BOUNDARY_ALL.  For P2 an
+ *                       edge node is constrained when its edge lies on a
+ *                       boundary face whose three vertices are all constrained.
+ *   flags             : 0 or TG_PATTERN_HOST_ONLY.
+ *   out               : receives the new pattern (NULL on error).
+ * Errors: TG_E_ARG for bad sizes, ids out of range, repeated vertices in an
+ * element, vertices used by no element, or a node shared by more elements
+ * than the kernel's block capacity (512 for P1, 64 for P2); TG_E_NOMEM; TG_E_HIP.
+ * P1 nodes are the vertices; P2 nodes are the vertices followed by the edges
+ * ranked by their (min vertex, max vertex) pair.
+ */
+tg_status tg_pattern_create(int32_t dim, int32_t order, int32_t ncomp, int64_t n_vertices, int64_t n_elements,
+                            const int32_t *conn, const int32_t *dirichlet_vertices, int64_t n_dirichlet,
+                            uint32_t flags, tg_pattern **out);
+
+/* Fill *info (host struct). */
+tg_status tg_pattern_query(const tg_pattern *p, tg_pattern_info *info);
+
+/* Copy the scalar CSR structure to host arrays: h_row_ptr [n_dofs+1], h_col_idx [nnz]
+ * (either may be NULL).  Columns are sorted; both triangles are stored; entries
+ * whose value cancels to zero are kept. */
+tg_status tg_pattern_copy_csr(const tg_pattern *p, int32_t *h_row_ptr, int32_t *h_col_idx);
+
+/* Copy the constrained DoF ids (ascending) to host h_dofs [n_constrained]. */
+tg_status tg_pattern_copy_constrained(const tg_pattern *p, int32_t *h_dofs);
+
+/* Copy the global node ids of every element to host h_nodes [n_elements][k]
+ * (P1: the vertices; P2: 4 vertices then the edge nodes of the local edges
+ * (0,1),(0,2),(0,3),(1,2),(1,3),(2,3)). */
+tg_status tg_pattern_copy_element_nodes(const tg_pattern *p, int32_t *h_nodes);
+
+/*
+ * Copy the routing of Sec. 2 Stage II to host arrays (sizes from
+ * tg_pattern_query: N = n_nodes, P = n_elements * nodes_per_element pairs,
+ * B = n_blocks, Z = nnz / ncomp^2 node-level entries).  Any pointer may be NULL.
+ *   h_inc_ptr [N+1], h_inc [P] : S_vec as segments: node i receives the pairs
+ *       h_inc[h_inc_ptr[i] .. h_inc_ptr[i+1]) in ascending element order, each
+ *       coded e * k + a (element e, local node a).
+ *   h_blk_row [B+1] : row block b of the fused kernel covers nodes
+ *       [h_blk_row[b], h_blk_row[b+1]).
+ *   h_node_rp [N+1] : node-level CSR row pointers (node columns are the scalar
+ *       CSR columns of component 0 divided by ncomp).
+ *   h_seg_ptr [Z+1], h_slot [P*k] : S_mat as segments: node-level entry z sums
+ *       the local-matrix slots h_slot[h_seg_ptr[z] .. h_seg_ptr[z+1]) in
+ *       ascending element order; a slot is (pair - first pair of the entry's
+ *       row block) * k + b, i.e. local block (a, b) of the pair's element.
+ *       For ncomp = 3 each slot is a 3x3 block.
+ */
+tg_status tg_pattern_copy_routing(const tg_pattern *p, int32_t *h_inc_ptr, int32_t *h_inc, int32_t *h_blk_row,
+                                  int32_t *h_node_rp, int32_t *h_seg_ptr, uint16_t *h_slot);
+
+/* Free the pattern and its device memory.  Work using it must have completed. */
+void tg_pattern_destroy(tg_pattern *p);
+
+/*
+ * Assemble the CSR values and the right-hand side of `form` on the pattern's
+ * mesh: Stage I and Stage II fused in one kernel launch (Sec. 2 Alg. 1 and
+ * Alg. 2).  Every entry is written (no accumulation into prior contents).
+ *
+ *   dtype    : value type of coef, load, values and rhs.  Geometry (J, det J,
+ *              J^{-1}) is always computed in FP64.
+ *   d_coords : device [n_vertices][dim] FP64 vertex coordinates.
+ *   d_coef   : LAPLACE: device [n_elements] coefficient a per element;
+ *              ELASTICITY: device [2][n_elements] (lambda row, then mu row);
+ *              MASS: ignored (may be NULL).
+ *   d_load   : LAPLACE: device [n_elements] source f per element;
+ *              ELASTICITY: device [n_elements][3] body force per element;
+ *              may be NULL (then d_rhs is not written).  MASS: ignored.
+ *   d_values : device [nnz] output values, CSR order of tg_pattern_copy_csr.
+ *   d_rhs    : device [n_dofs] output right-hand side, or NULL.
+ *   d_status : device int32 or NULL.  If given it must hold TG_STATUS_CLEAN
+ *              before the call; after the kernel it holds the smallest index
+ *              of an element with det J == 0 or a non-finite value (det J,
+ *              a coefficient or a load), or is unchanged.  It is the only
+ *              word the library updates atomically.
+ * Errors (host): TG_E_ARG (NULL required pointer, form/dtype not valid for the
+ * pattern), TG_E_STATE (host-only pattern), TG_E_HIP (launch failure).
+ */
+tg_status tg_assemble(const tg_pattern *p, tg_form form, tg_dtype dtype, const double *d_coords, const void *d_coef,
+                      const void *d_load, void *d_values, void *d_rhs, int32_t *d_status, void *stream);
+
+/*
+ * Impose Dirichlet conditions on an assembled system by symmetric
+ * elimination on the fixed pattern.  For a constrained DoF b with value g_b:
+ * row b becomes e_b^T with rhs_b = g_b; for every other row i,
+ * rhs_i -= K_ib g_b and K_ib = 0.  With x_0 = 0 the solution of the result
+ * equals the condensed system of Sec. B.1.2 on the free DoFs and g on the
+ * constrained ones.
+ *   d_values, d_rhs : device, as written by tg_assemble (modified in place).
+ *   d_g             : device [n_dofs] of dtype (only constrained entries are
+ *                     read), or NULL for g = 0.
+ */
+tg_status tg_apply_dirichlet(const tg_pattern *p, tg_dtype dtype, void *d_values, void *d_rhs, const void *d_g,
+                             void *stream);
+
+/*
+ * y = K x on the pattern's CSR (device arrays of dtype; rows accumulated in FP64).
+ */
+tg_status tg_spmv(const tg_pattern *p, tg_dtype dtype, const void *d_values, const void *d_x, void *d_y,
+                  void *stream);
+
+/*
+ * Solve K x = b with Jacobi-preconditioned conjugate gradients, x_0 = 0, and
+ * stop when ||r_k||_2 / ||b||_2 <= rtol for the recursive residual r_k (the
+ * criterion of Sec. B.1.2; CG replaces the paper's BiCGSTAB because every
+ * configured system is symmetric positive definite).  Dot products and norms
+ * are accumulated in FP64 in a fixed order (bitwise reproducible).
+ *   d_values, d_rhs : device arrays of dtype (e.g. after tg_apply_dirichlet).
+ *   d_x             : device [n_dofs] of dtype, output.
+ *   check_every     : iterations between host checks of the stop test (>= 1);
+ *                     the iteration count reported is exact regardless.
+ *   iters, relres   : host outputs: iterations done, and the final TRUE
+ *                     relative residual ||b - K x|| / ||b|| (eq. linres).
+ * Blocks until done (host syncs on `stream`).  Uses the pattern's own
+ * workspace: calls on one pattern must not overlap.  Returns TG_E_NOCONV
+ * (with the last iterate in d_x) if max_iter is reached.
+ */
+tg_status tg_pcg(const tg_pattern *p, tg_dtype dtype, const void *d_values, const void *d_rhs, void *d_x, double rtol,
+                 int32_t max_iter, int32_t check_every, int32_t *iters, double *relres, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TG_H */

@@ -218,6 +218,21 @@ def assemble_p1(coords, conn, a=None, f=None, form: str = "laplace") -> Assemble
     return Assembled(row_ptr, col_idx, vals, rhs)
 
 
+def assemble_p1_values(coords, conn, a, f, row_ptr, col_idx):
+    """Value and load assembly only (Laplace), on a CSR pattern built beforehand by csr_pattern."""
+    coords = _f64(coords)
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    nv, dim = coords.shape
+    vals = np.zeros(col_idx.shape[0])
+    rhs = np.zeros(nv)
+    bad = ctypes.c_int64(-1)
+    rc = _load().oracle_assemble_p1(dim, 0, nv, _ptr(coords, _dp), conn.shape[0], _ptr(conn, _i32p),
+                                    _ptr(_f64(a), _dp), _ptr(_f64(f), _dp), _ptr(row_ptr, _i64p),
+                                    _ptr(col_idx, _i64p), _ptr(vals, _dp), _ptr(rhs, _dp), ctypes.byref(bad))
+    _check(rc, "assemble_p1_values", bad.value)
+    return vals, rhs
+
+
 def assemble_p2_elasticity(coords, conn, lam, mu, b=None) -> Assembled:
     """Scatter-add assembly of P2 linear elasticity (3 DoFs per node, DoF = 3*node + c)."""
     coords = _f64(coords)

@@ -1,0 +1,121 @@
+// Internal declarations of libtg (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "tg.h"
+
+namespace tg {
+
+// Row-block capacities of the fused Map+Reduce kernels, in (node, element)
+// pairs.  A block is a run of consecutive node rows whose pairs all fit in
+// LDS; the greedy partition fills a block up to the target and a single row
+// may use up to the capacity.
+constexpr int kP1Threads = 256;
+constexpr int kP1BlockTarget = 256;
+constexpr int kP1BlockCap = 512;
+constexpr int kP2Threads = 256;
+constexpr int kP2BlockTarget = 64;
+constexpr int kP2BlockCap = 64;
+
+// Host-side topology of one mesh: numbering, node-level CSR and the routing
+// of element slots to CSR entries.
+struct HostPattern {
+    int dim = 0, order = 0, ncomp = 0, k = 0;  // k = nodes per element
+    int64_t nv = 0, E = 0, n_nodes = 0, n_dofs = 0;
+    int64_t nnz_nodes = 0;  // node-level entries (node pairs sharing an element)
+    int64_t nnz = 0;        // scalar entries = ncomp^2 * nnz_nodes
+
+    std::vector<int32_t> conn;        // [E][dim+1] vertex ids (as given)
+    std::vector<int32_t> elem_nodes;  // [E][k] global node ids
+    std::vector<int32_t> node_rp;     // [n_nodes+1] node-level CSR rows
+    std::vector<int32_t> node_ci;     // [nnz_nodes] node-level CSR columns (sorted)
+    // S_vec routing: pairs (node i, element e, local node a) grouped by node,
+    // ascending e inside a node.  pair code = e * k + a.
+    std::vector<int32_t> inc_ptr;  // [n_nodes+1]
+    std::vector<int32_t> inc;      // [n_pairs]
+    // Row blocks for the fused kernels.
+    std::vector<int32_t> blk_row;  // [n_blocks+1]
+    // S_mat routing: node-level entry p sums slots slot[seg_ptr[p] .. seg_ptr[p+1]),
+    // ascending element order; slot = (pair - first pair of the block) * k + b.
+    std::vector<int32_t> seg_ptr;  // [nnz_nodes+1]
+    std::vector<uint16_t> slot;    // [n_pairs * k]
+    // Scalar CSR (DoF = ncomp * node + c).
+    std::vector<int32_t> row_ptr;   // [n_dofs+1]
+    std::vector<int32_t> col_idx;   // [nnz]
+    std::vector<int32_t> diag_pos;  // [n_dofs]
+    // Dirichlet.
+    std::vector<uint8_t> constrained;  // [n_dofs] 0/1
+    std::vector<int32_t> constrained_list;
+
+    int64_t n_pairs() const { return (int64_t)inc.size(); }
+    int64_t n_blocks() const { return (int64_t)blk_row.size() - 1; }
+};
+
+// Builds everything above; returns TG_OK or an error with *msg set.
+tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t E, const int32_t *conn,
+                             const int32_t *dirichlet, int64_t n_dirichlet, HostPattern &hp, std::string &msg);
+
+// PCG device state (one per pattern).
+struct PcgState {
+    double rz[2];  // r.z of the current iterate, double-buffered by iteration parity
+    double bb;     // b.b
+    double rr;     // r.r of the latest iterate
+    double tol2;   // rtol^2 * b.b
+    int32_t done;  // 1 once the stop test held
+    int32_t iters; // iteration at which it held
+};
+
+constexpr int kVecThreads = 256;
+constexpr int kMaxPartials = 1024;  // blocks of the reduction kernels
+
+struct DevicePattern {
+    int32_t *conn = nullptr;      // [E][dim+1]
+    int32_t *inc_ptr = nullptr;   // [n_nodes+1]
+    int32_t *inc = nullptr;       // [n_pairs]
+    int32_t *blk_row = nullptr;   // [n_blocks+1]
+    int32_t *node_rp = nullptr;   // [n_nodes+1]
+    int32_t *seg_ptr = nullptr;   // [nnz_nodes+1]
+    uint16_t *slot = nullptr;     // [n_pairs*k]
+    int32_t *row_ptr = nullptr;   // [n_dofs+1]
+    int32_t *col_idx = nullptr;   // [nnz]
+    int32_t *diag_pos = nullptr;  // [n_dofs]
+    uint8_t *constrained = nullptr;  // [n_dofs]
+    // PCG workspace: 5 vectors of n_dofs doubles (used as T), partials, state.
+    double *work = nullptr;
+    double *partials = nullptr;  // [3 * kMaxPartials]
+    PcgState *state = nullptr;
+    PcgState *host_state = nullptr;  // pinned mirror
+    size_t bytes = 0;
+    int spmv_group = 4;  // lanes per CSR row in the SpMV
+};
+
+}  // namespace tg
+
+struct tg_pattern {
+    tg::HostPattern host;
+    tg::DevicePattern dev;
+    bool host_only = false;
+    int device = -1;
+};
+
+// Kernel launchers (tg_assemble.hip, tg_solve.hip).  They return hipError_t.
+namespace tg {
+hipError_t launch_assemble_p1(const tg_pattern &p, tg_form form, tg_dtype dtype, const double *coords,
+                              const void *coef, const void *load, void *values, void *rhs, int32_t *status,
+                              hipStream_t s);
+hipError_t launch_assemble_p2(const tg_pattern &p, tg_dtype dtype, const double *coords, const void *coef,
+                              const void *load, void *values, void *rhs, int32_t *status, hipStream_t s);
+hipError_t launch_dirichlet(const tg_pattern &p, tg_dtype dtype, void *values, void *rhs, const void *g,
+                            hipStream_t s);
+hipError_t launch_spmv(const tg_pattern &p, tg_dtype dtype, const void *values, const void *x, void *y,
+                       hipStream_t s);
+// Runs the whole PCG; returns TG_OK / TG_E_NOCONV / TG_E_HIP with *msg on failure.
+tg_status run_pcg(const tg_pattern &p, tg_dtype dtype, const void *values, const void *rhs, void *x, double rtol,
+                  int32_t max_iter, int32_t check_every, int32_t *iters, double *relres, hipStream_t s,
+                  std::string &msg);
+}  // namespace tg

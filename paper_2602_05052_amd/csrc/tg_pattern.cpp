@@ -1,0 +1,304 @@
+// Host construction of the CSR pattern and the routing tables of one mesh
+// topology (TensorGalerkin Sec. 2, Stage II: routing matrices precomputed from
+// the topology alone).
+//
+// The paper stores the routing as 0/1 matrices S_vec (N x E k) and
+// S_mat (N_nnz x E k^2).  Every column of either has exactly one 1, so the
+// products S_vec vec(F_local) and S_mat vec(K_local) are segmented sums.  This
+// builder stores them in that form:
+//   S_vec: for each node i, its (element, local node) pairs in ascending
+//          element order  (inc_ptr / inc);
+//   S_mat: for each node-level CSR entry (i, j), the element slots (pair of row
+//          i, local column b) that land on it, in ascending element order
+//          (seg_ptr / slot).  Slot ids are relative to the row block of the
+//          fused kernel, i.e. they index the block's local matrices in LDS.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "tg_internal.h"
+
+namespace tg {
+namespace {
+
+constexpr int kP2Edge[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+
+struct FaceKey {
+    int32_t v[3];
+    bool operator<(const FaceKey &o) const {
+        return std::lexicographical_compare(v, v + 3, o.v, o.v + 3);
+    }
+    bool operator==(const FaceKey &o) const { return v[0] == o.v[0] && v[1] == o.v[1] && v[2] == o.v[2]; }
+};
+
+// Faces (dim vertices, sorted) that belong to exactly one element.
+std::vector<FaceKey> boundary_faces(int dim, int64_t E, const int32_t *conn) {
+    const int nvtx = dim + 1;
+    std::vector<FaceKey> faces;
+    faces.reserve((size_t)E * nvtx);
+    for (int64_t e = 0; e < E; ++e)
+        for (int skip = 0; skip < nvtx; ++skip) {
+            FaceKey f{{-1, -1, -1}};
+            int m = 0;
+            for (int a = 0; a < nvtx; ++a)
+                if (a != skip) f.v[m++] = conn[e * nvtx + a];
+            std::sort(f.v, f.v + dim);
+            faces.push_back(f);
+        }
+    std::sort(faces.begin(), faces.end());
+    std::vector<FaceKey> out;
+    for (size_t t = 0; t < faces.size();) {
+        size_t u = t + 1;
+        while (u < faces.size() && faces[u] == faces[t]) ++u;
+        if (u - t == 1) out.push_back(faces[t]);
+        t = u;
+    }
+    return out;
+}
+
+}  // namespace
+
+tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t E, const int32_t *conn,
+                             const int32_t *dirichlet, int64_t n_dirichlet, HostPattern &hp, std::string &msg) {
+    const bool p1 = (order == 1 && ncomp == 1 && (dim == 2 || dim == 3));
+    const bool p2 = (order == 2 && ncomp == 3 && dim == 3);
+    if (!p1 && !p2) {
+        msg = "unsupported (dim, order, ncomp); supported: (2|3, 1, 1) and (3, 2, 3)";
+        return TG_E_ARG;
+    }
+    if (nv <= 0 || E <= 0 || !conn) {
+        msg = "n_vertices and n_elements must be positive and conn non-NULL";
+        return TG_E_ARG;
+    }
+    const int nvtx = dim + 1;
+    const int k = p1 ? nvtx : 10;
+    if (nv >= INT32_MAX || E * (int64_t)k >= INT32_MAX) {
+        msg = "mesh too large for int32 indexing";
+        return TG_E_ARG;
+    }
+    hp.dim = dim;
+    hp.order = order;
+    hp.ncomp = ncomp;
+    hp.k = k;
+    hp.nv = nv;
+    hp.E = E;
+    hp.conn.assign(conn, conn + E * nvtx);
+
+    // ---- validate connectivity
+    std::vector<uint8_t> used(nv, 0);
+    for (int64_t e = 0; e < E; ++e) {
+        const int32_t *g = conn + e * nvtx;
+        for (int a = 0; a < nvtx; ++a) {
+            if (g[a] < 0 || g[a] >= nv) {
+                msg = "element " + std::to_string(e) + " has vertex id out of range";
+                return TG_E_ARG;
+            }
+            for (int b = 0; b < a; ++b)
+                if (g[a] == g[b]) {
+                    msg = "element " + std::to_string(e) + " repeats a vertex";
+                    return TG_E_ARG;
+                }
+            used[g[a]] = 1;
+        }
+    }
+    for (int64_t v = 0; v < nv; ++v)
+        if (!used[v]) {
+            msg = "vertex " + std::to_string(v) + " is used by no element";
+            return TG_E_ARG;
+        }
+
+    // ---- nodes: P1 = vertices; P2 = vertices, then edges by (min, max)
+    std::vector<uint64_t> edges;
+    hp.elem_nodes.resize((size_t)E * k);
+    if (p1) {
+        hp.n_nodes = nv;
+        std::memcpy(hp.elem_nodes.data(), conn, sizeof(int32_t) * E * k);
+    } else {
+        edges.reserve((size_t)E * 6);
+        for (int64_t e = 0; e < E; ++e)
+            for (int m = 0; m < 6; ++m) {
+                uint64_t p = (uint32_t)conn[e * 4 + kP2Edge[m][0]], q = (uint32_t)conn[e * 4 + kP2Edge[m][1]];
+                edges.push_back(std::min(p, q) << 32 | std::max(p, q));
+            }
+        std::sort(edges.begin(), edges.end());
+        edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
+        hp.n_nodes = nv + (int64_t)edges.size();
+        if (hp.n_nodes * 3 >= INT32_MAX) {
+            msg = "mesh too large for int32 indexing";
+            return TG_E_ARG;
+        }
+        for (int64_t e = 0; e < E; ++e) {
+            for (int a = 0; a < 4; ++a) hp.elem_nodes[e * 10 + a] = conn[e * 4 + a];
+            for (int m = 0; m < 6; ++m) {
+                uint64_t p = (uint32_t)conn[e * 4 + kP2Edge[m][0]], q = (uint32_t)conn[e * 4 + kP2Edge[m][1]];
+                uint64_t key = std::min(p, q) << 32 | std::max(p, q);
+                int64_t r = std::lower_bound(edges.begin(), edges.end(), key) - edges.begin();
+                hp.elem_nodes[e * 10 + 4 + m] = (int32_t)(nv + r);
+            }
+        }
+    }
+    const int64_t N = hp.n_nodes;
+    hp.n_dofs = N * ncomp;
+
+    // ---- S_vec routing: pairs grouped by node, ascending element inside a node
+    hp.inc_ptr.assign(N + 1, 0);
+    for (int64_t t = 0; t < E * k; ++t) hp.inc_ptr[hp.elem_nodes[t] + 1]++;
+    const int cap = p1 ? kP1BlockCap : kP2BlockCap;
+    for (int64_t i = 0; i < N; ++i) {
+        if (hp.inc_ptr[i + 1] > cap) {
+            msg = "node " + std::to_string(i) + " belongs to " + std::to_string(hp.inc_ptr[i + 1]) +
+                  " elements, more than the kernel block capacity " + std::to_string(cap);
+            return TG_E_ARG;
+        }
+        hp.inc_ptr[i + 1] += hp.inc_ptr[i];
+    }
+    hp.inc.resize((size_t)E * k);
+    {
+        std::vector<int32_t> fill(hp.inc_ptr.begin(), hp.inc_ptr.end() - 1);
+        for (int64_t e = 0; e < E; ++e)
+            for (int a = 0; a < k; ++a) hp.inc[fill[hp.elem_nodes[e * k + a]]++] = (int32_t)(e * k + a);
+    }
+
+    // ---- row blocks: consecutive rows while the pairs fit the target
+    const int target = p1 ? kP1BlockTarget : kP2BlockTarget;
+    hp.blk_row.clear();
+    hp.blk_row.push_back(0);
+    for (int64_t i = 0; i < N;) {
+        const int32_t first = hp.inc_ptr[i];
+        int64_t j = i + 1;
+        while (j < N && hp.inc_ptr[j + 1] - first <= target) ++j;
+        hp.blk_row.push_back((int32_t)j);
+        i = j;
+    }
+
+    // ---- node-level CSR and S_mat routing, row by row
+    hp.node_rp.assign(N + 1, 0);
+    hp.node_ci.clear();
+    hp.node_ci.reserve((size_t)E * k * 2);
+    hp.seg_ptr.clear();
+    hp.seg_ptr.reserve((size_t)E * k * 2);
+    hp.slot.resize((size_t)E * k * k);
+    std::vector<int32_t> mark(N, -1), pos(N, 0), cols, cnt;
+    int64_t slot_fill = 0;
+    int64_t blk = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        while (hp.blk_row[blk + 1] <= i) ++blk;
+        const int32_t blk_first_pair = hp.inc_ptr[hp.blk_row[blk]];
+        cols.clear();
+        for (int32_t t = hp.inc_ptr[i]; t < hp.inc_ptr[i + 1]; ++t) {
+            const int64_t e = hp.inc[t] / k;
+            for (int b = 0; b < k; ++b) {
+                int32_t j = hp.elem_nodes[e * k + b];
+                if (mark[j] != (int32_t)i) {
+                    mark[j] = (int32_t)i;
+                    cols.push_back(j);
+                }
+            }
+        }
+        std::sort(cols.begin(), cols.end());
+        for (size_t c = 0; c < cols.size(); ++c) pos[cols[c]] = (int32_t)c;
+        // counts per entry, then slots in (pair ascending, b) order -> ascending element per entry
+        cnt.assign(cols.size() + 1, 0);
+        for (int32_t t = hp.inc_ptr[i]; t < hp.inc_ptr[i + 1]; ++t) {
+            const int64_t e = hp.inc[t] / k;
+            for (int b = 0; b < k; ++b) cnt[pos[hp.elem_nodes[e * k + b]] + 1]++;
+        }
+        for (size_t c = 0; c < cols.size(); ++c) cnt[c + 1] += cnt[c];
+        for (size_t c = 0; c < cols.size(); ++c) hp.seg_ptr.push_back((int32_t)(slot_fill + cnt[c]));
+        for (int32_t t = hp.inc_ptr[i]; t < hp.inc_ptr[i + 1]; ++t) {
+            const int64_t e = hp.inc[t] / k;
+            for (int b = 0; b < k; ++b) {
+                const int c = pos[hp.elem_nodes[e * k + b]];
+                hp.slot[slot_fill + cnt[c]++] = (uint16_t)((t - blk_first_pair) * k + b);
+            }
+        }
+        slot_fill += (int64_t)(hp.inc_ptr[i + 1] - hp.inc_ptr[i]) * k;
+        hp.node_ci.insert(hp.node_ci.end(), cols.begin(), cols.end());
+        hp.node_rp[i + 1] = (int32_t)hp.node_ci.size();
+        if ((int64_t)hp.node_ci.size() * ncomp * ncomp >= INT32_MAX) {
+            msg = "too many nonzeros for int32 indexing";
+            return TG_E_ARG;
+        }
+    }
+    hp.seg_ptr.push_back((int32_t)slot_fill);
+    hp.nnz_nodes = (int64_t)hp.node_ci.size();
+    hp.nnz = hp.nnz_nodes * ncomp * ncomp;
+
+    // ---- scalar CSR (DoF = ncomp * node + c; the 3 rows of a node share its node columns)
+    if (ncomp == 1) {
+        hp.row_ptr = hp.node_rp;
+        hp.col_idx = hp.node_ci;
+    } else {
+        hp.row_ptr.assign(hp.n_dofs + 1, 0);
+        hp.col_idx.resize(hp.nnz);
+        for (int64_t i = 0; i < N; ++i) {
+            const int32_t m = hp.node_rp[i + 1] - hp.node_rp[i];
+            for (int c = 0; c < ncomp; ++c) {
+                const int64_t r = i * ncomp + c;
+                const int64_t base = (int64_t)ncomp * ncomp * hp.node_rp[i] + (int64_t)c * ncomp * m;
+                hp.row_ptr[r] = (int32_t)base;
+                for (int32_t q = 0; q < m; ++q)
+                    for (int cc = 0; cc < ncomp; ++cc)
+                        hp.col_idx[base + q * ncomp + cc] = hp.node_ci[hp.node_rp[i] + q] * ncomp + cc;
+            }
+        }
+        hp.row_ptr[hp.n_dofs] = (int32_t)hp.nnz;
+    }
+    hp.diag_pos.resize(hp.n_dofs);
+    for (int64_t r = 0; r < hp.n_dofs; ++r) {
+        auto b = hp.col_idx.begin() + hp.row_ptr[r], e = hp.col_idx.begin() + hp.row_ptr[r + 1];
+        hp.diag_pos[r] = (int32_t)(std::lower_bound(b, e, (int32_t)r) - hp.col_idx.begin());
+    }
+
+    // ---- Dirichlet DoFs
+    std::vector<uint8_t> cvert(nv, 0);
+    std::vector<FaceKey> bfaces;
+    if (n_dirichlet == TG_BOUNDARY_ALL || p2) bfaces = boundary_faces(dim, E, conn);
+    if (n_dirichlet == TG_BOUNDARY_ALL) {
+        if (dirichlet) {
+            msg = "dirichlet_vertices must be NULL with TG_BOUNDARY_ALL";
+            return TG_E_ARG;
+        }
+        for (const FaceKey &f : bfaces)
+            for (int a = 0; a < dim; ++a) cvert[f.v[a]] = 1;
+    } else if (n_dirichlet > 0) {
+        if (!dirichlet) {
+            msg = "dirichlet_vertices is NULL";
+            return TG_E_ARG;
+        }
+        for (int64_t t = 0; t < n_dirichlet; ++t) {
+            if (dirichlet[t] < 0 || dirichlet[t] >= nv) {
+                msg = "Dirichlet vertex id out of range";
+                return TG_E_ARG;
+            }
+            cvert[dirichlet[t]] = 1;
+        }
+    } else if (n_dirichlet < 0) {
+        msg = "n_dirichlet must be >= 0 or TG_BOUNDARY_ALL";
+        return TG_E_ARG;
+    }
+    std::vector<uint8_t> cnode(N, 0);
+    for (int64_t v = 0; v < nv; ++v) cnode[v] = cvert[v];
+    if (p2) {
+        for (const FaceKey &f : bfaces) {
+            if (!(cvert[f.v[0]] && cvert[f.v[1]] && cvert[f.v[2]])) continue;
+            for (int m = 0; m < 3; ++m) {
+                uint64_t p = (uint32_t)f.v[m], q = (uint32_t)f.v[(m + 1) % 3];
+                uint64_t key = std::min(p, q) << 32 | std::max(p, q);
+                int64_t r = std::lower_bound(edges.begin(), edges.end(), key) - edges.begin();
+                cnode[nv + r] = 1;
+            }
+        }
+    }
+    hp.constrained.assign(hp.n_dofs, 0);
+    hp.constrained_list.clear();
+    for (int64_t i = 0; i < N; ++i)
+        if (cnode[i])
+            for (int c = 0; c < ncomp; ++c) {
+                hp.constrained[i * ncomp + c] = 1;
+                hp.constrained_list.push_back((int32_t)(i * ncomp + c));
+            }
+    return TG_OK;
+}
+
+}  // namespace tg

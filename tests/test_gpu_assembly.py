@@ -1,0 +1,229 @@
+"""GPU parity of the fused Map+Reduce kernels against the FP64 oracle (through the C ABI).
+
+Bar (normwise, max absolute row sum): ||K - K*||_inf / ||K*||_inf and
+||F - F*||_inf / ||F*||_inf <= 1e-12 in FP64 and <= 1e-5 in FP32; the CSR
+pattern must be identical.  Sizes span one element up to the full 64^3 tet mesh
+(several row blocks and a ragged last block in every case).
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import meshgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+tg = pytest.importorskip("paper_2602_05052_amd")
+
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
+
+
+def _norm_rel(K, Kref):
+    num = np.abs(K - Kref) @ np.ones(K.shape[1]) if sp.issparse(K) else np.abs(K - Kref).sum(axis=1)
+    den = np.abs(Kref) @ np.ones(Kref.shape[1]) if sp.issparse(Kref) else np.abs(Kref).sum(axis=1)
+    return float(np.max(num) / np.max(den))
+
+
+def _vec_rel(v, vref):
+    return float(np.max(np.abs(v - vref)) / max(np.max(np.abs(vref)), 1e-300))
+
+
+def _gpu_poisson(d, dtype, form=tg.LAPLACE, pat=None):
+    pat = pat or tg.Pattern(d["conn"], len(d["coords"]))
+    coords = torch.from_numpy(d["coords"]).cuda()
+    if form == tg.MASS:
+        vals, rhs = tg.assemble(pat, tg.MASS, coords, dtype=dtype)
+    else:
+        a = torch.from_numpy(d["a"]).to(dtype).cuda()
+        f = torch.from_numpy(d["f"]).to(dtype).cuda()
+        vals, rhs = tg.assemble(pat, tg.LAPLACE, coords, a, f)
+    torch.cuda.synchronize()
+    return pat, vals.double().cpu().numpy(), (rhs.double().cpu().numpy() if rhs is not None else None)
+
+
+def _check_p1(d, dtype, form=tg.LAPLACE):
+    print(f"p1 parity E={len(d['conn'])} dim={d['coords'].shape[1]} dtype={dtype} form={form}", flush=True)
+    pat, vals, rhs = _gpu_poisson(d, dtype, form)
+    if form == tg.MASS:
+        A = oracle.assemble_p1(d["coords"], d["conn"], form="mass")
+    else:
+        A = oracle.assemble_p1(d["coords"], d["conn"], d["a"], d["f"])
+    rp, ci = pat.csr()
+    np.testing.assert_array_equal(rp, A.row_ptr)
+    np.testing.assert_array_equal(ci, A.col_idx)
+    K = sp.csr_matrix((vals, ci, rp), shape=(A.n, A.n))
+    err = _norm_rel(K, A.scipy())
+    assert err <= TOL[dtype], err
+    if form != tg.MASS:
+        ferr = _vec_rel(rhs, A.rhs)
+        assert ferr <= TOL[dtype], ferr
+    return err
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dim,n", [(2, 1), (2, 7), (2, 64), (3, 1), (3, 5), (3, 17)])
+def test_p1_laplace_parity(dim, n, dtype):
+    _check_p1(meshgen.poisson_inputs(dim, n, seed=0), dtype)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_p1_full_64cube_parity(dtype):
+    """The 64^3 Kuhn mesh (1,572,864 tets) the benchmark times, checked entry by entry."""
+    _check_p1(meshgen.poisson_inputs(3, 64, seed=0), dtype)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dim,n", [(2, 9), (3, 6)])
+def test_p1_mass_parity(dim, n, dtype):
+    _check_p1(meshgen.poisson_inputs(dim, n, seed=3), dtype, form=tg.MASS)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_single_element(dim):
+    rng = np.random.default_rng(dim)
+    X = rng.random((dim + 1, dim))
+    d = {"coords": X, "conn": np.arange(dim + 1, dtype=np.int32)[None, :], "a": np.array([2.5]), "f": np.array([-0.7])}
+    _check_p1(d, torch.float64)
+
+
+def test_shuffled_numbering_parity():
+    d = meshgen.poisson_inputs(3, 9, seed=8)
+    c2, t2, _, _, a2, f2 = meshgen.shuffle_numbering(d["coords"], d["conn"], 4, d["a"], d["f"])
+    _check_p1({"coords": c2, "conn": t2, "a": a2, "f": f2}, torch.float64)
+
+
+def test_bitwise_deterministic_across_repeats_and_streams():
+    d = meshgen.poisson_inputs(3, 20, seed=1)
+    pat = tg.Pattern(d["conn"], len(d["coords"]))
+    coords = torch.from_numpy(d["coords"]).cuda()
+    a = torch.from_numpy(d["a"]).cuda()
+    f = torch.from_numpy(d["f"]).cuda()
+    v0, r0 = tg.assemble(pat, tg.LAPLACE, coords, a, f)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    for i in range(10):
+        with torch.cuda.stream(s if i % 2 else torch.cuda.current_stream()):
+            noise = torch.randn(1 << 20, device="cuda").sum()  # concurrent unrelated work
+            v, r = tg.assemble(pat, tg.LAPLACE, coords, a, f, stream=s if i % 2 else None)
+        torch.cuda.synchronize()
+        assert torch.equal(v, v0) and torch.equal(r, r0)
+    del noise
+
+
+def test_status_degenerate_and_nonfinite():
+    d = meshgen.poisson_inputs(2, 6, seed=0)
+    coords = d["coords"].copy()
+    # collapse element 17: move its third vertex onto its first
+    g = d["conn"][17]
+    coords[g[2]] = coords[g[0]]
+    pat = tg.Pattern(d["conn"], len(coords))
+    st = tg.new_status()
+    tg.assemble(pat, tg.LAPLACE, torch.from_numpy(coords).cuda(), torch.from_numpy(d["a"]).cuda(),
+                torch.from_numpy(d["f"]).cuda(), status=st)
+    bad = tg.check_status(st)
+    touching = np.flatnonzero(np.any(d["conn"] == g[2], axis=1))
+    degenerate = [e for e in touching if abs(np.linalg.det((coords[d["conn"][e]][1:] - coords[d["conn"][e]][0]))) == 0]
+    assert bad == min(degenerate)
+    a = d["a"].copy()
+    a[40] = np.nan
+    a[41] = np.inf
+    st = tg.new_status()
+    tg.assemble(pat, tg.LAPLACE, torch.from_numpy(d["coords"]).cuda(), torch.from_numpy(a).cuda(),
+                torch.from_numpy(d["f"]).cuda(), status=st)
+    assert tg.check_status(st) == 40
+    st = tg.new_status()
+    tg.assemble(pat, tg.LAPLACE, torch.from_numpy(d["coords"]).cuda(), torch.from_numpy(d["a"]).cuda(),
+                torch.from_numpy(d["f"]).cuda(), status=st)
+    assert tg.check_status(st) is None
+
+
+def test_argument_checks_on_device_pattern():
+    d = meshgen.poisson_inputs(2, 3, seed=0)
+    pat = tg.Pattern(d["conn"], len(d["coords"]))
+    coords = torch.from_numpy(d["coords"]).cuda()
+    with pytest.raises(tg.TGError, match="ELASTICITY needs"):
+        tg.assemble(pat, tg.ELASTICITY, coords, torch.ones(2, pat.n_elements, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        tg.assemble(pat, tg.LAPLACE, coords, torch.ones(3, device="cuda", dtype=torch.float64))
+
+
+# ---------------------------------------------------------------- P2 elasticity
+
+def _gpu_elasticity(d, dtype):
+    pat = tg.Pattern(d["conn"], len(d["coords"]), order=2, ncomp=3)
+    coords = torch.from_numpy(d["coords"]).cuda()
+    coef = torch.from_numpy(np.stack([d["lam"], d["mu"]])).to(dtype).cuda()
+    load = torch.from_numpy(d["b"]).to(dtype).cuda()
+    vals, rhs = tg.assemble(pat, tg.ELASTICITY, coords, coef, load)
+    torch.cuda.synchronize()
+    return pat, vals.double().cpu().numpy(), rhs.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("n", [1, 2, 5])
+def test_p2_elasticity_parity(n, dtype):
+    d = meshgen.elasticity_inputs(n, seed=0)
+    print(f"p2 parity n={n} dtype={dtype}", flush=True)
+    pat, vals, rhs = _gpu_elasticity(d, dtype)
+    A = oracle.assemble_p2_elasticity(d["coords"], d["conn"], d["lam"], d["mu"], d["b"])
+    rp, ci = pat.csr()
+    np.testing.assert_array_equal(rp, A.row_ptr)
+    np.testing.assert_array_equal(ci, A.col_idx)
+    K = sp.csr_matrix((vals, ci, rp), shape=(A.n, A.n))
+    err = _norm_rel(K, A.scipy())
+    assert err <= TOL[dtype], err
+    assert _vec_rel(rhs, A.rhs) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_p2_full_32cube_sampled_rows(dtype):
+    """The 32^3 P2 mesh (196,608 tets, 69M nonzeros): 300 sampled DoF rows rebuilt by the oracle element by element."""
+    d = meshgen.elasticity_inputs(32, seed=0)
+    print(f"p2 full sampled dtype={dtype}", flush=True)
+    pat, vals, rhs = _gpu_elasticity(d, dtype)
+    rp, ci = pat.csr()
+    nodes10 = pat.element_nodes()
+    ref_nodes, _ = oracle.p2_numbering(len(d["coords"]), d["conn"])
+    np.testing.assert_array_equal(nodes10, ref_nodes)
+    rng = np.random.default_rng(0)
+    rows = np.unique(np.concatenate([rng.choice(pat.n_dofs, 298, replace=False), [0, pat.n_dofs - 1]]))
+    node_rows = set((rows // 3).tolist())
+    inc = {}
+    for e in range(len(d["conn"])):
+        for a, nd in enumerate(nodes10[e]):
+            if nd in node_rows:
+                inc.setdefault(int(nd), []).append((e, a))
+    worst = 0.0
+    for r in rows:
+        node, c = divmod(int(r), 3)
+        row = {}
+        F = 0.0
+        for e, a in inc[node]:
+            Ke, Fe = oracle.p2_elasticity_element(d["coords"][d["conn"][e]], d["lam"][e], d["mu"][e], d["b"][e])
+            for bn in range(10):
+                for cc in range(3):
+                    col = 3 * int(nodes10[e][bn]) + cc
+                    row[col] = row.get(col, 0.0) + Ke[3 * a + c, 3 * bn + cc]
+            F += Fe[3 * a + c]
+        cols = np.array(sorted(row))
+        np.testing.assert_array_equal(ci[rp[r]:rp[r + 1]], cols)
+        ref = np.array([row[j] for j in cols])
+        got = vals[rp[r]:rp[r + 1]]
+        worst = max(worst, np.abs(got - ref).sum() / np.abs(ref).sum())
+        assert abs(rhs[r] - F) <= TOL[dtype] * max(abs(F), 1e-3)
+    assert worst <= TOL[dtype], worst
+
+
+def test_p2_symmetry_and_rigid_modes_on_gpu():
+    d = meshgen.elasticity_inputs(4, seed=1)
+    pat, vals, _ = _gpu_elasticity(d, torch.float64)
+    rp, ci = pat.csr()
+    K = sp.csr_matrix((vals, ci, rp), shape=(pat.n_dofs, pat.n_dofs))
+    assert abs(K - K.T).max() <= 1e-14 * abs(K).max()
+    nodes10 = pat.element_nodes()
+    xyz = oracle.p2_node_coords(d["coords"], d["conn"], nodes10, pat.n_nodes)
+    import indep
+    R = indep.rigid_modes(xyz)
+    assert np.abs(K @ R.T).max() < 1e-11 * abs(K).max()

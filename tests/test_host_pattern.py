@@ -1,0 +1,185 @@
+"""Host logic of libtg, no GPU: exports, CSR pattern, routing, Dirichlet sets, argument errors.
+
+The routing check replays Stage II (Sec. 2 Alg. 2) on the CPU: the oracle's own
+element matrices are pushed through the library's S_mat / S_vec segments in
+their stored order, and the result must equal the oracle's scatter-add
+assembly bit for bit (both sum every entry in ascending element order).
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import meshgen
+import oracle
+
+tg = pytest.importorskip("paper_2602_05052_amd")
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "tg.h")
+
+
+def test_library_exports_every_declared_symbol():
+    decl = set(re.findall(r"^(?:const char \*|tg_status |void )(tg_[a-z_]+)\(", open(HEADER).read(), re.M))
+    assert decl, "no declarations found"
+    lib = ctypes.CDLL(tg.library_path())
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert decl == set(tg.EXPORTED)
+
+
+def _sequential_segment_sum(contrib, seg_ptr):
+    """out[z] = contrib[seg[z]] + contrib[seg[z]+1] + ... summed left to right, starting from 0."""
+    lens = np.diff(seg_ptr)
+    out = np.zeros(len(lens))
+    for t in range(int(lens.max()) if len(lens) else 0):
+        m = lens > t
+        out[m] = out[m] + contrib[seg_ptr[:-1][m] + t]
+    return out
+
+
+def _pair_of_slot(r, k):
+    """Global pair index and local column b of every slot, in stored order."""
+    nodes = len(r["inc_ptr"]) - 1
+    blk_first_pair = r["inc_ptr"][r["blk_row"][:-1]]
+    row_blk = np.searchsorted(r["blk_row"], np.arange(nodes), side="right") - 1
+    node_of_entry = np.repeat(np.arange(nodes), np.diff(r["node_rp"]))
+    seg_len = np.diff(r["seg_ptr"])
+    slot_entry = np.repeat(np.arange(len(seg_len)), seg_len)
+    slot = r["slot"].astype(np.int64)
+    pair = blk_first_pair[row_blk[node_of_entry[slot_entry]]] + slot // k
+    return pair, slot % k
+
+
+@pytest.mark.parametrize("dim,n", [(2, 1), (2, 7), (3, 1), (3, 4)])
+def test_p1_pattern_routing_equals_oracle(dim, n):
+    d = meshgen.poisson_inputs(dim, n, seed=1)
+    pat = tg.Pattern(d["conn"], len(d["coords"]), host_only=True)
+    A = oracle.assemble_p1(d["coords"], d["conn"], d["a"], d["f"])
+    rp, ci = pat.csr()
+    np.testing.assert_array_equal(rp, A.row_ptr)
+    np.testing.assert_array_equal(ci, A.col_idx)
+    k = dim + 1
+    r = pat.routing()
+    assert r["slot"].max() < tg_block_cap(1) * k
+    pairs_per_block = r["inc_ptr"][r["blk_row"][1:]] - r["inc_ptr"][r["blk_row"][:-1]]
+    assert pairs_per_block.max() <= tg_block_cap(1)
+    assert r["blk_row"][0] == 0 and r["blk_row"][-1] == pat.n_nodes
+    # oracle element matrices, replayed through S_mat and S_vec
+    Kl = np.zeros((len(d["conn"]), k, k))
+    Fl = np.zeros((len(d["conn"]), k))
+    for e, g in enumerate(d["conn"]):
+        Kl[e], Fl[e] = oracle.p1_laplace_element(d["coords"][g], d["a"][e], d["f"][e])
+    pair, b = _pair_of_slot(r, k)
+    code = r["inc"][pair]
+    vals = _sequential_segment_sum(Kl[code // k, code % k, b], r["seg_ptr"])
+    assert np.array_equal(vals, A.vals)  # bitwise
+    rhs = _sequential_segment_sum(Fl[r["inc"] // k, r["inc"] % k], r["inc_ptr"])
+    assert np.array_equal(rhs, A.rhs)
+    # pairs ascending by element inside every node
+    for i in range(pat.n_nodes):
+        seg = r["inc"][r["inc_ptr"][i]:r["inc_ptr"][i + 1]] // k
+        assert np.all(np.diff(seg) > 0)
+
+
+def tg_block_cap(order):
+    return 512 if order == 1 else 64
+
+
+def test_p2_pattern_routing_equals_oracle():
+    d = meshgen.elasticity_inputs(2, seed=2)
+    pat = tg.Pattern(d["conn"], len(d["coords"]), order=2, ncomp=3, host_only=True)
+    A = oracle.assemble_p2_elasticity(d["coords"], d["conn"], d["lam"], d["mu"], d["b"])
+    np.testing.assert_array_equal(pat.element_nodes(), A.nodes10)
+    assert pat.n_nodes == A.n_nodes and pat.n_dofs == 3 * A.n_nodes
+    rp, ci = pat.csr()
+    np.testing.assert_array_equal(rp, A.row_ptr)
+    np.testing.assert_array_equal(ci, A.col_idx)
+    r = pat.routing()
+    k = 10
+    Kl = np.zeros((len(d["conn"]), 10, 3, 10, 3))
+    Fl = np.zeros((len(d["conn"]), 10, 3))
+    for e, g in enumerate(d["conn"]):
+        Ke, Fe = oracle.p2_elasticity_element(d["coords"][g], d["lam"][e], d["mu"][e], d["b"][e])
+        Kl[e], Fl[e] = Ke.reshape(10, 3, 10, 3), Fe.reshape(10, 3)
+    pair, b = _pair_of_slot(r, k)
+    code = r["inc"][pair]
+    e, a = code // k, code % k
+    # scalar value of node entry z, components (c, c') -> CSR position
+    node_rp = r["node_rp"]
+    vals = np.zeros(pat.nnz)
+    for c in range(3):
+        for cc in range(3):
+            v = _sequential_segment_sum(Kl[e, a, c, b, cc], r["seg_ptr"])
+            for i in range(pat.n_nodes):
+                m = node_rp[i + 1] - node_rp[i]
+                base = 9 * node_rp[i] + c * 3 * m
+                vals[base + 3 * np.arange(m) + cc] = v[node_rp[i]:node_rp[i + 1]]
+    assert np.array_equal(vals, A.vals)
+    for c in range(3):
+        rhs_c = _sequential_segment_sum(Fl[r["inc"] // k, r["inc"] % k, c], r["inc_ptr"])
+        assert np.array_equal(rhs_c, A.rhs[c::3])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_p1_boundary_dofs(dim):
+    d = meshgen.poisson_inputs(dim, 5, seed=0)
+    pat = tg.Pattern(d["conn"], len(d["coords"]), host_only=True)
+    np.testing.assert_array_equal(pat.constrained_dofs(), meshgen.boundary_vertices(d["coords"]))
+    explicit = np.array([0, 3, 7], dtype=np.int32)
+    pat2 = tg.Pattern(d["conn"], len(d["coords"]), dirichlet=explicit, host_only=True)
+    np.testing.assert_array_equal(pat2.constrained_dofs(), explicit)
+    assert tg.Pattern(d["conn"], len(d["coords"]), dirichlet=None, host_only=True).n_constrained == 0
+
+
+def test_p2_boundary_dofs_are_geometric_boundary():
+    d = meshgen.elasticity_inputs(3, seed=0)
+    pat = tg.Pattern(d["conn"], len(d["coords"]), order=2, ncomp=3, host_only=True)
+    nodes10, nn = oracle.p2_numbering(len(d["coords"]), d["conn"])
+    xyz = oracle.p2_node_coords(d["coords"], d["conn"], nodes10, nn)
+    on = np.flatnonzero(np.any((xyz == 0.0) | (xyz == 1.0), axis=1))
+    expect = (3 * on[:, None] + np.arange(3)[None, :]).ravel()
+    np.testing.assert_array_equal(pat.constrained_dofs(), expect)
+
+
+def test_shuffled_mesh_pattern():
+    d = meshgen.poisson_inputs(3, 3, seed=5)
+    c2, t2, *_ = meshgen.shuffle_numbering(d["coords"], d["conn"], 3)
+    pat = tg.Pattern(t2, len(c2), host_only=True)
+    A = oracle.assemble_p1(c2, t2, np.ones(len(t2)), np.ones(len(t2)))
+    rp, ci = pat.csr()
+    np.testing.assert_array_equal(rp, A.row_ptr)
+    np.testing.assert_array_equal(ci, A.col_idx)
+
+
+def test_argument_errors():
+    c, t = meshgen.structured_mesh(2, 2)
+    with pytest.raises(tg.TGError, match="TG_E_ARG"):
+        tg.Pattern(t, len(c), order=2, ncomp=3, host_only=True)  # P2 needs dim 3
+    bad = t.copy()
+    bad[0, 0] = len(c)
+    with pytest.raises(tg.TGError, match="out of range"):
+        tg.Pattern(bad, len(c), host_only=True)
+    rep = t.copy()
+    rep[1, 1] = rep[1, 0]
+    with pytest.raises(tg.TGError, match="repeats"):
+        tg.Pattern(rep, len(c), host_only=True)
+    with pytest.raises(tg.TGError, match="used by no element"):
+        tg.Pattern(t, len(c) + 1, host_only=True)
+    with pytest.raises(tg.TGError, match="out of range"):
+        tg.Pattern(t, len(c), dirichlet=np.array([-1]), host_only=True)
+    # a host-only pattern refuses device work (checked before any GPU call)
+    pat = tg.Pattern(t, len(c), host_only=True)
+    st = tg._lib.tg_assemble(pat.handle, tg.LAPLACE, tg.F64, 8, 8, 8, 8, 8, None, None)
+    assert st == tg.TG_E_STATE
+    assert tg._lib.tg_pcg(pat.handle, tg.F64, 8, 8, 8, 1e-8, 10, 1, None, None, None) == tg.TG_E_STATE
+
+
+def test_valence_over_capacity_rejected():
+    # a fan of 600 triangles around vertex 0 exceeds the P1 block capacity
+    m = 600
+    ang = np.linspace(0, 2 * np.pi, m, endpoint=False)
+    conn = np.array([[0, 1 + i, 1 + (i + 1) % m] for i in range(m)], dtype=np.int32)
+    with pytest.raises(tg.TGError, match="block capacity"):
+        tg.Pattern(conn, m + 1, host_only=True)
