@@ -179,8 +179,10 @@ void tg_pattern_destroy(tg_pattern *p);
  *   d_rhs    : device [n_dofs] output right-hand side, or NULL.
  *   d_status : device int32 or NULL.  If given it must hold TG_STATUS_CLEAN
  *              before the call; after the kernel it holds the smallest index
- *              of an element with det J == 0 or a non-finite value (det J,
- *              a coefficient or a load), or is unchanged.  It is the only
+ *              of an element that is numerically degenerate
+ *              (|det J| <= 16 eps |x_1 - x_0| ... |x_d - x_0|) or has a
+ *              non-finite value (det J, a coefficient or a load), or is
+ *              unchanged.  It is the only
  *              word the library updates atomically.
  * Errors (host): TG_E_ARG (NULL required pointer, form/dtype not valid for the
  * pattern), TG_E_STATE (host-only pattern), TG_E_HIP (launch failure).

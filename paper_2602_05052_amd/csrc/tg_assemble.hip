@@ -98,6 +98,24 @@ __device__ __forceinline__ double p1_gradients(const double (&x)[D + 1][D], doub
     }
 }
 
+// J is numerically singular when |det J| <= 16 eps |x_1 - x_0| ... |x_d - x_0|
+// (a fraction of the Hadamard bound of J).  With fused multiply-adds, an
+// element with two coincident vertices need not give det J == 0 exactly, so a
+// scale-invariant threshold replaces the exact test; NaN and Inf fail it too.
+template <int D>
+__device__ __forceinline__ bool numerically_singular(const double (&x)[D + 1][D], double det) {
+    double prod = 1.0;
+#pragma unroll
+    for (int c = 1; c <= D; ++c) {
+        double n = 0.0;
+#pragma unroll
+        for (int r = 0; r < D; ++r) n += (x[c][r] - x[0][r]) * (x[c][r] - x[0][r]);
+        prod *= n;
+    }
+    constexpr double tol = 16.0 * 2.220446049250313e-16;
+    return !(det * det > tol * tol * prod) || !finite(det);
+}
+
 template <int D>
 __device__ __forceinline__ void load_vertices(const int32_t *__restrict__ conn, const double *__restrict__ coords,
                                               int e, double (&x)[D + 1][D]) {
@@ -144,7 +162,7 @@ __global__ __launch_bounds__(kP1Threads) void p1_assemble_kernel(
         load_vertices<D>(conn, coords, e, x);
         const double det = p1_gradients<D>(x, G);
         const double adet = fabs(det);
-        bool bad = !(adet > 0.0) || !finite(det);
+        bool bad = numerically_singular<D>(x, det);
         if constexpr (MASS) {
             // M_ab = sum_q w_q |det J| phi_a(x_q) phi_b(x_q), degree-2 rule
             using R = Deg2Rule<D>;
@@ -280,7 +298,7 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
         const double det = p1_gradients<3>(x, Gd);
         const double adet = fabs(det);
         const double lam_d = (double)coef[e], mu_d = (double)coef[(size_t)E + e];
-        bool bad = !(adet > 0.0) || !finite(det) || !finite(lam_d) || !finite(mu_d);
+        bool bad = numerically_singular<3>(x, det) || !finite(lam_d) || !finite(mu_d);
         T g[4][3];
 #pragma unroll
         for (int p = 0; p < 4; ++p)
