@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle timing sample")
+    ap.add_argument("--workload", choices=["poisson3d", "elasticity"], default="poisson3d",
+                    help="poisson3d: the benchmark line; elasticity: P2 32^3 assembly-only timing")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -90,6 +92,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
+    if args.workload == "elasticity":
+        return run_elasticity(args, dev)
 
     # ---------------------------------------------------------------- inputs (resident in HBM)
     d = meshgen.poisson_inputs(3, args.n, seed=0)
@@ -252,6 +256,61 @@ def main():
             diff = np.abs(v.double().cpu().numpy() - ovals)
             out["assembly"][f"{name}_err_vs_oracle"] = float(np.bincount(row, diff).max() / den)
 
+    print(json.dumps(out))
+
+
+def p2_bytes(nv, E, nnz, ndof, n_nodes, s):
+    """Algorithmic bytes of one P2 elasticity call (routing counted on 3x3 node-pair blocks)."""
+    b_min = nv * 3 * 8 + E * 4 * 4 + E * 5 * s + nnz * s + ndof * s
+    nnz_b = nnz // 9
+    routing = E * 100 * 4 + (nnz_b + 1) * 4 + E * 10 * 4 + (n_nodes + 1) * 4
+    return b_min, b_min + routing
+
+
+def run_elasticity(args, dev):
+    """P2 elasticity, 32^3 x 6 tets: FP64 and FP32 assembly (cold and warm), assembly only."""
+    import numpy as np
+    import torch
+
+    import meshgen
+    import paper_2602_05052_amd as tg
+
+    n = 32 if args.n == 64 else args.n
+    d = meshgen.elasticity_inputs(n, seed=0)
+    E, nv = d["conn"].shape[0], d["coords"].shape[0]
+    t0 = time.perf_counter()
+    pat = tg.Pattern(d["conn"], nv, order=2, ncomp=3)
+    pattern_s = time.perf_counter() - t0
+    coords = torch.from_numpy(d["coords"]).to(dev)
+    flush = torch.zeros(1 << 28, dtype=torch.float32, device=dev)
+    s = torch.cuda.Stream(device=dev)
+    res = {}
+    for name, dt in (("fp64", torch.float64), ("fp32", torch.float32)):
+        coef = torch.from_numpy(np.stack([d["lam"], d["mu"]])).to(dt).to(dev)
+        load = torch.from_numpy(d["b"]).to(dt).to(dev)
+        vals = torch.empty(pat.nnz, dtype=dt, device=dev)
+        rhs = torch.empty(pat.n_dofs, dtype=dt, device=dev)
+        for cold in (True, False):
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(args.steps)]
+            with torch.cuda.stream(s):
+                for _ in range(args.warmup):
+                    tg.assemble(pat, tg.ELASTICITY, coords, coef, load, values=vals, rhs=rhs, stream=s)
+                for e0, e1 in evs:
+                    if cold:
+                        flush.add_(1.0)
+                    e0.record(s)
+                    tg.assemble(pat, tg.ELASTICITY, coords, coef, load, values=vals, rhs=rhs, stream=s)
+                    e1.record(s)
+            torch.cuda.synchronize()
+            t = np.array([a.elapsed_time(b) for a, b in evs]) * 1e-3
+            bmin, balg = p2_bytes(nv, E, pat.nnz, pat.n_dofs, pat.n_nodes, 8 if dt == torch.float64 else 4)
+            res[f"{name}_{'cold' if cold else 'warm'}"] = {
+                "us": float(t.mean()) * 1e6, "elements_per_s": E / float(t.mean()),
+                "gbs_b_alg": balg / float(t.mean()) / 1e9, "gbs_b_min": bmin / float(t.mean()) / 1e9,
+                "frac_b_alg": balg / float(t.mean()) / 1e9 / HBM_PEAK_GBS}
+    out = {"workload": f"3D linear elasticity P2 tets, {n}^3 x 6 Kuhn, lambda,mu~U(0.5,2), b~N(0,1)^3, seed 0",
+           "elements": E, "nnz": pat.nnz, "dofs": pat.n_dofs, "pattern_build_s": pattern_s, **res}
     print(json.dumps(out))
 
 

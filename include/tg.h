@@ -151,9 +151,10 @@ tg_status tg_pattern_copy_element_nodes(const tg_pattern *p, int32_t *h_nodes);
  *       CSR columns of component 0 divided by ncomp).
  *   h_seg_ptr [Z+1], h_slot [P*k] : S_mat as segments: node-level entry z sums
  *       the local-matrix slots h_slot[h_seg_ptr[z] .. h_seg_ptr[z+1]) in
- *       ascending element order; a slot is (pair - first pair of the entry's
- *       row block) * k + b, i.e. local block (a, b) of the pair's element.
- *       For ncomp = 3 each slot is a 3x3 block.
+ *       ascending element order; a slot is b * n + (pair - f), where f is the
+ *       first pair and n the number of pairs of the entry's row block: local
+ *       entry (a, b) of the pair's element.  For ncomp = 3 each slot is a 3x3
+ *       block.
  */
 tg_status tg_pattern_copy_routing(const tg_pattern *p, int32_t *h_inc_ptr, int32_t *h_inc, int32_t *h_blk_row,
                                   int32_t *h_node_rp, int32_t *h_seg_ptr, uint16_t *h_slot);

@@ -32,9 +32,9 @@ hipError_t upload(const std::vector<V> &h, V **d, size_t &bytes) {
 }
 
 void free_device(tg::DevicePattern &d) {
-    void *ptrs[] = {d.conn,    d.inc_ptr, d.inc,      d.blk_row,     d.node_rp, d.seg_ptr,
+    void *ptrs[] = {d.conn,    d.inc_ptr, d.inc,      d.blk_row,     d.blk_desc, d.node_rp, d.node_ci, d.seg_ptr,
                     d.slot,    d.row_ptr, d.col_idx,  d.diag_pos,    d.constrained,
-                    d.work,    d.partials, d.state};
+                    d.work,    d.partials, d.state, d.dir_rows};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (d.host_state) (void)hipHostFree(d.host_state);
@@ -53,21 +53,25 @@ tg_status create_device(tg_pattern &pt) {
     TG_UP(inc_ptr, inc_ptr);
     TG_UP(inc, inc);
     TG_UP(blk_row, blk_row);
+    TG_UP(blk_desc, blk_desc);
     TG_UP(node_rp, node_rp);
+    TG_UP(node_ci, node_ci);
     TG_UP(seg_ptr, seg_ptr);
     TG_UP(slot, slot);
     TG_UP(row_ptr, row_ptr);
     TG_UP(col_idx, col_idx);
     TG_UP(diag_pos, diag_pos);
     TG_UP(constrained, constrained);
+    TG_UP(dirichlet_rows, dir_rows);
 #undef TG_UP
+    d.n_dir_rows = (int64_t)h.dirichlet_rows.size();
     if (e == hipSuccess) {
-        const size_t wb = 5 * (size_t)h.n_dofs * sizeof(double);
+        const size_t wb = 6 * (size_t)h.n_dofs * sizeof(double);
         e = hipMalloc((void **)&d.work, wb);
         bytes += wb;
     }
     if (e == hipSuccess) {
-        const size_t pb = 3 * (size_t)kMaxPartials * sizeof(double);
+        const size_t pb = 4 * (size_t)kMaxGrid * sizeof(double);
         e = hipMalloc((void **)&d.partials, pb);
         bytes += pb;
     }
@@ -208,6 +212,11 @@ tg_status tg_assemble(const tg_pattern *p, tg_form form, tg_dtype dtype, const d
     if (!d_coords || !d_values) return fail(TG_E_ARG, "d_coords and d_values are required");
     const tg::HostPattern &h = p->host;
     const bool scalar_p1 = (h.order == 1 && h.ncomp == 1);
+    // the kernels address every array with 32-bit byte offsets
+    const uint64_t elt = dtype == TG_F64 ? 8 : 4, lim = (uint64_t)1 << 32;
+    if ((uint64_t)h.nnz * elt >= lim || (uint64_t)h.nv * h.dim * 8 >= lim || (uint64_t)h.E * 5 * elt >= lim ||
+        (uint64_t)h.E * h.k * h.k * 2 >= lim)
+        return fail(TG_E_ARG, "an array of this mesh exceeds 4 GiB, beyond the kernels' 32-bit offsets");
     hipError_t e;
     if (form == TG_LAPLACE || form == TG_MASS) {
         if (!scalar_p1) return fail(TG_E_ARG, "LAPLACE and MASS need a P1 scalar pattern (order 1, ncomp 1)");

@@ -29,6 +29,20 @@ __device__ __forceinline__ int xcd_swizzle(int i, int n) {
     return x * q + min(x, rem) + j;
 }
 
+// Loads and stores through a uniform base pointer and a 32-bit unsigned byte
+// offset, so that the compiler can use the scalar-base + vector-offset
+// addressing of global memory instructions instead of 64-bit address
+// arithmetic per lane.  Every array the kernels touch is below 4 GiB (checked
+// on the host before the launch).
+template <typename T>
+__device__ __forceinline__ T ldg(const T *__restrict__ base, unsigned idx) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + idx * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void stg(T *__restrict__ base, unsigned idx, T v) {
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + idx * (unsigned)sizeof(T)) = v;
+}
+
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
 // Reference-simplex measure 1/d! (the weight of the 1-point centroid rule).
@@ -98,6 +112,41 @@ __device__ __forceinline__ double p1_gradients(const double (&x)[D + 1][D], doub
     }
 }
 
+// Cofactor form of the P1 gradients: grad(lambda_b) = C_b / det J, where
+// C_1..C_d are the rows of adj(J) (the reciprocal basis times det J) and
+// C_0 = -(C_1 + ... + C_d).  Then |T| grad(lambda_a).grad(lambda_b) =
+// (C_a . C_b) / (d! |det J|), which needs one division per element and no
+// scaling of the gradients.  Returns det J.
+template <int D>
+__device__ __forceinline__ double p1_cofactors(const double (&x)[D + 1][D], double (&C)[D + 1][D]) {
+    if constexpr (D == 2) {
+        const double e1x = x[1][0] - x[0][0], e1y = x[1][1] - x[0][1];
+        const double e2x = x[2][0] - x[0][0], e2y = x[2][1] - x[0][1];
+        C[1][0] = e2y;
+        C[1][1] = -e2x;
+        C[2][0] = -e1y;
+        C[2][1] = e1x;
+        C[0][0] = -(e2y - e1y);
+        C[0][1] = -(e1x - e2x);
+        return e1x * e2y - e1y * e2x;
+    } else {
+        double e[3][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) e[c][r] = x[c + 1][r] - x[0][r];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const int r1 = (r + 1) % 3, r2 = (r + 2) % 3;
+            C[1][r] = e[1][r1] * e[2][r2] - e[1][r2] * e[2][r1];
+            C[2][r] = e[2][r1] * e[0][r2] - e[2][r2] * e[0][r1];
+            C[3][r] = e[0][r1] * e[1][r2] - e[0][r2] * e[1][r1];
+            C[0][r] = -(C[1][r] + C[2][r] + C[3][r]);
+        }
+        return e[0][0] * C[1][0] + e[0][1] * C[1][1] + e[0][2] * C[1][2];
+    }
+}
+
 // J is numerically singular when |det J| <= 16 eps |x_1 - x_0| ... |x_d - x_0|
 // (a fraction of the Hadamard bound of J).  With fused multiply-adds, an
 // element with two coincident vertices need not give det J == 0 exactly, so a
@@ -113,54 +162,139 @@ __device__ __forceinline__ bool numerically_singular(const double (&x)[D + 1][D]
         prod *= n;
     }
     constexpr double tol = 16.0 * 2.220446049250313e-16;
-    return !(det * det > tol * tol * prod) || !finite(det);
+    return (bool)((int)!(det * det > tol * tol * prod) | (int)!finite(det));
 }
 
 template <int D>
 __device__ __forceinline__ void load_vertices(const int32_t *__restrict__ conn, const double *__restrict__ coords,
                                               int e, double (&x)[D + 1][D]) {
-    int v[D + 1];
+    unsigned v[D + 1];
     if constexpr (D == 3) {
-        const int4 q = *reinterpret_cast<const int4 *>(conn + 4 * (size_t)e);
-        v[0] = q.x;
-        v[1] = q.y;
-        v[2] = q.z;
-        v[3] = q.w;
+        const int4 q = ldg(reinterpret_cast<const int4 *>(conn), (unsigned)e);
+        v[0] = (unsigned)q.x;
+        v[1] = (unsigned)q.y;
+        v[2] = (unsigned)q.z;
+        v[3] = (unsigned)q.w;
     } else {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) v[a] = conn[3 * (size_t)e + a];
+        for (int a = 0; a < 3; ++a) v[a] = (unsigned)ldg(conn, 3u * (unsigned)e + a);
     }
 #pragma unroll
     for (int a = 0; a <= D; ++a)
 #pragma unroll
-        for (int c = 0; c < D; ++c) x[a][c] = coords[(size_t)v[a] * D + c];
+        for (int c = 0; c < D; ++c) x[a][c] = ldg(coords, v[a] * D + c);
 }
 
 // ---------------------------------------------------------------- P1 scalar forms
 
-template <int D, typename T, bool MASS>
+// Sum of src[slot[u]] for u in [u0, u1), added strictly left to right.  The
+// slot indices and values are read four at a time so that the dependent LDS
+// round trips overlap; the order of the additions is unchanged.
+template <typename T, int STRIDE = 1>
+__device__ __forceinline__ T segment_sum(const T *__restrict__ src, const uint16_t *__restrict__ slot, int u0, int u1,
+                                         int off = 0) {
+    T acc = 0;
+    int u = u0;
+    for (; u + 4 <= u1; u += 4) {
+        const int a0 = slot[u], a1 = slot[u + 1], a2 = slot[u + 2], a3 = slot[u + 3];
+        const T k0 = src[a0 * STRIDE + off], k1 = src[a1 * STRIDE + off];
+        const T k2 = src[a2 * STRIDE + off], k3 = src[a3 * STRIDE + off];
+        acc += k0;
+        acc += k1;
+        acc += k2;
+        acc += k3;
+    }
+    for (; u < u1; ++u) acc += src[slot[u] * STRIDE + off];
+    return acc;
+}
+
+// Dynamic LDS of one row block: local matrices, loads, and the block's share
+// of the routing (segment pointers and slot list, copied in with coalesced
+// loads, so the Reduce touches only LDS).
+template <typename T>
+struct BlockLds {
+    T *K;            // [mp * kk]  local matrix entries (kk = k, or 9 k for 3x3 blocks)
+    T *F;            // [mp * nc]  local load entries
+    int32_t *seg;    // [me + 1]   segment starts, relative to the block's first slot
+    uint16_t *slot;  // [mp * k]   slots of the block, in CSR entry order
+    __device__ BlockLds(unsigned char *base, int mp, int me, int kk, int nc, int k) {
+        K = reinterpret_cast<T *>(base);
+        F = K + (size_t)mp * kk;
+        seg = reinterpret_cast<int32_t *>(F + (size_t)mp * nc);
+        slot = reinterpret_cast<uint16_t *>(seg + ((me + 2) & ~1));
+        (void)k;
+    }
+    __host__ __device__ static size_t bytes(int mp, int me, int kk, int nc, int k) {
+        return sizeof(T) * (size_t)mp * (kk + nc) + sizeof(int32_t) * (size_t)((me + 2) & ~1) +
+               sizeof(uint16_t) * (size_t)mp * k;
+    }
+};
+
+// Row a (run time) of a [D+1][D] table as sum_k [a == k] C_k: exact (a product
+// by 1 and sums with zeros), branch-free, and with no run-time index into the
+// table (a select of two table entries can be folded into a load through a
+// selected address, which sends the table to scratch memory).
+template <int D>
+__device__ __forceinline__ void select_row(const double (&C)[D + 1][D], int a, double (&out)[D]) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) out[c] = 0.0;
+#pragma unroll
+    for (int k = 0; k <= D; ++k) {
+        const double m = (a == k) ? 1.0 : 0.0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) out[c] += m * C[k][c];
+    }
+}
+
+template <int D, typename T, bool MASS, bool LOAD>
 __global__ __launch_bounds__(kP1Threads) void p1_assemble_kernel(
-    const int32_t *__restrict__ blk_row, const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc,
-    const int32_t *__restrict__ node_rp, const int32_t *__restrict__ seg_ptr, const uint16_t *__restrict__ slot,
-    const int32_t *__restrict__ conn, const double *__restrict__ coords, const T *__restrict__ coef,
-    const T *__restrict__ load, T *__restrict__ values, T *__restrict__ rhs, int32_t *__restrict__ status,
-    int nblk) {
+    const int32_t *__restrict__ blk_desc, const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc,
+    const int32_t *__restrict__ seg_ptr, const uint16_t *__restrict__ slot, const int32_t *__restrict__ conn,
+    const double *__restrict__ coords, const T *__restrict__ coef, const T *__restrict__ load,
+    T *__restrict__ values, T *__restrict__ rhs, int32_t *__restrict__ status, int nblk, int mp, int me) {
     constexpr int K = D + 1;
-    __shared__ T sK[kP1BlockCap * K];
-    __shared__ T sF[kP1BlockCap];
+    extern __shared__ __align__(16) unsigned char smem[];
+    BlockLds<T> L(smem, mp, me, K, 1, K);
 
     const int blk = xcd_swizzle(blockIdx.x, nblk);
-    const int r0 = blk_row[blk], r1 = blk_row[blk + 1];
-    const int q0 = inc_ptr[r0], q1 = inc_ptr[r1];
-    const int np = q1 - q0;
+    const int4 dsc = ldg(reinterpret_cast<const int4 *>(blk_desc), 2u * blk);
+    const int2 dsv = ldg(reinterpret_cast<const int2 *>(blk_desc), 4u * blk + 2u);
+    const int r0 = dsc.x, r1 = dsc.y, q0 = dsc.z, q1 = dsc.w, v0 = dsv.x, v1 = dsv.y;
+    const int np = q1 - q0, nent = v1 - v0;
+    const unsigned s0 = (unsigned)q0 * K;  // the block's slots are slot[s0 .. s0 + np K)
+    const int tid = threadIdx.x;
+
+    // The block's share of the routing, fetched first (independent of the Map's
+    // load chain) and written to LDS after the Map: one unit of K slots and one
+    // segment pointer per thread, the remainder of a large block afterwards.
+    uint16_t slot_reg[K];
+    int seg_reg = 0;
+    if (tid < np) {
+        if constexpr (K == 4) {  // s0 is a multiple of 4 slots: one 8-byte load
+            const uint2 w = ldg(reinterpret_cast<const uint2 *>(slot), s0 / 4u + tid);
+            slot_reg[0] = (uint16_t)w.x;
+            slot_reg[1] = (uint16_t)(w.x >> 16);
+            slot_reg[2] = (uint16_t)w.y;
+            slot_reg[3] = (uint16_t)(w.y >> 16);
+        } else {
+#pragma unroll
+            for (int j = 0; j < K; ++j) slot_reg[j] = ldg(slot, s0 + (unsigned)(K * tid + j));
+        }
+    }
+    if (tid <= nent) seg_reg = ldg(seg_ptr, (unsigned)(v0 + tid));
 
     // ---- Map: row a of K_e (and F_e[a]) for every pair of the block
-    for (int t = threadIdx.x; t < np; t += kP1Threads) {
-        const int code = inc[q0 + t];
-        const int e = code / K, a = code - e * K;
-        double x[K][D], G[K][D];
-        load_vertices<D>(conn, coords, e, x);
-        const double det = p1_gradients<D>(x, G);
+    for (int t = tid; t < np; t += kP1Threads) {
+        const unsigned code = (unsigned)ldg(inc, (unsigned)(q0 + t));
+        const unsigned e = code / K;
+        const int a = (int)(code - e * K);
+        double ce = 1.0, fe = 0.0;
+        if (!MASS) ce = (double)ldg(coef, e);
+        if (LOAD) fe = (double)ldg(load, e);
+        double x[K][D];
+        load_vertices<D>(conn, coords, (int)e, x);
+        double C[K][D];
+        const double det = p1_cofactors<D>(x, C);
         const double adet = fabs(det);
         bool bad = numerically_singular<D>(x, det);
         if constexpr (MASS) {
@@ -175,46 +309,57 @@ __global__ __launch_bounds__(kP1Threads) void p1_assemble_kernel(
                     const double pb = (b == q) ? R::hi : R::lo;
                     m += R::w * pa * pb;
                 }
-                sK[t * K + b] = (T)(adet * m);
+                L.K[b * np + t] = (T)(adet * m);
             }
         } else {
-            // 1-point centroid rule: the integrand a_e G_a . G_b is constant
-            const double ce = (double)coef[e];
-            const double fe = load ? (double)load[e] : 0.0;
-            bad = bad || !finite(ce) || !finite(fe);
-            const double w = adet * RefSimplex<D>::vol;
-            const T wc = (T)(w * ce);
-            T ga[D];
+            bad = (bool)((int)bad | (int)!finite(ce) | (int)!finite(fe));
+            // 1-point centroid rule (the integrand a_e G_a . G_b is constant):
+            // K_ab = w |det J| a_e (C_a/det).(C_b/det) = a_e (C_a . C_b) / (d! |det J|)
+            const T sc = (T)(ce / (adet * (1.0 / RefSimplex<D>::vol)));
+            double cad[D];
+            select_row<D>(C, a, cad);
+            T ca[D];
 #pragma unroll
-            for (int c = 0; c < D; ++c) ga[c] = (T)(a == 0 ? G[0][c] : a == 1 ? G[1][c] : a == 2 ? G[2][c] : G[K - 1][c]);
+            for (int c = 0; c < D; ++c) ca[c] = (T)cad[c];
 #pragma unroll
             for (int b = 0; b < K; ++b) {
-                T s = 0;
+                T sum = 0;
 #pragma unroll
-                for (int c = 0; c < D; ++c) s += ga[c] * (T)G[b][c];
-                sK[t * K + b] = wc * s;
+                for (int c = 0; c < D; ++c) sum += ca[c] * (T)C[b][c];
+                L.K[b * np + t] = sc * sum;
             }
-            sF[t] = (T)(w * fe * (1.0 / K));  // phi_a(centroid) = 1/(d+1)
+            L.F[t] = (T)(fe * adet * (RefSimplex<D>::vol / K));  // phi_a(centroid) = 1/(d+1)
         }
-        if (bad && status) atomicMin(status, e);
+        if (bad && status) atomicMin(status, (int)e);
     }
+    // ---- routing -> LDS (registers first, then any remainder of a large block)
+    if (tid < np) {
+        if constexpr (K == 4) {
+            *reinterpret_cast<uint2 *>(L.slot + 4 * tid) =
+                make_uint2((uint32_t)slot_reg[0] | ((uint32_t)slot_reg[1] << 16),
+                           (uint32_t)slot_reg[2] | ((uint32_t)slot_reg[3] << 16));
+        } else {
+#pragma unroll
+            for (int j = 0; j < K; ++j) L.slot[K * tid + j] = slot_reg[j];
+        }
+    }
+    for (int u = K * (tid + kP1Threads); u < np * K; u += K * kP1Threads)
+#pragma unroll
+        for (int j = 0; j < K; ++j) L.slot[u + j] = ldg(slot, s0 + (unsigned)(u + j));
+    if (tid <= nent) L.seg[tid] = seg_reg - (int)s0;
+    for (int u = tid + kP1Threads; u <= nent; u += kP1Threads) L.seg[u] = ldg(seg_ptr, (unsigned)(v0 + u)) - (int)s0;
     __syncthreads();
 
-    // ---- Reduce: CSR values of the block rows (S_mat projection)
-    const int v0 = node_rp[r0], v1 = node_rp[r1];
-    for (int p = v0 + threadIdx.x; p < v1; p += kP1Threads) {
-        const int s0 = seg_ptr[p], s1 = seg_ptr[p + 1];
-        T acc = 0;
-        for (int s = s0; s < s1; ++s) acc += sK[slot[s]];
-        values[p] = acc;
-    }
+    // ---- Reduce: CSR values of the block rows (S_mat projection), LDS only
+    for (int p = threadIdx.x; p < nent; p += kP1Threads)
+        stg(values, (unsigned)(v0 + p), segment_sum<T>(L.K, L.slot, L.seg[p], L.seg[p + 1]));
     // ---- Reduce: right-hand side (S_vec projection)
-    if (!MASS && rhs) {
+    if (LOAD) {
         for (int r = r0 + threadIdx.x; r < r1; r += kP1Threads) {
-            const int u0 = inc_ptr[r] - q0, u1 = inc_ptr[r + 1] - q0;
+            const int u0 = ldg(inc_ptr, (unsigned)r) - q0, u1 = ldg(inc_ptr, (unsigned)r + 1u) - q0;
             T acc = 0;
-            for (int u = u0; u < u1; ++u) acc += sF[u];
-            rhs[r] = acc;
+            for (int u = u0; u < u1; ++u) acc += L.F[u];
+            stg(rhs, (unsigned)r, acc);
         }
     }
 }
@@ -223,29 +368,28 @@ __global__ __launch_bounds__(kP1Threads) void p1_assemble_kernel(
 
 constexpr int kP2LanesPerPair = 4;
 
-// grad(phi_n) at a Keast point for P2 node n (vertices 0..3, then edges
-// (0,1),(0,2),(0,3),(1,2),(1,3),(2,3)):  vertex p: (4 lambda_p - 1) grad(lambda_p);
-// edge (p,r): 4 (lambda_r grad(lambda_p) + lambda_p grad(lambda_r)).
-// lam_q(p) is the barycentric coordinate of vertex p at the point.
-template <typename T>
-__device__ __forceinline__ void p2_grad(int n, int q, const T (&g)[4][3], T hi, T lo, T (&out)[3]) {
-    const int p = n < 4 ? n : (n < 7 ? 0 : (n < 9 ? 1 : 2));
-    const int r = n < 4 ? n : (n == 4 ? 1 : n == 5 ? 2 : n == 6 ? 3 : n == 7 ? 2 : 3);
-    const T lp = (p == q) ? hi : lo;
-    const T lr = (r == q) ? hi : lo;
-    T gp[3], gr[3];
+// grad(phi_n) at Keast point q (compile time) for P2 node n (run time):
+// vertex p: (4 lambda_p - 1) grad(lambda_p); edge (i,j): 4 (lambda_j grad(lambda_i)
+// + lambda_i grad(lambda_j)).  Written as sum_p c_p grad(lambda_p) with the
+// coefficients chosen by comparisons against the compile-time p, so no array
+// is indexed with a run-time value (that would go through scratch memory).
+// Nodes: vertices 0..3, then edges (0,1),(0,2),(0,3),(1,2),(1,3),(2,3).
+template <typename T, int Q>
+__device__ __forceinline__ void p2_grad(int n, const T (&g)[4][3], T hi, T lo, T (&out)[3]) {
+    const bool vtx = n < 4;
+    const int i = vtx ? n : (n < 7 ? 0 : (n < 9 ? 1 : 2));
+    const int j = vtx ? n : (n == 4 ? 1 : (n == 5 || n == 7) ? 2 : 3);
+    const T li = (i == Q) ? hi : lo;  // lambda_i at the point
+    const T lj = (j == Q) ? hi : lo;
+    const T ci = vtx ? (T)4 * li - (T)1 : (T)4 * lj;  // coefficient of grad(lambda_i)
+    const T cj = vtx ? (T)0 : (T)4 * li;              // coefficient of grad(lambda_j)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        gp[c] = p == 0 ? g[0][c] : p == 1 ? g[1][c] : p == 2 ? g[2][c] : g[3][c];
-        gr[c] = r == 0 ? g[0][c] : r == 1 ? g[1][c] : r == 2 ? g[2][c] : g[3][c];
-    }
-    if (n < 4) {
-        const T s = (T)4 * lp - (T)1;
+    for (int c = 0; c < 3; ++c) out[c] = 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) out[c] = s * gp[c];
-    } else {
+    for (int p = 0; p < 4; ++p) {
+        const T cp = (p == i) ? ci : ((p == j) ? cj : (T)0);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) out[c] = (T)4 * (lr * gp[c] + lp * gr[c]);
+        for (int c = 0; c < 3; ++c) out[c] += cp * g[p][c];
     }
 }
 
@@ -273,19 +417,23 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     const int32_t *__restrict__ node_rp, const int32_t *__restrict__ seg_ptr, const uint16_t *__restrict__ slot,
     const int32_t *__restrict__ conn, const double *__restrict__ coords, const T *__restrict__ coef,
     const T *__restrict__ load, T *__restrict__ values, T *__restrict__ rhs, int32_t *__restrict__ status, int nblk,
-    int E) {
+    int E, int mp, int me) {
     constexpr int K = 10;
-    __shared__ T sK[kP2BlockCap * K * 9];
-    __shared__ T sF[kP2BlockCap * 3];
+    extern __shared__ __align__(16) unsigned char smem[];
+    BlockLds<T> L(smem, mp, me, 9 * K, 3, K);
     __shared__ int sRp[kP2BlockCap + 1];
 
     const int blk = xcd_swizzle(blockIdx.x, nblk);
     const int r0 = blk_row[blk], r1 = blk_row[blk + 1];
     const int q0 = inc_ptr[r0], q1 = inc_ptr[r1];
-    const int np = q1 - q0;
+    const int rp0 = node_rp[r0], rp1 = node_rp[r1];
+    const int np = q1 - q0, nent = rp1 - rp0;
     const int nrows = r1 - r0;
-    const int rp0 = node_rp[r0];
+    const int s0 = q0 * K;
     for (int r = threadIdx.x; r <= nrows; r += kP2Threads) sRp[r] = node_rp[r0 + r] - rp0;
+    for (int t = threadIdx.x; t <= nent; t += kP2Threads) L.seg[t] = seg_ptr[rp0 + t] - s0;
+    for (int t = threadIdx.x; t < np * K / 2; t += kP2Threads)  // s0 and np K are even: 4-byte copies
+        reinterpret_cast<uint32_t *>(L.slot)[t] = reinterpret_cast<const uint32_t *>(slot + s0)[t];
 
     // ---- Map: block row a of K_e (10 blocks of 3x3), split over 4 lanes by column node
     using R = Deg2Rule<3>;
@@ -295,9 +443,9 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
         const int e = code / K, a = code - e * K;
         double x[4][3], Gd[4][3];
         load_vertices<3>(conn, coords, e, x);
+        const double lam_d = (double)coef[e], mu_d = (double)coef[(size_t)E + e];
         const double det = p1_gradients<3>(x, Gd);
         const double adet = fabs(det);
-        const double lam_d = (double)coef[e], mu_d = (double)coef[(size_t)E + e];
         bool bad = numerically_singular<3>(x, det) || !finite(lam_d) || !finite(mu_d);
         T g[4][3];
 #pragma unroll
@@ -308,23 +456,27 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
         const T w = (T)(adet * R::w);
         const T lam = (T)lam_d, mu = (T)mu_d;
         T ga[4][3];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) p2_grad<T>(a, q, g, hi, lo, ga[q]);
+        p2_grad<T, 0>(a, g, hi, lo, ga[0]);
+        p2_grad<T, 1>(a, g, hi, lo, ga[1]);
+        p2_grad<T, 2>(a, g, hi, lo, ga[2]);
+        p2_grad<T, 3>(a, g, hi, lo, ga[3]);
         for (int b = sub; b < K; b += kP2LanesPerPair) {
             // D_ab = sum_q w_q |det J| grad(phi_a) grad(phi_b)^T
             T Dm[3][3] = {};
+            T gb[4][3];
+            p2_grad<T, 0>(b, g, hi, lo, gb[0]);
+            p2_grad<T, 1>(b, g, hi, lo, gb[1]);
+            p2_grad<T, 2>(b, g, hi, lo, gb[2]);
+            p2_grad<T, 3>(b, g, hi, lo, gb[3]);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                T gb[3];
-                p2_grad<T>(b, q, g, hi, lo, gb);
+            for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
-                    for (int cc = 0; cc < 3; ++cc) Dm[c][cc] += w * ga[q][c] * gb[cc];
-            }
+                    for (int cc = 0; cc < 3; ++cc) Dm[c][cc] += w * ga[q][c] * gb[q][cc];
             // Hooke: block[c][c'] = lam D[c][c'] + mu (D[c'][c] + delta_cc' tr D)
             const T tr = Dm[0][0] + Dm[1][1] + Dm[2][2];
-            T *dst = sK + (t * K + b) * 9;
+            T *dst = L.K + (b * np + t) * 9;
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -337,7 +489,7 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
                 for (int c = 0; c < 3; ++c) {
                     const double bc = (double)load[(size_t)e * 3 + c];
                     bad = bad || !finite(bc);
-                    sF[t * 3 + c] = (T)(bc * ia);
+                    L.F[t * 3 + c] = (T)(bc * ia);
                 }
             }
             if (bad && status) atomicMin(status, e);
@@ -346,7 +498,7 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     __syncthreads();
 
     // ---- Reduce: the block's scalar values are the contiguous range [9 rp0, 9 rp1)
-    const int nval = 9 * sRp[nrows];
+    const int nval = 9 * nent;
     T *out = values + 9 * (size_t)rp0;
     for (int v = threadIdx.x; v < nval; v += kP2Threads) {
         int lo_r = 0, hi_r = nrows - 1;  // last row with 9 * sRp[r] <= v
@@ -362,18 +514,15 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
         const int rem = off - c * 3 * m;
         const int jpos = rem / 3;
         const int cc = rem - 3 * jpos;
-        const int pnode = rp0 + sRp[r] + jpos;
-        const int s0 = seg_ptr[pnode], s1 = seg_ptr[pnode + 1];
-        T acc = 0;
-        for (int s = s0; s < s1; ++s) acc += sK[(int)slot[s] * 9 + c * 3 + cc];
-        out[v] = acc;
+        const int pe = sRp[r] + jpos;  // node-level entry within the block
+        out[v] = segment_sum<T, 9>(L.K, L.slot, L.seg[pe], L.seg[pe + 1], c * 3 + cc);
     }
     if (rhs && load) {
         for (int u = threadIdx.x; u < 3 * nrows; u += kP2Threads) {
             const int r = u / 3, c = u - 3 * r;
             const int u0 = inc_ptr[r0 + r] - q0, u1 = inc_ptr[r0 + r + 1] - q0;
             T acc = 0;
-            for (int s = u0; s < u1; ++s) acc += sF[s * 3 + c];
+            for (int s = u0; s < u1; ++s) acc += L.F[s * 3 + c];
             rhs[3 * (size_t)(r0 + r) + c] = acc;
         }
     }
@@ -383,14 +532,16 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
 
 // ---------------------------------------------------------------- launchers
 
-template <int D, typename T, bool MASS>
+template <int D, typename T, bool MASS, bool LOAD>
 static hipError_t launch_p1_t(const tg_pattern &p, const double *coords, const void *coef, const void *load,
                               void *values, void *rhs, int32_t *status, hipStream_t s) {
     const DevicePattern &d = p.dev;
     const int nblk = (int)p.host.n_blocks();
-    hipLaunchKernelGGL((p1_assemble_kernel<D, T, MASS>), dim3(nblk), dim3(kP1Threads), 0, s, d.blk_row, d.inc_ptr,
-                       d.inc, d.node_rp, d.seg_ptr, d.slot, d.conn, coords, (const T *)coef, (const T *)load,
-                       (T *)values, (T *)rhs, status, nblk);
+    const int mp = p.host.max_block_pairs, me = p.host.max_block_entries;
+    const size_t lds = BlockLds<T>::bytes(mp, me, D + 1, 1, D + 1);
+    hipLaunchKernelGGL((p1_assemble_kernel<D, T, MASS, LOAD>), dim3(nblk), dim3(kP1Threads), lds, s, d.blk_desc,
+                       d.inc_ptr, d.inc, d.seg_ptr, d.slot, d.conn, coords, (const T *)coef, (const T *)load,
+                       (T *)values, (T *)rhs, status, nblk, mp, me);
     return hipGetLastError();
 }
 
@@ -398,11 +549,13 @@ hipError_t launch_assemble_p1(const tg_pattern &p, tg_form form, tg_dtype dtype,
                               const void *coef, const void *load, void *values, void *rhs, int32_t *status,
                               hipStream_t s) {
     const bool mass = form == TG_MASS;
+    const bool with_load = !mass && load && rhs;
     const int D = p.host.dim;
-#define TG_P1_CASE(DD, TT)                                                                               \
-    if (D == DD) {                                                                                       \
-        if (mass) return launch_p1_t<DD, TT, true>(p, coords, coef, load, values, rhs, status, s);      \
-        return launch_p1_t<DD, TT, false>(p, coords, coef, load, values, rhs, status, s);                \
+#define TG_P1_CASE(DD, TT)                                                                                \
+    if (D == DD) {                                                                                        \
+        if (mass) return launch_p1_t<DD, TT, true, false>(p, coords, coef, load, values, rhs, status, s); \
+        if (with_load) return launch_p1_t<DD, TT, false, true>(p, coords, coef, load, values, rhs, status, s); \
+        return launch_p1_t<DD, TT, false, false>(p, coords, coef, load, values, rhs, status, s);          \
     }
     if (dtype == TG_F64) {
         TG_P1_CASE(2, double)
@@ -420,14 +573,17 @@ hipError_t launch_assemble_p2(const tg_pattern &p, tg_dtype dtype, const double 
     const DevicePattern &d = p.dev;
     const int nblk = (int)p.host.n_blocks();
     const int E = (int)p.host.E;
+    const int mp = p.host.max_block_pairs, me = p.host.max_block_entries;
     if (dtype == TG_F64)
-        hipLaunchKernelGGL(p2_elasticity_kernel<double>, dim3(nblk), dim3(kP2Threads), 0, s, d.blk_row, d.inc_ptr,
-                           d.inc, d.node_rp, d.seg_ptr, d.slot, d.conn, coords, (const double *)coef,
-                           (const double *)load, (double *)values, (double *)rhs, status, nblk, E);
+        hipLaunchKernelGGL(p2_elasticity_kernel<double>, dim3(nblk), dim3(kP2Threads),
+                           BlockLds<double>::bytes(mp, me, 90, 3, 10), s, d.blk_row, d.inc_ptr, d.inc, d.node_rp,
+                           d.seg_ptr, d.slot, d.conn, coords, (const double *)coef, (const double *)load,
+                           (double *)values, (double *)rhs, status, nblk, E, mp, me);
     else
-        hipLaunchKernelGGL(p2_elasticity_kernel<float>, dim3(nblk), dim3(kP2Threads), 0, s, d.blk_row, d.inc_ptr,
-                           d.inc, d.node_rp, d.seg_ptr, d.slot, d.conn, coords, (const float *)coef,
-                           (const float *)load, (float *)values, (float *)rhs, status, nblk, E);
+        hipLaunchKernelGGL(p2_elasticity_kernel<float>, dim3(nblk), dim3(kP2Threads),
+                           BlockLds<float>::bytes(mp, me, 90, 3, 10), s, d.blk_row, d.inc_ptr, d.inc, d.node_rp,
+                           d.seg_ptr, d.slot, d.conn, coords, (const float *)coef, (const float *)load,
+                           (float *)values, (float *)rhs, status, nblk, E, mp, me);
     return hipGetLastError();
 }
 

@@ -39,9 +39,10 @@ struct HostPattern {
     std::vector<int32_t> inc_ptr;  // [n_nodes+1]
     std::vector<int32_t> inc;      // [n_pairs]
     // Row blocks for the fused kernels.
-    std::vector<int32_t> blk_row;  // [n_blocks+1]
+    std::vector<int32_t> blk_row;   // [n_blocks+1]
+    std::vector<int32_t> blk_desc;  // [n_blocks][8]: r0, r1, q0, q1, v0, v1 (rows, pairs, node entries), 0, 0
     // S_mat routing: node-level entry p sums slots slot[seg_ptr[p] .. seg_ptr[p+1]),
-    // ascending element order; slot = (pair - first pair of the block) * k + b.
+    // ascending element order; slot = b * (pairs of the block) + (pair - first pair of the block).
     std::vector<int32_t> seg_ptr;  // [nnz_nodes+1]
     std::vector<uint16_t> slot;    // [n_pairs * k]
     // Scalar CSR (DoF = ncomp * node + c).
@@ -51,6 +52,11 @@ struct HostPattern {
     // Dirichlet.
     std::vector<uint8_t> constrained;  // [n_dofs] 0/1
     std::vector<int32_t> constrained_list;
+    std::vector<int32_t> dirichlet_rows;  // rows touched by the elimination, ascending
+
+    // Largest row block, for sizing the kernels' LDS.
+    int32_t max_block_pairs = 0;
+    int32_t max_block_entries = 0;  // node-level CSR entries
 
     int64_t n_pairs() const { return (int64_t)inc.size(); }
     int64_t n_blocks() const { return (int64_t)blk_row.size() - 1; }
@@ -62,32 +68,35 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
 
 // PCG device state (one per pattern).
 struct PcgState {
-    double rz[2];  // r.z of the current iterate, double-buffered by iteration parity
-    double bb;     // b.b
-    double rr;     // r.r of the latest iterate
-    double tol2;   // rtol^2 * b.b
-    int32_t done;  // 1 once the stop test held
-    int32_t iters; // iteration at which it held
+    double bb;      // b.b
+    double rr;      // true residual r.r after the final check
+    double tol2;    // rtol^2 * b.b
+    int32_t done;   // 1 once the stop test held
+    int32_t iters;  // iteration at which it held
 };
 
-constexpr int kVecThreads = 256;
-constexpr int kMaxPartials = 1024;  // blocks of the reduction kernels
+constexpr int kVecThreads = 1024;  // threads per block of the PCG kernels
+constexpr int kMaxGrid = 512;      // blocks of the PCG kernels (grid-stride beyond): 2 per CU
 
 struct DevicePattern {
     int32_t *conn = nullptr;      // [E][dim+1]
     int32_t *inc_ptr = nullptr;   // [n_nodes+1]
     int32_t *inc = nullptr;       // [n_pairs]
     int32_t *blk_row = nullptr;   // [n_blocks+1]
+    int32_t *blk_desc = nullptr;  // [n_blocks][8]
     int32_t *node_rp = nullptr;   // [n_nodes+1]
+    int32_t *node_ci = nullptr;   // [nnz_nodes]
     int32_t *seg_ptr = nullptr;   // [nnz_nodes+1]
     uint16_t *slot = nullptr;     // [n_pairs*k]
     int32_t *row_ptr = nullptr;   // [n_dofs+1]
     int32_t *col_idx = nullptr;   // [nnz]
     int32_t *diag_pos = nullptr;  // [n_dofs]
     uint8_t *constrained = nullptr;  // [n_dofs]
-    // PCG workspace: 5 vectors of n_dofs doubles (used as T), partials, state.
+    // PCG workspace: 6 vectors of n_dofs doubles (used as T), partials, state.
     double *work = nullptr;
-    double *partials = nullptr;  // [3 * kMaxPartials]
+    double *partials = nullptr;  // [4][kMaxGrid]: (p.q), (r.z, r.r), (b.b) partials
+    int32_t *dir_rows = nullptr; // rows that are constrained or have a constrained column
+    int64_t n_dir_rows = 0;
     PcgState *state = nullptr;
     PcgState *host_state = nullptr;  // pinned mirror
     size_t bytes = 0;

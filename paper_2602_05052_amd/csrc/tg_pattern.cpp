@@ -11,7 +11,8 @@
 //   S_mat: for each node-level CSR entry (i, j), the element slots (pair of row
 //          i, local column b) that land on it, in ascending element order
 //          (seg_ptr / slot).  Slot ids are relative to the row block of the
-//          fused kernel, i.e. they index the block's local matrices in LDS.
+//          fused kernel and index its local matrices in LDS, stored column by
+//          column: slot = b * (pairs of the block) + (pair - first pair).
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -184,6 +185,7 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
     for (int64_t i = 0; i < N; ++i) {
         while (hp.blk_row[blk + 1] <= i) ++blk;
         const int32_t blk_first_pair = hp.inc_ptr[hp.blk_row[blk]];
+        const int32_t blk_pairs = hp.inc_ptr[hp.blk_row[blk + 1]] - blk_first_pair;
         cols.clear();
         for (int32_t t = hp.inc_ptr[i]; t < hp.inc_ptr[i + 1]; ++t) {
             const int64_t e = hp.inc[t] / k;
@@ -209,7 +211,7 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
             const int64_t e = hp.inc[t] / k;
             for (int b = 0; b < k; ++b) {
                 const int c = pos[hp.elem_nodes[e * k + b]];
-                hp.slot[slot_fill + cnt[c]++] = (uint16_t)((t - blk_first_pair) * k + b);
+                hp.slot[slot_fill + cnt[c]++] = (uint16_t)(b * blk_pairs + (t - blk_first_pair));
             }
         }
         slot_fill += (int64_t)(hp.inc_ptr[i + 1] - hp.inc_ptr[i]) * k;
@@ -222,6 +224,20 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
     }
     hp.seg_ptr.push_back((int32_t)slot_fill);
     hp.nnz_nodes = (int64_t)hp.node_ci.size();
+    hp.max_block_pairs = hp.max_block_entries = 0;
+    hp.blk_desc.assign((hp.blk_row.size() - 1) * 8, 0);
+    for (int64_t b = 0; b + 1 < (int64_t)hp.blk_row.size(); ++b) {
+        const int32_t r0 = hp.blk_row[b], r1 = hp.blk_row[b + 1];
+        int32_t *dsc = &hp.blk_desc[b * 8];
+        dsc[0] = r0;
+        dsc[1] = r1;
+        dsc[2] = hp.inc_ptr[r0];
+        dsc[3] = hp.inc_ptr[r1];
+        dsc[4] = hp.node_rp[r0];
+        dsc[5] = hp.node_rp[r1];
+        hp.max_block_pairs = std::max(hp.max_block_pairs, hp.inc_ptr[r1] - hp.inc_ptr[r0]);
+        hp.max_block_entries = std::max(hp.max_block_entries, hp.node_rp[r1] - hp.node_rp[r0]);
+    }
     hp.nnz = hp.nnz_nodes * ncomp * ncomp;
 
     // ---- scalar CSR (DoF = ncomp * node + c; the 3 rows of a node share its node columns)
@@ -298,6 +314,12 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
                 hp.constrained[i * ncomp + c] = 1;
                 hp.constrained_list.push_back((int32_t)(i * ncomp + c));
             }
+    hp.dirichlet_rows.clear();
+    for (int64_t r = 0; r < hp.n_dofs; ++r) {
+        bool touched = hp.constrained[r] != 0;
+        for (int32_t q = hp.row_ptr[r]; !touched && q < hp.row_ptr[r + 1]; ++q) touched = hp.constrained[hp.col_idx[q]];
+        if (touched) hp.dirichlet_rows.push_back((int32_t)r);
+    }
     return TG_OK;
 }
 

@@ -2,44 +2,59 @@
 // CSR system (TensorGalerkin Sec. B.1.2: Jacobi-preconditioned Krylov solve of
 // the condensed system, stopped on ||K u - f|| / ||f||).
 //
-// Reductions are deterministic: each block reduces its grid-stride share in a
-// fixed order, writes one partial, and every consumer sums the partials in the
-// same fixed order, so the solver is bitwise reproducible without atomics.
+// One CG iteration is two kernels of at most 512 blocks of 1024 threads:
+//   pcg_spmv   : stop test on r.r, beta = r.z / r.z_prev, p = z + beta p
+//                (formed on the fly into the other half of a double buffer),
+//                q = K p and per-block partials of p.q;
+//   pcg_update : alpha = r.z / p.q, x += alpha p, r -= alpha q, z = D^{-1} r,
+//                per-block partials of r.z and r.r.
+// Every scalar (alpha, beta, the stop decision) is recomputed by every block
+// from the previous kernel's partials, summed in one fixed order, so all
+// blocks agree bitwise and the solver is reproducible with no atomics, no
+// fences and no extra launches.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "tg_internal.h"
 
 namespace tg {
 namespace {
 
+constexpr int kWaves = kVecThreads / 64;
+
+// Sum over the block in a fixed order: butterfly within each wave (every lane
+// ends with the same bits: a + b == b + a), then the wave sums in index order.
 __device__ __forceinline__ double block_sum(double v, double *sh) {
-    sh[threadIdx.x] = v;
-    __syncthreads();
 #pragma unroll
-    for (int s = kVecThreads / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    const double r = sh[0];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) r += sh[w];
     __syncthreads();
     return r;
 }
 
-// Sum of partials[0..n) (stride `stride`) in a fixed order; same value in every block.
-__device__ __forceinline__ double sum_partials(const double *__restrict__ partials, int n, int stride, double *sh) {
-    double v = 0.0;
-    for (int i = threadIdx.x; i < n; i += kVecThreads) v += partials[(size_t)i * stride];
-    return block_sum(v, sh);
+// Sum of partials[0 .. n), n <= kVecThreads, identical in every block.
+__device__ __forceinline__ double sum_partials(const double *__restrict__ partials, int n, double *sh) {
+    return block_sum((int)threadIdx.x < n ? partials[threadIdx.x] : 0.0, sh);
 }
 
+// Partials layout: [PQ | RZ0 | RZ1 | RR | BB] blocks of kMaxGrid doubles.
+__device__ __forceinline__ double *part(double *base, int which) { return base + (size_t)which * kMaxGrid; }
+constexpr int kPQ = 0, kRZ0 = 1, kRR = 3, kBB = 4;
+
 template <typename T>
-__global__ __launch_bounds__(256) void dirichlet_kernel(int n, const int32_t *__restrict__ row_ptr,
+__global__ __launch_bounds__(256) void dirichlet_kernel(int nrows, const int32_t *__restrict__ rows,
+                                                        const int32_t *__restrict__ row_ptr,
                                                         const int32_t *__restrict__ col_idx,
                                                         const uint8_t *__restrict__ constrained, T *__restrict__ values,
                                                         T *__restrict__ rhs, const T *__restrict__ g) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nrows) return;
+    const int i = rows[k];
     const int p0 = row_ptr[i], p1 = row_ptr[i + 1];
     if (constrained[i]) {
         for (int p = p0; p < p1; ++p) values[p] = (col_idx[p] == i) ? (T)1 : (T)0;
@@ -57,14 +72,19 @@ __global__ __launch_bounds__(256) void dirichlet_kernel(int n, const int32_t *__
     }
 }
 
-// Row i of K x, accumulated in FP64 by a group of G lanes in a fixed pattern.
-template <typename T, int G>
+// Row i of K y, accumulated in FP64 by a group of G lanes in a fixed pattern,
+// where y_j = z_j + beta p_j if DIR, else y_j = x_j.
+template <typename T, int G, bool DIR>
 __device__ __forceinline__ double row_dot(int i, int lane, const int32_t *__restrict__ row_ptr,
                                           const int32_t *__restrict__ col_idx, const T *__restrict__ values,
-                                          const T *__restrict__ x) {
+                                          const T *__restrict__ x, const T *__restrict__ p, T beta) {
     const int p0 = row_ptr[i], p1 = row_ptr[i + 1];
     double acc = 0.0;
-    for (int p = p0 + lane; p < p1; p += G) acc += (double)values[p] * (double)x[col_idx[p]];
+    for (int q = p0 + lane; q < p1; q += G) {
+        const int j = col_idx[q];
+        const T y = DIR ? x[j] + beta * p[j] : x[j];
+        acc += (double)values[q] * (double)y;
+    }
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
     return acc;
@@ -77,13 +97,13 @@ __global__ __launch_bounds__(256) void spmv_kernel(int n, const int32_t *__restr
     const int lane = threadIdx.x % G;
     const int rows_per_grid = gridDim.x * (256 / G);
     for (int i = blockIdx.x * (256 / G) + threadIdx.x / G; i < n; i += rows_per_grid) {
-        const double v = row_dot<T, G>(i, lane, row_ptr, col_idx, values, x);
+        const double v = row_dot<T, G, false>(i, lane, row_ptr, col_idx, values, x, nullptr, (T)0);
         if (lane == 0) y[i] = (T)v;
     }
 }
 
 // ---------------------------------------------------------------- PCG kernels
-// Workspace layout (T elements of n each): r, z, p, q, dinv.
+// Workspace (T elements of n each): r, z, pA, pB, q, dinv.
 
 template <typename T>
 __global__ __launch_bounds__(kVecThreads) void pcg_init_kernel(int n, const T *__restrict__ b, T *__restrict__ x,
@@ -92,7 +112,7 @@ __global__ __launch_bounds__(kVecThreads) void pcg_init_kernel(int n, const T *_
                                                                const T *__restrict__ values,
                                                                const int32_t *__restrict__ diag_pos,
                                                                double *__restrict__ partials) {
-    __shared__ double sh[kVecThreads];
+    __shared__ double sh[kWaves];
     double rz = 0.0, bb = 0.0;
     for (int i = blockIdx.x * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads) {
         const T bi = b[i];
@@ -101,7 +121,7 @@ __global__ __launch_bounds__(kVecThreads) void pcg_init_kernel(int n, const T *_
         x[i] = (T)0;
         r[i] = bi;
         z[i] = zi;
-        p[i] = zi;
+        p[i] = (T)0;
         dinv[i] = di;
         rz += (double)bi * (double)zi;
         bb += (double)bi * (double)bi;
@@ -109,160 +129,149 @@ __global__ __launch_bounds__(kVecThreads) void pcg_init_kernel(int n, const T *_
     rz = block_sum(rz, sh);
     bb = block_sum(bb, sh);
     if (threadIdx.x == 0) {
-        partials[blockIdx.x] = rz;
-        partials[kMaxPartials + blockIdx.x] = bb;
+        part(partials, kRZ0)[blockIdx.x] = rz;
+        part(partials, kBB)[blockIdx.x] = bb;
     }
 }
 
-__global__ __launch_bounds__(kVecThreads) void pcg_init_finish_kernel(int nparts, const double *__restrict__ partials,
-                                                                      PcgState *__restrict__ st, double rtol2) {
-    __shared__ double sh[kVecThreads];
-    const double rz = sum_partials(partials, nparts, 1, sh);
-    const double bb = sum_partials(partials + kMaxPartials, nparts, 1, sh);
-    if (threadIdx.x == 0) {
-        st->rz[0] = rz;
-        st->rz[1] = 0.0;
-        st->bb = bb;
-        st->rr = bb;
-        st->tol2 = rtol2 * bb;
-        st->done = (bb == 0.0) ? 1 : 0;
-        st->iters = 0;
-    }
-}
-
-// q = K p and a partial of p.q per block.
-template <typename T, int G>
-__global__ __launch_bounds__(256) void pcg_spmv_kernel(int n, const int32_t *__restrict__ row_ptr,
-                                                       const int32_t *__restrict__ col_idx,
-                                                       const T *__restrict__ values, const T *__restrict__ p,
-                                                       T *__restrict__ q, double *__restrict__ partials,
-                                                       const PcgState *__restrict__ st) {
-    __shared__ double sh[kVecThreads];
+// Stop test on the residual of the last update, then p_new = z + beta p_old,
+// q = K p_new and partials of p.q.  CHECK_ONLY launches stop after the test.
+// n_prev: number of partials written by the previous kernel (init or update).
+template <typename T, int G, bool CHECK_ONLY>
+__global__ __launch_bounds__(kVecThreads) void pcg_spmv_kernel(int n, const int32_t *__restrict__ row_ptr,
+                                                               const int32_t *__restrict__ col_idx,
+                                                               const T *__restrict__ values, const T *__restrict__ z,
+                                                               const T *__restrict__ p_old, T *__restrict__ p_new,
+                                                               T *__restrict__ q, double *__restrict__ partials,
+                                                               PcgState *__restrict__ st, int it, int n_prev,
+                                                               double rtol2) {
+    __shared__ double sh[kWaves];
     if (st->done) return;  // written only by earlier launches: the same value for every wave
+    double tol2, rr;
+    if (it == 0) {
+        const double bb = sum_partials(part(partials, kBB), n_prev, sh);
+        tol2 = rtol2 * bb;
+        rr = bb;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->bb = bb;
+            st->tol2 = tol2;
+        }
+    } else {
+        tol2 = st->tol2;
+        rr = sum_partials(part(partials, kRR), n_prev, sh);
+    }
+    if (rr <= tol2) {  // the same decision in every block
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->done = 1;
+            st->iters = it;
+        }
+        return;
+    }
+    if (CHECK_ONLY) return;
+    T beta = (T)0;
+    if (it > 0) {
+        const double rz = sum_partials(part(partials, kRZ0 + (it & 1)), n_prev, sh);
+        const double rz_prev = sum_partials(part(partials, kRZ0 + ((it + 1) & 1)), n_prev, sh);
+        beta = (T)(rz / rz_prev);
+    }
     const int lane = threadIdx.x % G;
-    const int rows_per_grid = gridDim.x * (256 / G);
+    const int rows_per_grid = gridDim.x * (kVecThreads / G);
     double pq = 0.0;
-    for (int i = blockIdx.x * (256 / G) + threadIdx.x / G; i < n; i += rows_per_grid) {
-        const double v = row_dot<T, G>(i, lane, row_ptr, col_idx, values, p);
+    for (int i = blockIdx.x * (kVecThreads / G) + threadIdx.x / G; i < n; i += rows_per_grid) {
+        const double v = row_dot<T, G, true>(i, lane, row_ptr, col_idx, values, z, p_old, beta);
         if (lane == 0) {
+            const T pi = z[i] + beta * p_old[i];
             const T qi = (T)v;
+            p_new[i] = pi;
             q[i] = qi;
-            pq += (double)p[i] * (double)qi;
+            pq += (double)pi * (double)qi;
         }
     }
     pq = block_sum(pq, sh);
-    if (threadIdx.x == 0) partials[2 * kMaxPartials + blockIdx.x] = pq;
+    if (threadIdx.x == 0) part(partials, kPQ)[blockIdx.x] = pq;
 }
 
-// alpha = rz / pq; x += alpha p; r -= alpha q; z = D^{-1} r; partials of r.z and r.r
+// alpha = r.z / p.q; x += alpha p; r -= alpha q; z = D^{-1} r; partials of r.z (next buffer) and r.r
 template <typename T>
-__global__ __launch_bounds__(kVecThreads) void pcg_update_xr_kernel(int n, int n_pq, T *__restrict__ x,
-                                                                    T *__restrict__ r, T *__restrict__ z,
-                                                                    const T *__restrict__ p, const T *__restrict__ q,
-                                                                    const T *__restrict__ dinv,
-                                                                    double *__restrict__ partials,
-                                                                    const PcgState *__restrict__ st, int it) {
-    __shared__ double sh[kVecThreads];
-    if (st->done) return;  // written only by earlier launches: the same value for every wave
-    const double pq = sum_partials(partials + 2 * kMaxPartials, n_pq, 1, sh);
-    const double alpha = st->rz[it & 1] / pq;
-    const T a = (T)alpha;
-    double rz = 0.0, rr = 0.0;
+__global__ __launch_bounds__(kVecThreads) void pcg_update_kernel(int n, T *__restrict__ x, T *__restrict__ r,
+                                                                 T *__restrict__ z, const T *__restrict__ p,
+                                                                 const T *__restrict__ q, const T *__restrict__ dinv,
+                                                                 double *__restrict__ partials,
+                                                                 const PcgState *__restrict__ st, int it,
+                                                                 int n_pq, int n_rz) {
+    __shared__ double sh[kWaves];
+    if (st->done) return;  // written only by earlier launches
+    const double pq = sum_partials(part(partials, kPQ), n_pq, sh);
+    const double rz = sum_partials(part(partials, kRZ0 + (it & 1)), n_rz, sh);
+    const T a = (T)(rz / pq);
+    double rzn = 0.0, rr = 0.0;
     for (int i = blockIdx.x * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads) {
         const T ri = r[i] - a * q[i];
         x[i] += a * p[i];
         const T zi = dinv[i] * ri;
         r[i] = ri;
         z[i] = zi;
-        rz += (double)ri * (double)zi;
+        rzn += (double)ri * (double)zi;
         rr += (double)ri * (double)ri;
     }
-    rz = block_sum(rz, sh);
+    rzn = block_sum(rzn, sh);
     rr = block_sum(rr, sh);
     if (threadIdx.x == 0) {
-        partials[blockIdx.x] = rz;
-        partials[kMaxPartials + blockIdx.x] = rr;
+        part(partials, kRZ0 + ((it + 1) & 1))[blockIdx.x] = rzn;
+        part(partials, kRR)[blockIdx.x] = rr;
     }
 }
 
-// beta = rz_new / rz; p = z + beta p; stop test on ||r||^2 <= rtol^2 ||b||^2.
-// `done` is not read here by the grid: every block takes the stop decision
-// from the same partials.  Only thread 0 of block 0 reads and writes `done`
-// and `iters`, so no block races with a writer inside this launch.  Once
-// converged, pcg_update_xr skips and leaves the partials of the converged
-// iteration in place, so later launches take the same decision again.
-template <typename T>
-__global__ __launch_bounds__(kVecThreads) void pcg_update_p_kernel(int n, int nparts, const T *__restrict__ z,
-                                                                   T *__restrict__ p,
-                                                                   const double *__restrict__ partials,
-                                                                   PcgState *__restrict__ st, int it) {
-    __shared__ double sh[kVecThreads];
-    const double rz_new = sum_partials(partials, nparts, 1, sh);
-    const double rr = sum_partials(partials + kMaxPartials, nparts, 1, sh);
-    if (rr <= st->tol2) {
-        if (blockIdx.x == 0 && threadIdx.x == 0 && !st->done) {
-            st->rr = rr;
-            st->done = 1;
-            st->iters = it + 1;
-        }
-        return;
-    }
-    const T beta = (T)(rz_new / st->rz[it & 1]);
-    for (int i = blockIdx.x * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads) p[i] = z[i] + beta * p[i];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->rz[(it + 1) & 1] = rz_new;
-        st->rr = rr;
-    }
-}
-
-// partials of ||b - K x||^2
+// per-block partials of ||b - K x||^2 (summed on the host in index order)
 template <typename T, int G>
-__global__ __launch_bounds__(256) void residual_kernel(int n, const int32_t *__restrict__ row_ptr,
-                                                       const int32_t *__restrict__ col_idx,
-                                                       const T *__restrict__ values, const T *__restrict__ x,
-                                                       const T *__restrict__ b, double *__restrict__ partials) {
-    __shared__ double sh[kVecThreads];
+__global__ __launch_bounds__(kVecThreads) void residual_kernel(int n, const int32_t *__restrict__ row_ptr,
+                                                               const int32_t *__restrict__ col_idx,
+                                                               const T *__restrict__ values, const T *__restrict__ x,
+                                                               const T *__restrict__ b, double *__restrict__ partials) {
+    __shared__ double sh[kWaves];
     const int lane = threadIdx.x % G;
-    const int rows_per_grid = gridDim.x * (256 / G);
+    const int rows_per_grid = gridDim.x * (kVecThreads / G);
     double acc = 0.0;
-    for (int i = blockIdx.x * (256 / G) + threadIdx.x / G; i < n; i += rows_per_grid) {
-        const double v = row_dot<T, G>(i, lane, row_ptr, col_idx, values, x);
+    for (int i = blockIdx.x * (kVecThreads / G) + threadIdx.x / G; i < n; i += rows_per_grid) {
+        const double v = row_dot<T, G, false>(i, lane, row_ptr, col_idx, values, x, nullptr, (T)0);
         if (lane == 0) {
             const double ri = (double)b[i] - v;
             acc += ri * ri;
         }
     }
     acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+    if (threadIdx.x == 0) part(partials, kRR)[blockIdx.x] = acc;
 }
 
-__global__ __launch_bounds__(kVecThreads) void residual_finish_kernel(int nparts, const double *__restrict__ partials,
-                                                                      PcgState *__restrict__ st) {
-    __shared__ double sh[kVecThreads];
-    const double rr = sum_partials(partials, nparts, 1, sh);
-    if (threadIdx.x == 0) st->rr = rr;  // true residual, read back by the host
+int vec_blocks(int64_t n) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxGrid, (n + kVecThreads - 1) / kVecThreads));
 }
-
-int vec_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxPartials, (n + 255) / 256)); }
 
 template <int G>
 int spmv_blocks(int64_t n) {
+    const int64_t rows_per_block = kVecThreads / G;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxGrid, (n + rows_per_block - 1) / rows_per_block));
+}
+
+template <int G>
+int spmv_blocks_256(int64_t n) {
     const int64_t rows_per_block = 256 / G;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxPartials, (n + rows_per_block - 1) / rows_per_block));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(8192, (n + rows_per_block - 1) / rows_per_block));
 }
 
 template <typename T>
 hipError_t launch_dirichlet_t(const tg_pattern &pt, void *values, void *rhs, const void *g, hipStream_t s) {
-    const int n = (int)pt.host.n_dofs;
-    hipLaunchKernelGGL(dirichlet_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, pt.dev.row_ptr,
-                       pt.dev.col_idx, pt.dev.constrained, (T *)values, (T *)rhs, (const T *)g);
+    const int nr = (int)pt.dev.n_dir_rows;
+    if (nr == 0) return hipSuccess;
+    hipLaunchKernelGGL(dirichlet_kernel<T>, dim3((nr + 255) / 256), dim3(256), 0, s, nr, pt.dev.dir_rows,
+                       pt.dev.row_ptr, pt.dev.col_idx, pt.dev.constrained, (T *)values, (T *)rhs, (const T *)g);
     return hipGetLastError();
 }
 
 template <typename T, int G>
 hipError_t launch_spmv_t(const tg_pattern &pt, const void *values, const void *x, void *y, hipStream_t s) {
     const int n = (int)pt.host.n_dofs;
-    hipLaunchKernelGGL((spmv_kernel<T, G>), dim3(spmv_blocks<G>(n)), dim3(256), 0, s, n, pt.dev.row_ptr,
+    hipLaunchKernelGGL((spmv_kernel<T, G>), dim3(spmv_blocks_256<G>(n)), dim3(256), 0, s, n, pt.dev.row_ptr,
                        pt.dev.col_idx, (const T *)values, (const T *)x, (T *)y);
     return hipGetLastError();
 }
@@ -284,58 +293,64 @@ tg_status run_pcg_t(const tg_pattern &pt, const T *values, const T *b, T *x, dou
     const int n = (int)pt.host.n_dofs;
     T *r = (T *)d.work;
     T *z = r + n;
-    T *p = z + n;
-    T *q = p + n;
+    T *pA = z + n;
+    T *pB = pA + n;
+    T *q = pB + n;
     T *dinv = q + n;
     const int nb = vec_blocks(n);
     const int ns = spmv_blocks<G>(n);
+    const double rtol2 = rtol * rtol;
     hipError_t err;
-#define TG_CHECK(call)                               \
-    do {                                             \
-        err = (call);                                \
-        if (err != hipSuccess) {                     \
-            msg = hipGetErrorString(err);            \
-            return TG_E_HIP;                         \
-        }                                            \
+#define TG_CHECK(call)                    \
+    do {                                  \
+        err = (call);                     \
+        if (err != hipSuccess) {          \
+            msg = hipGetErrorString(err); \
+            return TG_E_HIP;              \
+        }                                 \
     } while (0)
-    hipLaunchKernelGGL(pcg_init_kernel<T>, dim3(nb), dim3(kVecThreads), 0, s, n, b, x, r, z, p, dinv, values,
+    // reset the host-visible state (done = 0) with a copy, not a memset: a caller may capture this stream
+    d.host_state->done = 0;
+    d.host_state->iters = 0;
+    TG_CHECK(hipMemcpyAsync(d.state, d.host_state, sizeof(PcgState), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(pcg_init_kernel<T>, dim3(nb), dim3(kVecThreads), 0, s, n, b, x, r, z, pA, dinv, values,
                        d.diag_pos, d.partials);
-    hipLaunchKernelGGL(pcg_init_finish_kernel, dim3(1), dim3(kVecThreads), 0, s, nb, d.partials, d.state,
-                       rtol * rtol);
     TG_CHECK(hipGetLastError());
     int it = 0;
     bool done = false;
     while (it < max_iter && !done) {
-        hipLaunchKernelGGL((pcg_spmv_kernel<T, G>), dim3(ns), dim3(256), 0, s, n, d.row_ptr, d.col_idx, values, p,
-                           q, d.partials, d.state);
-        hipLaunchKernelGGL(pcg_update_xr_kernel<T>, dim3(nb), dim3(kVecThreads), 0, s, n, ns, x, r, z, p, q, dinv,
-                           d.partials, d.state, it);
-        hipLaunchKernelGGL(pcg_update_p_kernel<T>, dim3(nb), dim3(kVecThreads), 0, s, n, nb, z, p, d.partials,
-                           d.state, it);
+        T *p_old = (it & 1) ? pB : pA;
+        T *p_new = (it & 1) ? pA : pB;
+        hipLaunchKernelGGL((pcg_spmv_kernel<T, G, false>), dim3(ns), dim3(kVecThreads), 0, s, n, d.row_ptr,
+                           d.col_idx, values, z, p_old, p_new, q, d.partials, d.state, it, nb, rtol2);
+        hipLaunchKernelGGL(pcg_update_kernel<T>, dim3(nb), dim3(kVecThreads), 0, s, n, x, r, z, p_new, q, dinv,
+                           d.partials, d.state, it, ns, nb);
         TG_CHECK(hipGetLastError());
         ++it;
-        if (it % check_every == 0 || it == max_iter) {
+        if (it % check_every == 0) {
             TG_CHECK(hipMemcpyAsync(d.host_state, d.state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
             TG_CHECK(hipStreamSynchronize(s));
             done = d.host_state->done != 0;
         }
     }
-    if (!done) {  // converged at initialisation (b = 0) is caught here too
-        TG_CHECK(hipMemcpyAsync(d.host_state, d.state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-        TG_CHECK(hipStreamSynchronize(s));
-        done = d.host_state->done != 0;
-    }
-    const int32_t its = done ? d.host_state->iters : max_iter;
-    const double bb = d.host_state->bb;
-    hipLaunchKernelGGL((residual_kernel<T, G>), dim3(ns), dim3(256), 0, s, n, d.row_ptr, d.col_idx, values, x, b,
-                       d.partials);
-    hipLaunchKernelGGL(residual_finish_kernel, dim3(1), dim3(kVecThreads), 0, s, ns, d.partials, d.state);
+    // stop test on the last update (sets done/iters if it converged)
+    hipLaunchKernelGGL((pcg_spmv_kernel<T, G, true>), dim3(1), dim3(kVecThreads), 0, s, n, d.row_ptr, d.col_idx,
+                       values, z, pA, pB, q, d.partials, d.state, it, nb, rtol2);
+    hipLaunchKernelGGL((residual_kernel<T, G>), dim3(ns), dim3(kVecThreads), 0, s, n, d.row_ptr, d.col_idx, values,
+                       x, b, d.partials);
     TG_CHECK(hipGetLastError());
+    std::vector<double> host_parts(ns);
     TG_CHECK(hipMemcpyAsync(d.host_state, d.state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    TG_CHECK(hipMemcpyAsync(host_parts.data(), d.partials + (size_t)kRR * kMaxGrid, sizeof(double) * ns,
+                            hipMemcpyDeviceToHost, s));
     TG_CHECK(hipStreamSynchronize(s));
 #undef TG_CHECK
-    if (iters) *iters = its;
-    if (relres) *relres = bb > 0.0 ? std::sqrt(d.host_state->rr / bb) : std::sqrt(d.host_state->rr);
+    done = d.host_state->done != 0;
+    double rr = 0.0;
+    for (double v : host_parts) rr += v;
+    const double bb = d.host_state->bb;
+    if (iters) *iters = done ? d.host_state->iters : it;
+    if (relres) *relres = bb > 0.0 ? std::sqrt(rr / bb) : std::sqrt(rr);
     if (!done) {
         msg = "PCG did not reach rtol within max_iter iterations";
         return TG_E_NOCONV;

@@ -48,8 +48,10 @@ def _pair_of_slot(r, k):
     seg_len = np.diff(r["seg_ptr"])
     slot_entry = np.repeat(np.arange(len(seg_len)), seg_len)
     slot = r["slot"].astype(np.int64)
-    pair = blk_first_pair[row_blk[node_of_entry[slot_entry]]] + slot // k
-    return pair, slot % k
+    blk = row_blk[node_of_entry[slot_entry]]
+    blk_pairs = (r["inc_ptr"][r["blk_row"][1:]] - r["inc_ptr"][r["blk_row"][:-1]])[blk]
+    pair = blk_first_pair[blk] + slot % blk_pairs
+    return pair, slot // blk_pairs
 
 
 @pytest.mark.parametrize("dim,n", [(2, 1), (2, 7), (3, 1), (3, 4)])
