@@ -61,8 +61,11 @@ typedef enum { TG_F64 = 0, TG_F32 = 1 } tg_dtype;
  *   TG_ELASTICITY K_(i,c),(j,c') = int lambda div(phi_j e_c') div(phi_i e_c)
  *                 + 2 mu eps(phi_j e_c') : eps(phi_i e_c),  F_(i,c) = int b_c phi_i
  *                 (P2 tetrahedra, Hooke's law of Sec. B.1.1); DoF = 3*node + c
+ *   TG_MASS_LAPLACE  A_ij = M_ij + int c grad(phi_j).grad(phi_i), F_i = int f phi_i
+ *                 (P1, scalar): the matrix M + dt K(a) of an implicit Euler step
+ *                 of the method-of-lines system of SM A.1 (pass c = dt a)
  */
-typedef enum { TG_LAPLACE = 0, TG_MASS = 1, TG_ELASTICITY = 2 } tg_form;
+typedef enum { TG_LAPLACE = 0, TG_MASS = 1, TG_ELASTICITY = 2, TG_MASS_LAPLACE = 3 } tg_form;
 
 typedef struct tg_pattern tg_pattern; /* opaque, library-owned */
 
@@ -170,10 +173,10 @@ void tg_pattern_destroy(tg_pattern *p);
  *   dtype    : value type of coef, load, values and rhs.  Geometry (J, det J,
  *              J^{-1}) is always computed in FP64.
  *   d_coords : device [n_vertices][dim] FP64 vertex coordinates.
- *   d_coef   : LAPLACE: device [n_elements] coefficient a per element;
+ *   d_coef   : LAPLACE, MASS_LAPLACE: device [n_elements] coefficient per element;
  *              ELASTICITY: device [2][n_elements] (lambda row, then mu row);
  *              MASS: ignored (may be NULL).
- *   d_load   : LAPLACE: device [n_elements] source f per element;
+ *   d_load   : LAPLACE, MASS_LAPLACE: device [n_elements] source f per element;
  *              ELASTICITY: device [n_elements][3] body force per element;
  *              may be NULL (then d_rhs is not written).  MASS: ignored.
  *   d_values : device [nnz] output values, CSR order of tg_pattern_copy_csr.
@@ -190,6 +193,20 @@ void tg_pattern_destroy(tg_pattern *p);
  */
 tg_status tg_assemble(const tg_pattern *p, tg_form form, tg_dtype dtype, const double *d_coords, const void *d_coef,
                       const void *d_load, void *d_values, void *d_rhs, int32_t *d_status, void *stream);
+
+/*
+ * tg_assemble for nbatch coefficient sets on one pattern in one launch
+ * (LAPLACE and MASS_LAPLACE; many right-hand sides / coefficient fields on a
+ * fixed mesh, cf. the batched data generation of Sec. B.2).  The geometry and
+ * the routing are read once; member m reads d_coef + m*E and d_load + m*E
+ * (both [nbatch][n_elements]) and writes d_values + m*nnz and d_rhs + m*n_dofs
+ * ([nbatch][nnz] and [nbatch][n_dofs]).  Each member is bitwise equal to a
+ * single tg_assemble of its coefficients.  nbatch >= 1; other arguments and
+ * errors as tg_assemble.
+ */
+tg_status tg_assemble_batched(const tg_pattern *p, tg_form form, tg_dtype dtype, int32_t nbatch,
+                              const double *d_coords, const void *d_coef, const void *d_load, void *d_values,
+                              void *d_rhs, int32_t *d_status, void *stream);
 
 /*
  * Impose Dirichlet conditions on an assembled system by symmetric

@@ -33,7 +33,7 @@ _lib = ctypes.CDLL(_LIB_PATH)
 
 TG_OK, TG_E_ARG, TG_E_DEGENERATE, TG_E_NONFINITE, TG_E_NOMEM, TG_E_HIP, TG_E_NOCONV, TG_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 F64, F32 = 0, 1
-LAPLACE, MASS, ELASTICITY = 0, 1, 2
+LAPLACE, MASS, ELASTICITY, MASS_LAPLACE = 0, 1, 2, 3
 BOUNDARY_ALL = -1
 STATUS_CLEAN = 2 ** 31 - 1
 PATTERN_HOST_ONLY = 1
@@ -65,6 +65,8 @@ _SIGS = {
                                                ctypes.POINTER(ctypes.c_uint16)]),
     "tg_pattern_destroy": (None, [_vp]),
     "tg_assemble": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "tg_assemble_batched": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                           _vp]),
     "tg_apply_dirichlet": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "tg_spmv": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "tg_pcg": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, ctypes.c_double, _i32, _i32, _i32p,
@@ -250,7 +252,7 @@ def assemble(pattern: Pattern, form: int, coords, coef=None, load=None, dtype=No
     tdt = _torch_dtype(code)
     E = pattern.n_elements
     cp = _dev(coords, torch.float64, (pattern.n_vertices, pattern.dim), "coords")
-    if form == LAPLACE:
+    if form in (LAPLACE, MASS_LAPLACE):
         coef_p = _dev(coef, tdt, (E,), "coef")
         load_p = _dev(load, tdt, (E,), "load") if load is not None else None
     elif form == ELASTICITY:
@@ -271,6 +273,38 @@ def assemble(pattern: Pattern, form: int, coords, coef=None, load=None, dtype=No
     sp = _dev(status, torch.int32, (1,), "status") if status is not None else None
     _check(_lib.tg_assemble(pattern.handle, form, code, cp, coef_p, load_p, vp, rp, sp, _stream_handle(stream)))
     return values, (rhs if want_rhs else None)
+
+
+def assemble_batched(pattern: Pattern, form: int, coords, coef, load=None, values=None, rhs=None, status=None,
+                     stream=None):
+    """Assemble B coefficient sets in one launch (tg_assemble_batched).
+
+    coef, load: [B, E] tensors of one dtype (load may be None).  Returns
+    (values [B, nnz], rhs [B, n_dofs] or None); member b equals assemble() of
+    coef[b], load[b] bitwise.
+    """
+    torch = _torch()
+    if form not in (LAPLACE, MASS_LAPLACE):
+        raise ValueError("batched assembly supports LAPLACE and MASS_LAPLACE")
+    code = _dtype_code(coef.dtype)
+    tdt = _torch_dtype(code)
+    if coef.dim() != 2:
+        raise ValueError("coef must be [B, E]")
+    B = coef.shape[0]
+    E = pattern.n_elements
+    cp = _dev(coords, torch.float64, (pattern.n_vertices, pattern.dim), "coords")
+    coef_p = _dev(coef, tdt, (B, E), "coef")
+    load_p = _dev(load, tdt, (B, E), "load") if load is not None else None
+    if values is None:
+        values = torch.empty(B, pattern.nnz, dtype=tdt, device=coords.device)
+    vp = _dev(values, tdt, (B, pattern.nnz), "values")
+    if load_p is not None and rhs is None:
+        rhs = torch.empty(B, pattern.n_dofs, dtype=tdt, device=coords.device)
+    rp = _dev(rhs, tdt, (B, pattern.n_dofs), "rhs") if load_p is not None else None
+    sp = _dev(status, torch.int32, (1,), "status") if status is not None else None
+    _check(_lib.tg_assemble_batched(pattern.handle, form, code, B, cp, coef_p, load_p, vp, rp, sp,
+                                    _stream_handle(stream)))
+    return values, (rhs if load_p is not None else None)
 
 
 def new_status(device="cuda"):

@@ -92,6 +92,9 @@ tg_status create_device(tg_pattern &pt) {
     int g = 4;
     while (g < 32 && g < mean_row / 2) g *= 2;
     d.spmv_group = g;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, pt.device) == hipSuccess && prop.multiProcessorCount > 0)
+        d.n_cu = prop.multiProcessorCount;
     return TG_OK;
 }
 
@@ -204,28 +207,32 @@ void tg_pattern_destroy(tg_pattern *p) {
     delete p;
 }
 
-tg_status tg_assemble(const tg_pattern *p, tg_form form, tg_dtype dtype, const double *d_coords, const void *d_coef,
-                      const void *d_load, void *d_values, void *d_rhs, int32_t *d_status, void *stream) {
+static tg_status assemble_impl(const tg_pattern *p, tg_form form, tg_dtype dtype, int32_t nbatch,
+                               const double *d_coords, const void *d_coef, const void *d_load, void *d_values,
+                               void *d_rhs, int32_t *d_status, void *stream) {
     tg_status st = check_device_pattern(p);
     if (st != TG_OK) return st;
     if (!valid_dtype(dtype)) return fail(TG_E_ARG, "invalid dtype");
     if (!d_coords || !d_values) return fail(TG_E_ARG, "d_coords and d_values are required");
+    if (nbatch < 1) return fail(TG_E_ARG, "nbatch must be >= 1");
     const tg::HostPattern &h = p->host;
     const bool scalar_p1 = (h.order == 1 && h.ncomp == 1);
     // the kernels address every array with 32-bit byte offsets
-    const uint64_t elt = dtype == TG_F64 ? 8 : 4, lim = (uint64_t)1 << 32;
-    if ((uint64_t)h.nnz * elt >= lim || (uint64_t)h.nv * h.dim * 8 >= lim || (uint64_t)h.E * 5 * elt >= lim ||
-        (uint64_t)h.E * h.k * h.k * 2 >= lim)
-        return fail(TG_E_ARG, "an array of this mesh exceeds 4 GiB, beyond the kernels' 32-bit offsets");
+    const uint64_t elt = dtype == TG_F64 ? 8 : 4, lim = (uint64_t)1 << 32, nb = (uint64_t)nbatch;
+    if (nb * h.nnz * elt >= lim || (uint64_t)h.nv * h.dim * 8 >= lim || nb * h.E * 5 * elt >= lim ||
+        nb * h.n_dofs * elt >= lim || (uint64_t)h.E * h.k * h.k * 2 >= lim)
+        return fail(TG_E_ARG, "an array of this call exceeds 4 GiB, beyond the kernels' 32-bit offsets");
     hipError_t e;
-    if (form == TG_LAPLACE || form == TG_MASS) {
-        if (!scalar_p1) return fail(TG_E_ARG, "LAPLACE and MASS need a P1 scalar pattern (order 1, ncomp 1)");
-        if (form == TG_LAPLACE && !d_coef) return fail(TG_E_ARG, "LAPLACE needs d_coef");
-        e = tg::launch_assemble_p1(*p, form, dtype, d_coords, d_coef, form == TG_LAPLACE ? d_load : nullptr,
+    if (form == TG_LAPLACE || form == TG_MASS || form == TG_MASS_LAPLACE) {
+        if (!scalar_p1) return fail(TG_E_ARG, "LAPLACE, MASS and MASS_LAPLACE need a P1 scalar pattern (order 1, ncomp 1)");
+        if (form != TG_MASS && !d_coef) return fail(TG_E_ARG, "this form needs d_coef");
+        if (form == TG_MASS && nbatch != 1) return fail(TG_E_ARG, "MASS has no coefficients to batch");
+        e = tg::launch_assemble_p1(*p, form, dtype, nbatch, d_coords, d_coef, form == TG_MASS ? nullptr : d_load,
                                    d_values, d_rhs, d_status, (hipStream_t)stream);
     } else if (form == TG_ELASTICITY) {
         if (h.order != 2 || h.ncomp != 3) return fail(TG_E_ARG, "ELASTICITY needs a P2 vector pattern (3, 2, 3)");
         if (!d_coef) return fail(TG_E_ARG, "ELASTICITY needs d_coef (lambda, mu)");
+        if (nbatch != 1) return fail(TG_E_ARG, "batched ELASTICITY is not supported");
         e = tg::launch_assemble_p2(*p, dtype, d_coords, d_coef, d_load, d_values, d_rhs, d_status,
                                    (hipStream_t)stream);
     } else {
@@ -233,6 +240,19 @@ tg_status tg_assemble(const tg_pattern *p, tg_form form, tg_dtype dtype, const d
     }
     if (e != hipSuccess) return fail(TG_E_HIP, std::string("assembly launch failed: ") + hipGetErrorString(e));
     return ok();
+}
+
+tg_status tg_assemble(const tg_pattern *p, tg_form form, tg_dtype dtype, const double *d_coords, const void *d_coef,
+                      const void *d_load, void *d_values, void *d_rhs, int32_t *d_status, void *stream) {
+    return assemble_impl(p, form, dtype, 1, d_coords, d_coef, d_load, d_values, d_rhs, d_status, stream);
+}
+
+tg_status tg_assemble_batched(const tg_pattern *p, tg_form form, tg_dtype dtype, int32_t nbatch,
+                              const double *d_coords, const void *d_coef, const void *d_load, void *d_values,
+                              void *d_rhs, int32_t *d_status, void *stream) {
+    if (form != TG_LAPLACE && form != TG_MASS_LAPLACE)
+        return fail(TG_E_ARG, "tg_assemble_batched supports LAPLACE and MASS_LAPLACE");
+    return assemble_impl(p, form, dtype, nbatch, d_coords, d_coef, d_load, d_values, d_rhs, d_status, stream);
 }
 
 tg_status tg_apply_dirichlet(const tg_pattern *p, tg_dtype dtype, void *d_values, void *d_rhs, const void *d_g,

@@ -246,13 +246,86 @@ __device__ __forceinline__ void select_row(const double (&C)[D + 1][D], int a, d
     }
 }
 
-template <int D, typename T, bool MASS, bool LOAD>
+// P1 scalar forms handled by one kernel.
+enum P1Form { kLaplace = 0, kMass = 1, kMassLaplace = 2 };
+
+// Geometry of the pair's element, computed once and reused for every
+// coefficient set of a batched call.
+template <int D>
+struct P1Geom {
+    double C[D + 1][D];  // cofactor rows (det J grad(lambda_b))
+    double adet;         // |det J|
+    bool bad;            // numerically singular
+};
+
+template <int D>
+__device__ __forceinline__ void p1_geometry(const double (&x)[D + 1][D], P1Geom<D> &g) {
+    const double det = p1_cofactors<D>(x, g.C);
+    g.adet = fabs(det);
+    g.bad = numerically_singular<D>(x, det);
+}
+
+// Row a of the local matrix and entry a of the local load of one pair for
+// coefficient c and source f:
+//   Laplace:      K_ab = c (C_a . C_b) / (d! |det J|)       (1-point rule, exact)
+//   Mass:         M_ab = sum_q w_q |det J| phi_a(x_q) phi_b(x_q)  (degree-2 rule)
+//   MassLaplace:  M_ab + K_ab
+// F_a = f |det J| / (d! (d+1)) (centroid rule, exact for constant f).
+template <int D, typename T, int FORM>
+__device__ __forceinline__ void p1_row(const P1Geom<D> &g, int a, double c, double f, T (&row)[D + 1], T &fa) {
+    constexpr int K = D + 1;
+    T kr[K];
+#pragma unroll
+    for (int b = 0; b < K; ++b) kr[b] = (T)0;
+    if constexpr (FORM != kMass) {
+        const T sc = (T)(c / (g.adet * (1.0 / RefSimplex<D>::vol)));
+        double cad[D];
+        select_row<D>(g.C, a, cad);
+        T ca[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) ca[k] = (T)cad[k];
+#pragma unroll
+        for (int b = 0; b < K; ++b) {
+            T sum = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) sum += ca[k] * (T)g.C[b][k];
+            kr[b] = sc * sum;
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < K; ++b) {
+        if constexpr (FORM == kLaplace) {
+            row[b] = kr[b];
+        } else {
+            using R = Deg2Rule<D>;
+            double m = 0.0;
+#pragma unroll
+            for (int q = 0; q < R::Q; ++q) {
+                const double pa = (a == q) ? R::hi : R::lo;
+                const double pb = (b == q) ? R::hi : R::lo;
+                m += R::w * pa * pb;
+            }
+            const T mv = (T)(g.adet * m);
+            row[b] = (FORM == kMass) ? mv : mv + kr[b];
+        }
+    }
+    fa = (T)(f * g.adet * (RefSimplex<D>::vol / K));  // phi_a(centroid) = 1/(d+1)
+}
+
+// Fused Map + Reduce over a batch of coefficient sets (nbatch >= 1; a plain
+// call is nbatch = 1).  Member m reads coef[m E + e] and load[m E + e] and
+// writes values[m nnz + p] and rhs[m N + i]; the geometry and the routing are
+// read once for the whole batch.  Every member runs exactly the arithmetic
+// of a single call, so it is bitwise equal to assembling it alone.
+template <int D, typename T, int FORM, bool LOAD, bool BATCHED>
 __global__ __launch_bounds__(kP1Threads) void p1_assemble_kernel(
     const int32_t *__restrict__ blk_desc, const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc,
     const int32_t *__restrict__ seg_ptr, const uint16_t *__restrict__ slot, const int32_t *__restrict__ conn,
     const double *__restrict__ coords, const T *__restrict__ coef, const T *__restrict__ load,
-    T *__restrict__ values, T *__restrict__ rhs, int32_t *__restrict__ status, int nblk, int mp, int me) {
+    T *__restrict__ values, T *__restrict__ rhs, int32_t *__restrict__ status, int nblk, int mp, int me,
+    int nbatch, unsigned n_elem, unsigned nnz, unsigned n_rows) {
     constexpr int K = D + 1;
+    constexpr bool COEF = FORM != kMass;
     extern __shared__ __align__(16) unsigned char smem[];
     BlockLds<T> L(smem, mp, me, K, 1, K);
 
@@ -283,84 +356,89 @@ __global__ __launch_bounds__(kP1Threads) void p1_assemble_kernel(
     }
     if (tid <= nent) seg_reg = ldg(seg_ptr, (unsigned)(v0 + tid));
 
-    // ---- Map: row a of K_e (and F_e[a]) for every pair of the block
-    for (int t = tid; t < np; t += kP1Threads) {
-        const unsigned code = (unsigned)ldg(inc, (unsigned)(q0 + t));
-        const unsigned e = code / K;
-        const int a = (int)(code - e * K);
-        double ce = 1.0, fe = 0.0;
-        if (!MASS) ce = (double)ldg(coef, e);
-        if (LOAD) fe = (double)ldg(load, e);
+    // ---- Map geometry of this thread's pair (kept for the whole batch)
+    const bool own = tid < np;
+    unsigned e = 0;
+    int a = 0;
+    P1Geom<D> g;
+    g.adet = 1.0;
+    g.bad = false;
+    if (own) {
+        const unsigned code = (unsigned)ldg(inc, (unsigned)(q0 + tid));
+        e = code / K;
+        a = (int)(code - e * K);
         double x[K][D];
         load_vertices<D>(conn, coords, (int)e, x);
-        double C[K][D];
-        const double det = p1_cofactors<D>(x, C);
-        const double adet = fabs(det);
-        bool bad = numerically_singular<D>(x, det);
-        if constexpr (MASS) {
-            // M_ab = sum_q w_q |det J| phi_a(x_q) phi_b(x_q), degree-2 rule
-            using R = Deg2Rule<D>;
-#pragma unroll
-            for (int b = 0; b < K; ++b) {
-                double m = 0.0;
-#pragma unroll
-                for (int q = 0; q < R::Q; ++q) {
-                    const double pa = (a == q) ? R::hi : R::lo;
-                    const double pb = (b == q) ? R::hi : R::lo;
-                    m += R::w * pa * pb;
-                }
-                L.K[b * np + t] = (T)(adet * m);
-            }
-        } else {
-            bad = (bool)((int)bad | (int)!finite(ce) | (int)!finite(fe));
-            // 1-point centroid rule (the integrand a_e G_a . G_b is constant):
-            // K_ab = w |det J| a_e (C_a/det).(C_b/det) = a_e (C_a . C_b) / (d! |det J|)
-            const T sc = (T)(ce / (adet * (1.0 / RefSimplex<D>::vol)));
-            double cad[D];
-            select_row<D>(C, a, cad);
-            T ca[D];
-#pragma unroll
-            for (int c = 0; c < D; ++c) ca[c] = (T)cad[c];
-#pragma unroll
-            for (int b = 0; b < K; ++b) {
-                T sum = 0;
-#pragma unroll
-                for (int c = 0; c < D; ++c) sum += ca[c] * (T)C[b][c];
-                L.K[b * np + t] = sc * sum;
-            }
-            L.F[t] = (T)(fe * adet * (RefSimplex<D>::vol / K));  // phi_a(centroid) = 1/(d+1)
-        }
-        if (bad && status) atomicMin(status, (int)e);
+        p1_geometry<D>(x, g);
     }
-    // ---- routing -> LDS (registers first, then any remainder of a large block)
-    if (tid < np) {
-        if constexpr (K == 4) {
-            *reinterpret_cast<uint2 *>(L.slot + 4 * tid) =
-                make_uint2((uint32_t)slot_reg[0] | ((uint32_t)slot_reg[1] << 16),
-                           (uint32_t)slot_reg[2] | ((uint32_t)slot_reg[3] << 16));
-        } else {
-#pragma unroll
-            for (int j = 0; j < K; ++j) L.slot[K * tid + j] = slot_reg[j];
-        }
-    }
-    for (int u = K * (tid + kP1Threads); u < np * K; u += K * kP1Threads)
-#pragma unroll
-        for (int j = 0; j < K; ++j) L.slot[u + j] = ldg(slot, s0 + (unsigned)(u + j));
-    if (tid <= nent) L.seg[tid] = seg_reg - (int)s0;
-    for (int u = tid + kP1Threads; u <= nent; u += kP1Threads) L.seg[u] = ldg(seg_ptr, (unsigned)(v0 + u)) - (int)s0;
-    __syncthreads();
 
-    // ---- Reduce: CSR values of the block rows (S_mat projection), LDS only
-    for (int p = threadIdx.x; p < nent; p += kP1Threads)
-        stg(values, (unsigned)(v0 + p), segment_sum<T>(L.K, L.slot, L.seg[p], L.seg[p + 1]));
-    // ---- Reduce: right-hand side (S_vec projection)
-    if (LOAD) {
-        for (int r = r0 + threadIdx.x; r < r1; r += kP1Threads) {
-            const int u0 = ldg(inc_ptr, (unsigned)r) - q0, u1 = ldg(inc_ptr, (unsigned)r + 1u) - q0;
-            T acc = 0;
-            for (int u = u0; u < u1; ++u) acc += L.F[u];
-            stg(rhs, (unsigned)r, acc);
+    const int nmem = BATCHED ? nbatch : 1;
+    for (int m = 0; m < nmem; ++m) {
+        const unsigned eo = (unsigned)m * n_elem;
+        // ---- Map: row a of the local matrix (and F_e[a]) for member m
+        if (own) {
+            const double c = COEF ? (double)ldg(coef, eo + e) : 1.0;
+            const double f = LOAD ? (double)ldg(load, eo + e) : 0.0;
+            T row[K], fa;
+            p1_row<D, T, FORM>(g, a, c, f, row, fa);
+#pragma unroll
+            for (int b = 0; b < K; ++b) L.K[b * np + tid] = row[b];
+            L.F[tid] = fa;
+            const bool bad = (bool)((int)g.bad | (int)!finite(c) | (int)!finite(f));
+            if (bad && status) atomicMin(status, (int)e);
         }
+        for (int t = tid + kP1Threads; t < np; t += kP1Threads) {  // a single row with more pairs than threads
+            const unsigned code = (unsigned)ldg(inc, (unsigned)(q0 + t));
+            const unsigned ee = code / K;
+            double x[K][D];
+            load_vertices<D>(conn, coords, (int)ee, x);
+            P1Geom<D> gg;
+            p1_geometry<D>(x, gg);
+            const double c = COEF ? (double)ldg(coef, eo + ee) : 1.0;
+            const double f = LOAD ? (double)ldg(load, eo + ee) : 0.0;
+            T row[K], fa;
+            p1_row<D, T, FORM>(gg, (int)(code - ee * K), c, f, row, fa);
+#pragma unroll
+            for (int b = 0; b < K; ++b) L.K[b * np + t] = row[b];
+            L.F[t] = fa;
+            if (((int)gg.bad | (int)!finite(c) | (int)!finite(f)) && status) atomicMin(status, (int)ee);
+        }
+        if (m == 0) {
+            // ---- routing -> LDS (registers first, then any remainder of a large block)
+            if (own) {
+                if constexpr (K == 4) {
+                    *reinterpret_cast<uint2 *>(L.slot + 4 * tid) =
+                        make_uint2((uint32_t)slot_reg[0] | ((uint32_t)slot_reg[1] << 16),
+                                   (uint32_t)slot_reg[2] | ((uint32_t)slot_reg[3] << 16));
+                } else {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) L.slot[K * tid + j] = slot_reg[j];
+                }
+            }
+            for (int u = K * (tid + kP1Threads); u < np * K; u += K * kP1Threads)
+#pragma unroll
+                for (int j = 0; j < K; ++j) L.slot[u + j] = ldg(slot, s0 + (unsigned)(u + j));
+            if (tid <= nent) L.seg[tid] = seg_reg - (int)s0;
+            for (int u = tid + kP1Threads; u <= nent; u += kP1Threads)
+                L.seg[u] = ldg(seg_ptr, (unsigned)(v0 + u)) - (int)s0;
+        }
+        __syncthreads();
+
+        // ---- Reduce: CSR values of the block rows (S_mat projection), LDS only
+        const unsigned vo = (unsigned)m * nnz;
+        for (int p = tid; p < nent; p += kP1Threads)
+            stg(values, vo + (unsigned)(v0 + p), segment_sum<T>(L.K, L.slot, L.seg[p], L.seg[p + 1]));
+        // ---- Reduce: right-hand side (S_vec projection)
+        if (LOAD) {
+            const unsigned ro = (unsigned)m * n_rows;
+            for (int r = r0 + tid; r < r1; r += kP1Threads) {
+                const int u0 = ldg(inc_ptr, (unsigned)r) - q0, u1 = ldg(inc_ptr, (unsigned)r + 1u) - q0;
+                T acc = 0;
+                for (int u = u0; u < u1; ++u) acc += L.F[u];
+                stg(rhs, ro + (unsigned)r, acc);
+            }
+        }
+        if (m + 1 < nmem) __syncthreads();  // LDS is rewritten by the next member
     }
 }
 
@@ -532,40 +610,54 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
 
 // ---------------------------------------------------------------- launchers
 
-template <int D, typename T, bool MASS, bool LOAD>
-static hipError_t launch_p1_t(const tg_pattern &p, const double *coords, const void *coef, const void *load,
-                              void *values, void *rhs, int32_t *status, hipStream_t s) {
+template <int D, typename T, int FORM, bool LOAD>
+static hipError_t launch_p1_t(const tg_pattern &p, int nbatch, const double *coords, const void *coef,
+                              const void *load, void *values, void *rhs, int32_t *status, hipStream_t s) {
     const DevicePattern &d = p.dev;
-    const int nblk = (int)p.host.n_blocks();
-    const int mp = p.host.max_block_pairs, me = p.host.max_block_entries;
+    const HostPattern &h = p.host;
+    const int nblk = (int)h.n_blocks();
+    const int mp = h.max_block_pairs, me = h.max_block_entries;
     const size_t lds = BlockLds<T>::bytes(mp, me, D + 1, 1, D + 1);
-    hipLaunchKernelGGL((p1_assemble_kernel<D, T, MASS, LOAD>), dim3(nblk), dim3(kP1Threads), lds, s, d.blk_desc,
-                       d.inc_ptr, d.inc, d.seg_ptr, d.slot, d.conn, coords, (const T *)coef, (const T *)load,
-                       (T *)values, (T *)rhs, status, nblk, mp, me);
+    if (nbatch == 1)
+        hipLaunchKernelGGL((p1_assemble_kernel<D, T, FORM, LOAD, false>), dim3(nblk), dim3(kP1Threads), lds, s,
+                           d.blk_desc, d.inc_ptr, d.inc, d.seg_ptr, d.slot, d.conn, coords, (const T *)coef,
+                           (const T *)load, (T *)values, (T *)rhs, status, nblk, mp, me, 1, (unsigned)h.E,
+                           (unsigned)h.nnz, (unsigned)h.n_dofs);
+    else
+        hipLaunchKernelGGL((p1_assemble_kernel<D, T, FORM, LOAD, true>), dim3(nblk), dim3(kP1Threads), lds, s,
+                           d.blk_desc, d.inc_ptr, d.inc, d.seg_ptr, d.slot, d.conn, coords, (const T *)coef,
+                           (const T *)load, (T *)values, (T *)rhs, status, nblk, mp, me, nbatch, (unsigned)h.E,
+                           (unsigned)h.nnz, (unsigned)h.n_dofs);
     return hipGetLastError();
 }
 
-hipError_t launch_assemble_p1(const tg_pattern &p, tg_form form, tg_dtype dtype, const double *coords,
+template <int D, typename T>
+static hipError_t launch_p1_d(const tg_pattern &p, tg_form form, int nbatch, const double *coords, const void *coef,
+                              const void *load, void *values, void *rhs, int32_t *status, hipStream_t s) {
+    const bool with_load = form != TG_MASS && load && rhs;
+    switch (form) {
+        case TG_MASS: return launch_p1_t<D, T, kMass, false>(p, nbatch, coords, coef, load, values, rhs, status, s);
+        case TG_LAPLACE:
+            return with_load ? launch_p1_t<D, T, kLaplace, true>(p, nbatch, coords, coef, load, values, rhs, status, s)
+                             : launch_p1_t<D, T, kLaplace, false>(p, nbatch, coords, coef, load, values, rhs, status, s);
+        case TG_MASS_LAPLACE:
+            return with_load
+                       ? launch_p1_t<D, T, kMassLaplace, true>(p, nbatch, coords, coef, load, values, rhs, status, s)
+                       : launch_p1_t<D, T, kMassLaplace, false>(p, nbatch, coords, coef, load, values, rhs, status, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_assemble_p1(const tg_pattern &p, tg_form form, tg_dtype dtype, int nbatch, const double *coords,
                               const void *coef, const void *load, void *values, void *rhs, int32_t *status,
                               hipStream_t s) {
-    const bool mass = form == TG_MASS;
-    const bool with_load = !mass && load && rhs;
     const int D = p.host.dim;
-#define TG_P1_CASE(DD, TT)                                                                                \
-    if (D == DD) {                                                                                        \
-        if (mass) return launch_p1_t<DD, TT, true, false>(p, coords, coef, load, values, rhs, status, s); \
-        if (with_load) return launch_p1_t<DD, TT, false, true>(p, coords, coef, load, values, rhs, status, s); \
-        return launch_p1_t<DD, TT, false, false>(p, coords, coef, load, values, rhs, status, s);          \
-    }
     if (dtype == TG_F64) {
-        TG_P1_CASE(2, double)
-        TG_P1_CASE(3, double)
-    } else {
-        TG_P1_CASE(2, float)
-        TG_P1_CASE(3, float)
+        if (D == 2) return launch_p1_d<2, double>(p, form, nbatch, coords, coef, load, values, rhs, status, s);
+        return launch_p1_d<3, double>(p, form, nbatch, coords, coef, load, values, rhs, status, s);
     }
-#undef TG_P1_CASE
-    return hipErrorInvalidValue;
+    if (D == 2) return launch_p1_d<2, float>(p, form, nbatch, coords, coef, load, values, rhs, status, s);
+    return launch_p1_d<3, float>(p, form, nbatch, coords, coef, load, values, rhs, status, s);
 }
 
 hipError_t launch_assemble_p2(const tg_pattern &p, tg_dtype dtype, const double *coords, const void *coef,

@@ -101,6 +101,7 @@ struct DevicePattern {
     PcgState *host_state = nullptr;  // pinned mirror
     size_t bytes = 0;
     int spmv_group = 4;  // lanes per CSR row in the SpMV
+    int n_cu = 1;        // compute units of the pattern's device (persistent grids)
 };
 
 }  // namespace tg
@@ -114,7 +115,7 @@ struct tg_pattern {
 
 // Kernel launchers (tg_assemble.hip, tg_solve.hip).  They return hipError_t.
 namespace tg {
-hipError_t launch_assemble_p1(const tg_pattern &p, tg_form form, tg_dtype dtype, const double *coords,
+hipError_t launch_assemble_p1(const tg_pattern &p, tg_form form, tg_dtype dtype, int nbatch, const double *coords,
                               const void *coef, const void *load, void *values, void *rhs, int32_t *status,
                               hipStream_t s);
 hipError_t launch_assemble_p2(const tg_pattern &p, tg_dtype dtype, const double *coords, const void *coef,

@@ -160,32 +160,12 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
             for (int a = 0; a < k; ++a) hp.inc[fill[hp.elem_nodes[e * k + a]]++] = (int32_t)(e * k + a);
     }
 
-    // ---- row blocks: consecutive rows while the pairs fit the target
-    const int target = p1 ? kP1BlockTarget : kP2BlockTarget;
-    hp.blk_row.clear();
-    hp.blk_row.push_back(0);
-    for (int64_t i = 0; i < N;) {
-        const int32_t first = hp.inc_ptr[i];
-        int64_t j = i + 1;
-        while (j < N && hp.inc_ptr[j + 1] - first <= target) ++j;
-        hp.blk_row.push_back((int32_t)j);
-        i = j;
-    }
-
-    // ---- node-level CSR and S_mat routing, row by row
+    // ---- node-level CSR: row i holds every node sharing an element with i (sorted)
     hp.node_rp.assign(N + 1, 0);
     hp.node_ci.clear();
     hp.node_ci.reserve((size_t)E * k * 2);
-    hp.seg_ptr.clear();
-    hp.seg_ptr.reserve((size_t)E * k * 2);
-    hp.slot.resize((size_t)E * k * k);
     std::vector<int32_t> mark(N, -1), pos(N, 0), cols, cnt;
-    int64_t slot_fill = 0;
-    int64_t blk = 0;
     for (int64_t i = 0; i < N; ++i) {
-        while (hp.blk_row[blk + 1] <= i) ++blk;
-        const int32_t blk_first_pair = hp.inc_ptr[hp.blk_row[blk]];
-        const int32_t blk_pairs = hp.inc_ptr[hp.blk_row[blk + 1]] - blk_first_pair;
         cols.clear();
         for (int32_t t = hp.inc_ptr[i]; t < hp.inc_ptr[i + 1]; ++t) {
             const int64_t e = hp.inc[t] / k;
@@ -198,15 +178,49 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
             }
         }
         std::sort(cols.begin(), cols.end());
-        for (size_t c = 0; c < cols.size(); ++c) pos[cols[c]] = (int32_t)c;
+        hp.node_ci.insert(hp.node_ci.end(), cols.begin(), cols.end());
+        hp.node_rp[i + 1] = (int32_t)hp.node_ci.size();
+        if ((int64_t)hp.node_ci.size() * ncomp * ncomp >= INT32_MAX) {
+            msg = "too many nonzeros for int32 indexing";
+            return TG_E_ARG;
+        }
+    }
+
+    // ---- row blocks: consecutive rows while the pairs fit the target (and, for
+    // P1, the node-level entries fit one thread each); a single row may exceed
+    // the target up to the capacity
+    const int target = p1 ? kP1BlockTarget : kP2BlockTarget;
+    const int entry_target = p1 ? kP1Threads - 1 : INT32_MAX;
+    hp.blk_row.clear();
+    hp.blk_row.push_back(0);
+    for (int64_t i = 0; i < N;) {
+        const int32_t first = hp.inc_ptr[i], first_entry = hp.node_rp[i];
+        int64_t j = i + 1;
+        while (j < N && hp.inc_ptr[j + 1] - first <= target && hp.node_rp[j + 1] - first_entry <= entry_target) ++j;
+        hp.blk_row.push_back((int32_t)j);
+        i = j;
+    }
+
+    // ---- S_mat routing, row by row
+    hp.seg_ptr.clear();
+    hp.seg_ptr.reserve((size_t)hp.node_ci.size() + 1);
+    hp.slot.resize((size_t)E * k * k);
+    int64_t slot_fill = 0;
+    int64_t blk = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        while (hp.blk_row[blk + 1] <= i) ++blk;
+        const int32_t blk_first_pair = hp.inc_ptr[hp.blk_row[blk]];
+        const int32_t blk_pairs = hp.inc_ptr[hp.blk_row[blk + 1]] - blk_first_pair;
+        const int32_t c0 = hp.node_rp[i], m = hp.node_rp[i + 1] - c0;
+        for (int32_t c = 0; c < m; ++c) pos[hp.node_ci[c0 + c]] = c;
         // counts per entry, then slots in (pair ascending, b) order -> ascending element per entry
-        cnt.assign(cols.size() + 1, 0);
+        cnt.assign(m + 1, 0);
         for (int32_t t = hp.inc_ptr[i]; t < hp.inc_ptr[i + 1]; ++t) {
             const int64_t e = hp.inc[t] / k;
             for (int b = 0; b < k; ++b) cnt[pos[hp.elem_nodes[e * k + b]] + 1]++;
         }
-        for (size_t c = 0; c < cols.size(); ++c) cnt[c + 1] += cnt[c];
-        for (size_t c = 0; c < cols.size(); ++c) hp.seg_ptr.push_back((int32_t)(slot_fill + cnt[c]));
+        for (int32_t c = 0; c < m; ++c) cnt[c + 1] += cnt[c];
+        for (int32_t c = 0; c < m; ++c) hp.seg_ptr.push_back((int32_t)(slot_fill + cnt[c]));
         for (int32_t t = hp.inc_ptr[i]; t < hp.inc_ptr[i + 1]; ++t) {
             const int64_t e = hp.inc[t] / k;
             for (int b = 0; b < k; ++b) {
@@ -215,12 +229,6 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
             }
         }
         slot_fill += (int64_t)(hp.inc_ptr[i + 1] - hp.inc_ptr[i]) * k;
-        hp.node_ci.insert(hp.node_ci.end(), cols.begin(), cols.end());
-        hp.node_rp[i + 1] = (int32_t)hp.node_ci.size();
-        if ((int64_t)hp.node_ci.size() * ncomp * ncomp >= INT32_MAX) {
-            msg = "too many nonzeros for int32 indexing";
-            return TG_E_ARG;
-        }
     }
     hp.seg_ptr.push_back((int32_t)slot_fill);
     hp.nnz_nodes = (int64_t)hp.node_ci.size();

@@ -233,3 +233,53 @@ def test_p2_symmetry_and_rigid_modes_on_gpu():
     import indep
     R = indep.rigid_modes(xyz)
     assert np.abs(K @ R.T).max() < 1e-11 * abs(K).max()
+
+
+# ---------------------------------------------------------------- batched coefficients, M + K(c)
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dim,n", [(2, 20), (3, 9)])
+def test_batched_members_equal_solo_bitwise(dim, n, dtype):
+    d = meshgen.poisson_inputs(dim, n, seed=2)
+    pat = tg.Pattern(d["conn"], len(d["coords"]))
+    coords = torch.from_numpy(d["coords"]).cuda()
+    rng = np.random.default_rng(5)
+    B, E = 5, len(d["conn"])
+    a = torch.from_numpy(np.exp(rng.standard_normal((B, E)))).to(dtype).cuda()
+    f = torch.from_numpy(rng.uniform(-1, 1, (B, E))).to(dtype).cuda()
+    vb, rb = tg.assemble_batched(pat, tg.LAPLACE, coords, a, f)
+    for b in range(B):
+        v, r = tg.assemble(pat, tg.LAPLACE, coords, a[b].contiguous(), f[b].contiguous())
+        assert torch.equal(vb[b], v) and torch.equal(rb[b], r)
+    # and one member against the oracle
+    A = oracle.assemble_p1(d["coords"], d["conn"], a[3].double().cpu().numpy(), f[3].double().cpu().numpy())
+    rp, ci = pat.csr()
+    K = sp.csr_matrix((vb[3].double().cpu().numpy(), ci, rp), shape=(A.n, A.n))
+    assert _norm_rel(K, A.scipy()) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dim,n", [(2, 16), (3, 6)])
+def test_mass_laplace_parity(dim, n, dtype):
+    d = meshgen.poisson_inputs(dim, n, seed=7)
+    pat = tg.Pattern(d["conn"], len(d["coords"]))
+    c = 1e-3 * d["a"]
+    vals, rhs = tg.assemble(pat, tg.MASS_LAPLACE, torch.from_numpy(d["coords"]).cuda(),
+                            torch.from_numpy(c).to(dtype).cuda(), torch.from_numpy(d["f"]).to(dtype).cuda())
+    M = oracle.assemble_p1(d["coords"], d["conn"], form="mass").scipy()
+    A = oracle.assemble_p1(d["coords"], d["conn"], c, d["f"])
+    rp, ci = pat.csr()
+    K = sp.csr_matrix((vals.double().cpu().numpy(), ci, rp), shape=(A.n, A.n))
+    assert _norm_rel(K, M + A.scipy()) <= TOL[dtype]
+    assert _vec_rel(rhs.double().cpu().numpy(), A.rhs) <= TOL[dtype]
+
+
+def test_batched_argument_errors():
+    d = meshgen.poisson_inputs(2, 3, seed=0)
+    pat = tg.Pattern(d["conn"], len(d["coords"]))
+    coords = torch.from_numpy(d["coords"]).cuda()
+    with pytest.raises(ValueError):
+        tg.assemble_batched(pat, tg.MASS, coords, torch.ones(2, pat.n_elements, dtype=torch.float64, device="cuda"))
+    st = tg._lib.tg_assemble_batched(pat.handle, tg.LAPLACE, tg.F64, 0, coords.data_ptr(), 8, None, 8, None, None,
+                                     None)
+    assert st == tg.TG_E_ARG
