@@ -71,7 +71,7 @@ tg_status create_device(tg_pattern &pt) {
         bytes += wb;
     }
     if (e == hipSuccess) {
-        const size_t pb = 4 * (size_t)kMaxGrid * sizeof(double);
+        const size_t pb = (size_t)kNumPartials * kMaxGrid * sizeof(double);
         e = hipMalloc((void **)&d.partials, pb);
         bytes += pb;
     }

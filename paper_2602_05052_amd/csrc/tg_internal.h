@@ -77,6 +77,8 @@ struct PcgState {
 
 constexpr int kVecThreads = 1024;  // threads per block of the PCG kernels
 constexpr int kMaxGrid = 512;      // blocks of the PCG kernels (grid-stride beyond): 2 per CU
+// Per-block partial sums of the PCG kernels: [PQ | RZ0 | RZ1 | RR | BB], kMaxGrid doubles each.
+constexpr int kPQ = 0, kRZ0 = 1, kRR = 3, kBB = 4, kNumPartials = 5;
 
 struct DevicePattern {
     int32_t *conn = nullptr;      // [E][dim+1]
@@ -94,7 +96,7 @@ struct DevicePattern {
     uint8_t *constrained = nullptr;  // [n_dofs]
     // PCG workspace: 6 vectors of n_dofs doubles (used as T), partials, state.
     double *work = nullptr;
-    double *partials = nullptr;  // [4][kMaxGrid]: (p.q), (r.z, r.r), (b.b) partials
+    double *partials = nullptr;  // [kNumPartials][kMaxGrid]: (p.q), (r.z) x2, (r.r), (b.b) partials
     int32_t *dir_rows = nullptr; // rows that are constrained or have a constrained column
     int64_t n_dir_rows = 0;
     PcgState *state = nullptr;

@@ -42,9 +42,7 @@ __device__ __forceinline__ double sum_partials(const double *__restrict__ partia
     return block_sum((int)threadIdx.x < n ? partials[threadIdx.x] : 0.0, sh);
 }
 
-// Partials layout: [PQ | RZ0 | RZ1 | RR | BB] blocks of kMaxGrid doubles.
 __device__ __forceinline__ double *part(double *base, int which) { return base + (size_t)which * kMaxGrid; }
-constexpr int kPQ = 0, kRZ0 = 1, kRR = 3, kBB = 4;
 
 template <typename T>
 __global__ __launch_bounds__(256) void dirichlet_kernel(int nrows, const int32_t *__restrict__ rows,
