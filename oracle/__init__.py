@@ -67,6 +67,10 @@ def _load():
                                            _dp, _dp, _i64p, _i64p, _dp, _dp, _i64p]
         lib.oracle_assemble_p2_elasticity.argtypes = [ctypes.c_int64, _dp, ctypes.c_int64, _i32p, _i64p, _dp, _dp,
                                                       _dp, _i64p, _i64p, _dp, _dp, _i64p]
+        lib.oracle_p1_adjoint_element.argtypes = [ctypes.c_int, _dp, ctypes.c_double, _dp, _dp, _dp, ctypes.c_int,
+                                                  _dp, _dp]
+        lib.oracle_p1_adjoint.argtypes = [ctypes.c_int, ctypes.c_int64, _dp, ctypes.c_int64, _i32p, ctypes.c_int,
+                                          _dp, _dp, _dp, _dp, _dp, _dp, _i64p]
         _lib = lib
     return _lib
 
@@ -255,6 +259,92 @@ def assemble_p2_elasticity(coords, conn, lam, mu, b=None) -> Assembled:
     out = Assembled(row_ptr, col_idx, vals, rhs)
     out.nodes10, out.n_nodes = nodes10, n_nodes
     return out
+
+
+# ---------------------------------------------------------------- adjoint
+
+def p1_adjoint_element(X, c, lam, u, w=None, mass=False):
+    """(dPhi/dlog c, dPhi/dx [d+1, d]) of Phi = lam^T (A u - M w) on one P1 simplex (A = K(c) [+ M])."""
+    X = _f64(X)
+    dim = X.shape[1]
+    dlogc = ctypes.c_double()
+    dx = np.zeros((dim + 1, dim))
+    ww = _f64(w) if w is not None else None
+    _check(_load().oracle_p1_adjoint_element(dim, _ptr(X, _dp), float(c), _ptr(_f64(lam), _dp), _ptr(_f64(u), _dp),
+                                             _ptr(ww, _dp), int(mass), ctypes.byref(dlogc), _ptr(dx, _dp)), "adjoint")
+    return dlogc.value, dx
+
+
+def p1_adjoint(coords, conn, c, lam, u, w=None, mass=False):
+    """Global (dPhi/dlog c [E], dPhi/dcoords [nv, d]) of Phi = lam^T (A(c) u - M w), elements in order."""
+    coords = _f64(coords)
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    nv, dim = coords.shape
+    E = conn.shape[0]
+    dlogc = np.zeros(E)
+    dcoords = np.zeros((nv, dim))
+    bad = ctypes.c_int64(-1)
+    ww = _f64(w) if w is not None else None
+    rc = _load().oracle_p1_adjoint(dim, nv, _ptr(coords, _dp), E, _ptr(conn, _i32p), int(mass), _ptr(_f64(c), _dp),
+                                   _ptr(_f64(lam), _dp), _ptr(_f64(u), _dp), _ptr(ww, _dp), _ptr(dlogc, _dp),
+                                   _ptr(dcoords, _dp), ctypes.byref(bad))
+    _check(rc, "p1_adjoint", bad.value)
+    return dlogc, dcoords
+
+
+# ---------------------------------------------------------------- implicit-Euler heat rollout and its adjoint
+
+def heat_matrices(coords, conn, log_a, dt):
+    """(A, M) as scipy CSR: M the P1 mass matrix (Sec. A.1, mass inner product), A = M + dt K(exp(log_a))."""
+    a = np.exp(_f64(log_a))
+    K = assemble_p1(coords, conn, dt * a, np.zeros_like(a), form="laplace").scipy()
+    M = assemble_p1(coords, conn, form="mass").scipy()
+    return (M + K).tocsr(), M
+
+
+def _interior_solve(A, mask, b):
+    import scipy.sparse.linalg as spla
+    x = np.zeros(A.shape[0])
+    x[mask] = spla.spsolve(A[mask][:, mask].tocsc(), b[mask])
+    return x
+
+
+def heat_rollout(coords, conn, log_a, u0, dt, nsteps, constrained):
+    """States U [nsteps+1, nv] of implicit Euler for M U' + K U = 0 (Sec. A.1, method of lines)
+    with U = 0 on the constrained vertices:  A u^{n+1} = M u^n on the free rows, A = M + dt K."""
+    A, M = heat_matrices(coords, conn, log_a, dt)
+    mask = np.ones(A.shape[0], dtype=bool)
+    mask[np.asarray(constrained, dtype=np.int64)] = False
+    U = np.zeros((nsteps + 1, A.shape[0]))
+    U[0] = _f64(u0)
+    for n in range(nsteps):
+        U[n + 1] = _interior_solve(A, mask, M @ U[n])
+    return U
+
+
+def heat_adjoint(coords, conn, log_a, U, dt, g, constrained):
+    """Discrete adjoint (Sec. 2, eq. adj) of the rollout for a loss with dL/du^N = g.
+
+    lam^N solves A lam^N = g and lam^n solves A lam^n = M lam^{n+1} on the free rows (A symmetric).
+    With Phi_n = lam^n^T (A u^n - M u^{n-1}), every parameter gradient is -sum_n dPhi_n; the
+    element terms come from p1_adjoint.  Returns (dL/dlog_a [E], dL/dcoords [nv, d], dL/du0 [nv]).
+    """
+    A, M = heat_matrices(coords, conn, log_a, dt)
+    mask = np.ones(A.shape[0], dtype=bool)
+    mask[np.asarray(constrained, dtype=np.int64)] = False
+    N = U.shape[0] - 1
+    c = dt * np.exp(_f64(log_a))
+    lam = _interior_solve(A, mask, _f64(g))
+    dloga = np.zeros(conn.shape[0])
+    dcoords = np.zeros_like(_f64(coords))
+    for n in range(N, 0, -1):
+        dl, dx = p1_adjoint(coords, conn, c, lam, U[n], U[n - 1], mass=True)
+        dloga -= dl
+        dcoords -= dx
+        if n > 1:
+            lam = _interior_solve(A, mask, M @ lam)
+    du0 = M @ lam
+    return dloga, dcoords, du0
 
 
 # ---------------------------------------------------------------- condensed solve and metrics

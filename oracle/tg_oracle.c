@@ -452,3 +452,77 @@ int oracle_assemble_p2_elasticity(int64_t nv, const double *coords, int64_t E, c
     free(Ke);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* Adjoint of P1 assembly                                              */
+/* ------------------------------------------------------------------ */
+
+/*
+ * For one P1 simplex, the element term of
+ *   Phi = lam^T (A(c, x) u - M(x) w),   A = K(c) (mass = 0) or M + K(c) (mass = 1),
+ * returns dPhi/d(log c) = lam^T K_e u (= c |T| g_lam . g_u with g_v = sum_b v_b grad(l_b))
+ * in *dlogc, and dPhi/dx_a for every vertex a in dx [d+1][d]:
+ *   K part:    c |T| [ G_a (g_lam.g_u) - g_lam (G_a.g_u) - g_u (G_a.g_lam) ]
+ *   mass part: Phi_M G_a with Phi_M = lam^T M_e (mass u - w)
+ * using d|T|/dx_a = |T| G_a and d(grad l_b)/dx_a = -grad(l_b) G_a^T (affine map),
+ * G_a = grad(l_a).  w may be NULL (taken as 0).
+ */
+int oracle_p1_adjoint_element(int dim, const double *X, double c, const double *lam, const double *u,
+                              const double *w, int mass, double *dlogc, double *dx)
+{
+    double G[4 * 3], vol, gl[3] = {0, 0, 0}, gu[3] = {0, 0, 0}, M[16], phim = 0.0, glu = 0.0;
+    int k = dim + 1;
+    int rc = oracle_simplex_geometry(dim, X, G, &vol);
+    if (rc) return rc;
+    for (int b = 0; b < k; ++b)
+        for (int i = 0; i < dim; ++i) {
+            gl[i] += lam[b] * G[b * dim + i];
+            gu[i] += u[b] * G[b * dim + i];
+        }
+    for (int i = 0; i < dim; ++i) glu += gl[i] * gu[i];
+    oracle_p1_mass_element(dim, X, M);
+    for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b) phim += lam[a] * M[a * k + b] * ((mass ? u[b] : 0.0) - (w ? w[b] : 0.0));
+    *dlogc = c * vol * glu;
+    for (int a = 0; a < k; ++a) {
+        double Ga_gu = 0.0, Ga_gl = 0.0;
+        for (int i = 0; i < dim; ++i) {
+            Ga_gu += G[a * dim + i] * gu[i];
+            Ga_gl += G[a * dim + i] * gl[i];
+        }
+        for (int i = 0; i < dim; ++i)
+            dx[a * dim + i] = c * vol * (G[a * dim + i] * glu - gl[i] * Ga_gu - gu[i] * Ga_gl) + phim * G[a * dim + i];
+    }
+    return ORC_OK;
+}
+
+/*
+ * Global adjoint: dlogc [E] and dcoords [nv][dim] of Phi = lam^T (A u - M w), summed over
+ * elements in ascending order (arrays are overwritten).
+ */
+int oracle_p1_adjoint(int dim, int64_t nv, const double *coords, int64_t E, const int32_t *conn, int mass,
+                      const double *c, const double *lam, const double *u, const double *w, double *dlogc,
+                      double *dcoords, int64_t *bad)
+{
+    int k = dim + 1;
+    double X[12], le[4], ue[4], we[4], dx[12];
+    for (int64_t t = 0; t < nv * dim; ++t) dcoords[t] = 0.0;
+    for (int64_t e = 0; e < E; ++e) {
+        const int32_t *g = conn + e * k;
+        int rc;
+        gather_vertices(dim, coords, g, k, X);
+        for (int a = 0; a < k; ++a) {
+            le[a] = lam[g[a]];
+            ue[a] = u[g[a]];
+            we[a] = w ? w[g[a]] : 0.0;
+        }
+        rc = oracle_p1_adjoint_element(dim, X, c[e], le, ue, w ? we : NULL, mass, &dlogc[e], dx);
+        if (rc) {
+            if (bad) *bad = e;
+            return rc;
+        }
+        for (int a = 0; a < k; ++a)
+            for (int i = 0; i < dim; ++i) dcoords[(int64_t)g[a] * dim + i] += dx[a * dim + i];
+    }
+    return ORC_OK;
+}
