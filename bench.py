@@ -73,8 +73,11 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle timing sample")
-    ap.add_argument("--workload", choices=["poisson3d", "elasticity"], default="poisson3d",
-                    help="poisson3d: the benchmark line; elasticity: P2 32^3 assembly-only timing")
+    ap.add_argument("--workload", choices=["poisson3d", "elasticity", "heat", "batched"], default="poisson3d",
+                    help="poisson3d: the benchmark line; elasticity: P2 32^3 assembly-only timing; heat: "
+                         "differentiable 2D heat rollout 256^2 (forward + adjoint gradient); batched: B "
+                         "coefficient sets on the 64^3 pattern in one launch")
+    ap.add_argument("--batch", type=int, default=8, help="coefficient sets for --workload batched")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -94,6 +97,10 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "elasticity":
         return run_elasticity(args, dev)
+    if args.workload == "heat":
+        return run_heat(args, dev)
+    if args.workload == "batched":
+        return run_batched(args, dev)
 
     # ---------------------------------------------------------------- inputs (resident in HBM)
     d = meshgen.poisson_inputs(3, args.n, seed=0)
@@ -311,6 +318,181 @@ def run_elasticity(args, dev):
                 "frac_b_alg": balg / float(t.mean()) / 1e9 / HBM_PEAK_GBS}
     out = {"workload": f"3D linear elasticity P2 tets, {n}^3 x 6 Kuhn, lambda,mu~U(0.5,2), b~N(0,1)^3, seed 0",
            "elements": E, "nnz": pat.nnz, "dofs": pat.n_dofs, "pattern_build_s": pattern_s, **res}
+    print(json.dumps(out))
+
+
+def adjoint_bytes(nv, dim, E, ndof, nbatch, s):
+    """Algorithmic bytes of one tg_adjoint_p1 call with w = the states shifted by one (heat):
+    element kernel (conn, coords, coef, nbatch lam + nbatch+1 state vectors, dlogc, scratch write)
+    plus the vertex Reduce (inc_ptr, inc, scratch read, dcoords)."""
+    k = dim + 1
+    elem = E * k * 4 + nv * dim * 8 + E * s + (2 * nbatch + 1) * ndof * s + E * 8 + E * k * dim * 8
+    red = (nv + 1) * 4 + E * k * 4 + E * k * dim * 8 + nv * dim * 8
+    return elem + red
+
+
+def run_heat(args, dev):
+    """Differentiable heat: 2D P1 256^2 (131,072 triangles), 20 implicit-Euler steps, dt = 1e-3;
+    one step of the benchmark = forward rollout + dL/du^N + adjoint gradient (log a, x, u0)."""
+    import numpy as np
+    import torch
+
+    import meshgen
+    import paper_2602_05052_amd as tg
+
+    n = 256 if args.n == 64 else args.n
+    dt_, nsteps, rtol = 1e-3, 20, 1e-10
+    d = meshgen.heat_inputs(n, seed=0)
+    E, nv = d["conn"].shape[0], d["coords"].shape[0]
+    pat = tg.Pattern(d["conn"], nv)
+    coords = torch.from_numpy(d["coords"]).to(dev)
+    log_a = torch.from_numpy(d["log_a"]).to(dev)
+    log_t = torch.from_numpy(meshgen.heat_inputs(n, seed=1)["log_a"]).to(dev)
+    u0_np = np.sin(np.pi * d["coords"][:, 0]) * np.sin(np.pi * d["coords"][:, 1])
+    s = torch.cuda.Stream(device=dev)
+    res = {}
+    print(f"# bench heat: E={E} nv={nv} steps {args.steps}", file=sys.stderr, flush=True)
+    for name, dt in (("fp64", torch.float64), ("fp32", torch.float32)):
+        r = rtol if dt == torch.float64 else 1e-6
+        u0 = torch.from_numpy(u0_np).to(dt).to(dev)
+        with torch.cuda.stream(s):
+            target = tg.heat_rollout(pat, coords, log_t, u0, dt_, nsteps, rtol=r, stream=s)[0][-1].clone()
+            t_f, t_b, it_f, it_b = [], [], [], []
+            for k in range(args.warmup + args.steps):
+                e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+                e0.record(s)
+                states, itf, _ = tg.heat_rollout(pat, coords, log_a, u0, dt_, nsteps, rtol=r, stream=s)
+                e1.record(s)
+                g = 2.0 * (states[-1] - target)
+                dla, dx, du0, itb, _ = tg.heat_adjoint(pat, coords, log_a, states, g, dt_, rtol=r, stream=s)
+                e2.record(s)
+                torch.cuda.synchronize()
+                if k >= args.warmup:
+                    t_f.append(e0.elapsed_time(e1) * 1e-3)
+                    t_b.append(e1.elapsed_time(e2) * 1e-3)
+                    it_f.append(itf)
+                    it_b.append(itb)
+            # the batched adjoint kernel alone (element kernel + vertex Reduce), same shapes as in the backward
+            lam = states[1:].clone()
+            coef = (dt_ * torch.exp(log_a)).to(dt)
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+            dlc = torch.empty(E, dtype=torch.float64, device=dev)
+            dxc = torch.empty(nv, 2, dtype=torch.float64, device=dev)
+            tg.adjoint_p1(pat, tg.MASS_LAPLACE, coords, coef, lam, states[1:], states[:-1], -1.0, dlc, dxc, stream=s)
+            for a0, a1 in evs:
+                a0.record(s)
+                tg.adjoint_p1(pat, tg.MASS_LAPLACE, coords, coef, lam, states[1:], states[:-1], -1.0, dlc, dxc,
+                              stream=s)
+                a1.record(s)
+            torch.cuda.synchronize()
+        t_adj = float(np.mean([a.elapsed_time(b) for a, b in evs])) * 1e-3
+        badj = adjoint_bytes(nv, 2, E, pat.n_dofs, nsteps, 8 if dt == torch.float64 else 4)
+        tf, tb = float(np.mean(t_f)), float(np.mean(t_b))
+        res[name] = {"forward_ms": tf * 1e3, "backward_ms": tb * 1e3, "grad_evals_per_s": 1.0 / (tf + tb),
+                     "forward_pcg_iters": int(np.median(it_f)), "backward_pcg_iters": int(np.median(it_b)),
+                     "pcg_us_per_iter": (tf + tb) / max(1, np.median(it_f) + np.median(it_b)) * 1e6,
+                     "adjoint_kernel_us": t_adj * 1e6, "adjoint_gbs": badj / t_adj / 1e9,
+                     "adjoint_bytes": badj, "pcg_rtol": r}
+        res[name]["_grads"] = (dla, dx, du0, g)
+    out = {"metric": "differentiable heat: gradient evaluations/s (forward rollout + adjoint)",
+           "value": res["fp64"]["grad_evals_per_s"], "unit": "grad/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": (res["fp64"]["forward_ms"] + res["fp64"]["backward_ms"]),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"2D heat P1 triangles {n}^2 x 2, jitter 0.2h, log a~N(0,1) (seed 0), target "
+                                  f"from log a seed 1, u0 = sin(pi x) sin(pi y), {nsteps} implicit-Euler steps dt "
+                                  f"{dt_:g}, Dirichlet u = 0 on the boundary, loss ||u^N - target||^2",
+                      "elements": E, "vertices": nv, "nnz": pat.nnz, "parallelism": "single GPU"},
+           "roofline": {"bound": "hbm", "kernel": "p1_adjoint_element_kernel<2,double,mass_laplace> + "
+                                                  "vertex_reduce_kernel<2> (nbatch 20)",
+                        "achieved": res["fp64"]["adjoint_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": res["fp64"]["adjoint_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                        "algorithmic_bytes_per_launch": res["fp64"]["adjoint_bytes"],
+                        "note": "the step time is dominated by the 40 PCG solves, not by this kernel"}}
+    if not args.no_cpu_baseline:
+        import oracle
+
+        print("# cpu baseline (oracle heat rollout + adjoint) ...", file=sys.stderr, flush=True)
+        bnd = meshgen.boundary_vertices(d["coords"])
+        c0 = time.perf_counter()
+        U = oracle.heat_rollout(d["coords"], d["conn"], d["log_a"], u0_np, dt_, nsteps, bnd)
+        Ut = oracle.heat_rollout(d["coords"], d["conn"], meshgen.heat_inputs(n, seed=1)["log_a"], u0_np, dt_,
+                                 nsteps, bnd)
+        c1 = time.perf_counter()
+        ref = oracle.heat_adjoint(d["coords"], d["conn"], d["log_a"], U, dt_, 2 * (U[-1] - Ut[-1]), bnd)
+        c2 = time.perf_counter()
+        t_cpu = (c1 - c0) / 2 + (c2 - c1)
+        out["cpu_baseline"] = {"value": 1.0 / t_cpu, "unit": "grad/s", "cores": 1, "kind": "oracle",
+                               "sample": f"one forward rollout + adjoint of the same problem by the oracle (scipy "
+                                         f"sparse LU factorised once per call, FP64 C element adjoint), {t_cpu:.2f} s",
+                               "cpu": _cpu_model()}
+        for name in ("fp64", "fp32"):
+            dla, dx, du0, _ = res[name]["_grads"]
+            errs = [float(np.max(np.abs(x.double().cpu().numpy() - r)) / np.max(np.abs(r)))
+                    for x, r in zip((dla, dx, du0), ref)]
+            res[name]["grad_err_vs_oracle"] = {"log_a": errs[0], "coords": errs[1], "u0": errs[2]}
+    for name in ("fp64", "fp32"):
+        res[name].pop("_grads")
+    out["heat"] = res
+    print(json.dumps(out))
+
+
+def run_batched(args, dev):
+    """B coefficient sets on the 64^3 Poisson pattern in one launch (values + rhs per member) against
+    B single launches; bytes counted with the geometry and the routing read once per launch."""
+    import numpy as np
+    import torch
+
+    import meshgen
+    import paper_2602_05052_amd as tg
+
+    B = args.batch
+    d = meshgen.poisson_inputs(3, args.n, seed=0)
+    E, nv = d["conn"].shape[0], d["coords"].shape[0]
+    pat = tg.Pattern(d["conn"], nv)
+    coords = torch.from_numpy(d["coords"]).to(dev)
+    rng = np.random.default_rng(5)
+    flush = torch.zeros(1 << 28, dtype=torch.float32, device=dev)
+    s = torch.cuda.Stream(device=dev)
+    res = {}
+    for name, dt in (("fp64", torch.float64), ("fp32", torch.float32)):
+        sz = 8 if dt == torch.float64 else 4
+        coef = torch.from_numpy(np.exp(rng.standard_normal((B, E)))).to(dt).to(dev)
+        load = torch.from_numpy(rng.uniform(-1, 1, (B, E))).to(dt).to(dev)
+        vals = torch.empty(B, pat.nnz, dtype=dt, device=dev)
+        rhs = torch.empty(B, pat.n_dofs, dtype=dt, device=dev)
+
+        def batched():
+            tg.assemble_batched(pat, tg.LAPLACE, coords, coef, load, values=vals, rhs=rhs, stream=s)
+
+        def solo():
+            for b in range(B):
+                tg.assemble(pat, tg.LAPLACE, coords, coef[b], load[b], values=vals[b], rhs=rhs[b], stream=s)
+
+        times = {}
+        for label, fn in (("batched", batched), ("solo_loop", solo)):
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(args.steps)]
+            with torch.cuda.stream(s):
+                for _ in range(args.warmup):
+                    fn()
+                for e0, e1 in evs:
+                    flush.add_(1.0)
+                    e0.record(s)
+                    fn()
+                    e1.record(s)
+            torch.cuda.synchronize()
+            times[label] = float(np.mean([a.elapsed_time(b) for a, b in evs])) * 1e-3
+        bmin, balg = p1_bytes(nv, 3, E, pat.nnz, pat.n_dofs, sz, 2)
+        per_member = E * 2 * sz + pat.nnz * sz + pat.n_dofs * sz
+        b_batch = balg + (B - 1) * per_member  # geometry + routing once, B sets of coefficients/outputs
+        res[name] = {"batched_us": times["batched"] * 1e6, "solo_loop_us": times["solo_loop"] * 1e6,
+                     "speedup": times["solo_loop"] / times["batched"],
+                     "member_elements_per_s": B * E / times["batched"],
+                     "gbs_routing_once": b_batch / times["batched"] / 1e9, "bytes_per_launch": b_batch,
+                     "frac": b_batch / times["batched"] / 1e9 / HBM_PEAK_GBS}
+    out = {"workload": f"3D Poisson P1 64^3 x 6 Kuhn, {B} coefficient sets (a=exp(N(0,1)), f=U(-1,1)) on one "
+                       f"pattern, cold (1 GiB flush before each launch)",
+           "batch": B, "elements": E, "nnz": pat.nnz, **res}
     print(json.dumps(out))
 
 

@@ -218,6 +218,8 @@ tg_status tg_assemble_batched(const tg_pattern *p, tg_form form, tg_dtype dtype,
  *   d_values, d_rhs : device, as written by tg_assemble (modified in place).
  *   d_g             : device [n_dofs] of dtype (only constrained entries are
  *                     read), or NULL for g = 0.
+ * d_values may be NULL when d_g is NULL: then only rhs_b = 0 is written on the
+ * constrained DoFs (the form an implicit step's right-hand side needs).
  */
 tg_status tg_apply_dirichlet(const tg_pattern *p, tg_dtype dtype, void *d_values, void *d_rhs, const void *d_g,
                              void *stream);
@@ -246,6 +248,143 @@ tg_status tg_spmv(const tg_pattern *p, tg_dtype dtype, const void *d_values, con
  */
 tg_status tg_pcg(const tg_pattern *p, tg_dtype dtype, const void *d_values, const void *d_rhs, void *d_x, double rtol,
                  int32_t max_iter, int32_t check_every, int32_t *iters, double *relres, void *stream);
+
+/*
+ * Adjoint of P1 assembly (Sec. 2, eq. adj): the gradient of an assembled
+ * system's bilinear quantity with respect to the element coefficients and the
+ * vertex coordinates, for given adjoint and state vectors.  For members
+ * m = 0 .. nbatch-1 it differentiates
+ *     Phi = scale * sum_m lam_m^T (A u_m - M w_m),
+ * with A = K(c) (TG_LAPLACE), M (TG_MASS) or M + K(c) (TG_MASS_LAPLACE) as
+ * tg_assemble defines them and M the P1 mass matrix (the mass inner product of
+ * SM A.1).  A gradient dL/du = A^T lam through a solve A u = b(w) gives
+ * dL/dtheta = -dPhi/dtheta with scale = 1 (the relation dL/dK = -lam u^T of
+ * eq. adj restricted to the pattern), so scale = -1 returns dL/dtheta.
+ *   form           : TG_LAPLACE, TG_MASS or TG_MASS_LAPLACE on a P1 scalar pattern.
+ *   d_coords       : device FP64 [n_vertices][dim], AoS.
+ *   d_coef         : device [n_elements] of dtype, c_e (ignored for TG_MASS).
+ *   d_lam, d_u     : device [nbatch][stride] of dtype; member m at offset m*stride.
+ *   d_w            : as d_u, or NULL for w = 0.
+ *   stride         : >= n_dofs (elements of dtype between members).
+ *   d_dlogc        : device FP64 [n_elements] out, dPhi/d(log c_e) = scale *
+ *                    sum_m lam_e^T K_e u_e (0 for TG_MASS), or NULL.
+ *   d_dcoords      : device FP64 [n_vertices][dim] out, dPhi/dx, or NULL.
+ *   d_status       : as in tg_assemble (numerically singular elements, non-finite c).
+ * Arithmetic is FP64 for either dtype.  The vertex gradients are reduced over
+ * each vertex's incident elements in ascending element order (no atomics), so
+ * repeated calls give bitwise identical results.  Uses the pattern's scratch
+ * (E*(dim+1)*dim doubles, allocated on first use): calls on one pattern must
+ * not overlap.  Errors: TG_E_ARG (NULL inputs, no output, nbatch < 1,
+ * stride < n_dofs, not P1 scalar, beyond 4 GiB), TG_E_NOMEM, TG_E_HIP.
+ */
+tg_status tg_adjoint_p1(const tg_pattern *p, tg_form form, tg_dtype dtype, int32_t nbatch, const double *d_coords,
+                        const void *d_coef, const void *d_lam, const void *d_u, const void *d_w, int64_t stride,
+                        double scale, double *d_dlogc, double *d_dcoords, int32_t *d_status, void *stream);
+
+/*
+ * Implicit-Euler rollout of the method-of-lines system M U' + K(a) U = 0
+ * (SM A.1, with no semilinear term and no source) on a P1 scalar pattern, U = 0
+ * on the pattern's constrained DoFs:
+ *     (M + dt K(a)) u^{k+1} = M u^k on the free DoFs,  k = 0 .. nsteps-1,
+ * with a_e = exp(log_a_e).  Per step: one SpMV with M, then Jacobi-PCG on
+ * A = M + dt K(a) (both assembled once per call by the Map-Reduce kernels).
+ *   d_coords  : device FP64 [n_vertices][dim].   d_log_a : device FP64 [n_elements].
+ *   d_u0      : device [n_dofs] of dtype (entries on constrained DoFs enter M u^0).
+ *   d_states  : device [nsteps+1][n_dofs] of dtype, out: row k = u^k (row 0 = u^0).
+ *   rtol, max_iter, check_every : per-step PCG controls as in tg_pcg.
+ *   iters     : host out (may be NULL), PCG iterations summed over the steps.
+ *   relres    : host out (may be NULL), the largest true relative residual.
+ *   d_status  : as in tg_assemble.
+ * Blocks until done.  Uses the pattern's scratch and PCG workspace: calls on
+ * one pattern must not overlap.  Errors: as tg_pcg (TG_E_NOCONV stops the
+ * rollout at that step), TG_E_ARG for dt <= 0 or nsteps < 0.
+ */
+tg_status tg_heat_rollout(const tg_pattern *p, tg_dtype dtype, const double *d_coords, const double *d_log_a,
+                          double dt, int32_t nsteps, const void *d_u0, void *d_states, double rtol, int32_t max_iter,
+                          int32_t check_every, int64_t *iters, double *relres, int32_t *d_status, void *stream);
+
+/*
+ * Discrete adjoint (Sec. 2, eq. adj) of tg_heat_rollout for a loss L with
+ * d_g = dL/du^N (N = nsteps).  With A = M + dt K(a):
+ *     A lam^N = g,   A lam^k = M lam^{k+1}  (k = N-1 .. 1)   on the free DoFs,
+ *     dL/dtheta = -sum_k d/dtheta [lam^k^T (A u^k - M u^{k-1})],
+ * evaluated by tg_adjoint_p1 over the N (lam^k, u^k, u^{k-1}) triples in one
+ * launch, and dL/du^0 = M lam^1.
+ *   d_states    : the rollout's [nsteps+1][n_dofs] of dtype (read only).
+ *   d_g         : device [n_dofs] of dtype.
+ *   d_dlog_a    : device FP64 [n_elements] out, dL/d(log a_e), or NULL.
+ *   d_dcoords   : device FP64 [n_vertices][dim] out, dL/dx, or NULL.
+ *   d_du0       : device [n_dofs] of dtype out, dL/du^0, or NULL.
+ * Other arguments, blocking and errors as tg_heat_rollout.
+ */
+tg_status tg_heat_adjoint(const tg_pattern *p, tg_dtype dtype, const double *d_coords, const double *d_log_a,
+                          double dt, int32_t nsteps, const void *d_states, const void *d_g, double *d_dlog_a,
+                          double *d_dcoords, void *d_du0, double rtol, int32_t max_iter, int32_t check_every,
+                          int64_t *iters, double *relres, int32_t *d_status, void *stream);
+
+/*
+ * Request server: continuous batching of assemble + solve requests with
+ * iteration-level scheduling (the batched generation of many PDE instances of
+ * SM B.2, served the way LLM servers batch generation steps).
+ *
+ * A request = assemble (tg_assemble's forms except TG_MASS), eliminate
+ * Dirichlet data (tg_apply_dirichlet, with d_g or g = 0), and solve with
+ * Jacobi-PCG (tg_pcg).  Requests are grouped by (pattern, dtype); a group keeps
+ * up to max_slots systems in one batched CG (one launch pair per iteration for
+ * the whole group).  Each tg_server_step admits queued requests into free
+ * slots (a slot is allocated when the server's HBM budget allows), runs
+ * check_every CG iterations, then retires the converged systems (or those at
+ * max_iter).  A request's solution and iteration count are bitwise the same as
+ * a solo tg_assemble + tg_apply_dirichlet + tg_pcg of it: every slot's
+ * reductions are its own, in the same fixed order.
+ *
+ * Ownership: the server owns the slot buffers (freed by tg_server_destroy).
+ * The caller owns every pointer of a request (coords, coef, load, g, x), which
+ * must stay valid until the request's result has been polled, and the pattern,
+ * which must outlive the server.  All work runs on `stream` (NULL: the default
+ * stream); the server is not thread-safe.
+ */
+typedef struct tg_server tg_server; /* opaque */
+
+typedef struct {
+    int64_t request_id;
+    int32_t status;      /* TG_OK, TG_E_NOCONV, TG_E_DEGENERATE (bad assembly), TG_E_NOMEM (budget too small) */
+    int32_t iters;       /* CG iterations, as tg_pcg reports them */
+    double relres;       /* true relative residual ||b - K x|| / ||b|| */
+    int32_t bad_element; /* first numerically singular element, or -1 */
+    int32_t pad;
+    double t_submit;     /* host seconds since tg_server_create */
+    double t_done;
+} tg_server_result;
+
+typedef struct {
+    int64_t n_queued, n_active, n_slots, n_groups, n_results;
+    size_t hbm_used, hbm_budget;
+} tg_server_info;
+
+/* hbm_budget_bytes: cap on slot memory (per slot: nnz + 7 n_dofs values of the
+ * dtype + 20 KB); max_slots: slots per group (1..65535); check_every: CG
+ * iterations per tg_server_step (>= 1). */
+tg_status tg_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t check_every, void *stream,
+                           tg_server **out);
+
+/* Queue one request (arguments as tg_assemble / tg_apply_dirichlet / tg_pcg;
+ * d_load is required, d_g may be NULL; d_x device [n_dofs] of dtype receives
+ * the solution).  Nothing runs until tg_server_step. */
+tg_status tg_server_submit(tg_server *srv, const tg_pattern *p, tg_form form, tg_dtype dtype, const double *d_coords,
+                           const void *d_coef, const void *d_load, const void *d_g, void *d_x, double rtol,
+                           int32_t max_iter, int64_t *request_id);
+
+/* One scheduling round (blocks until its iterations are done).  Optional outputs: systems in flight, queued. */
+tg_status tg_server_step(tg_server *srv, int32_t *n_active, int32_t *n_queued);
+
+/* Pop up to max_results finished requests, oldest first. */
+tg_status tg_server_poll(tg_server *srv, int32_t max_results, tg_server_result *out, int32_t *n_out);
+
+tg_status tg_server_query(const tg_server *srv, tg_server_info *info);
+
+/* Synchronises the server's stream and frees its slots (NULL is a no-op). */
+void tg_server_destroy(tg_server *srv);
 
 #ifdef __cplusplus
 }

@@ -302,11 +302,20 @@ def heat_matrices(coords, conn, log_a, dt):
     return (M + K).tocsr(), M
 
 
-def _interior_solve(A, mask, b):
-    import scipy.sparse.linalg as spla
-    x = np.zeros(A.shape[0])
-    x[mask] = spla.spsolve(A[mask][:, mask].tocsc(), b[mask])
-    return x
+class _InteriorSolver:
+    """Direct solves with the free-DoF block A[mask][:, mask] (one sparse LU factorisation)."""
+
+    def __init__(self, A, mask):
+        import scipy.sparse.linalg as spla
+        self.mask = mask
+        self.n = A.shape[0]
+        self.lu = spla.splu(A[mask][:, mask].tocsc()) if mask.any() else None
+
+    def __call__(self, b):
+        x = np.zeros(self.n)
+        if self.lu is not None:
+            x[self.mask] = self.lu.solve(np.ascontiguousarray(b[self.mask]))
+        return x
 
 
 def heat_rollout(coords, conn, log_a, u0, dt, nsteps, constrained):
@@ -317,8 +326,9 @@ def heat_rollout(coords, conn, log_a, u0, dt, nsteps, constrained):
     mask[np.asarray(constrained, dtype=np.int64)] = False
     U = np.zeros((nsteps + 1, A.shape[0]))
     U[0] = _f64(u0)
+    solve = _InteriorSolver(A, mask)
     for n in range(nsteps):
-        U[n + 1] = _interior_solve(A, mask, M @ U[n])
+        U[n + 1] = solve(M @ U[n])
     return U
 
 
@@ -329,12 +339,15 @@ def heat_adjoint(coords, conn, log_a, U, dt, g, constrained):
     With Phi_n = lam^n^T (A u^n - M u^{n-1}), every parameter gradient is -sum_n dPhi_n; the
     element terms come from p1_adjoint.  Returns (dL/dlog_a [E], dL/dcoords [nv, d], dL/du0 [nv]).
     """
+    N = U.shape[0] - 1
+    if N == 0:  # u^N = u^0
+        return np.zeros(conn.shape[0]), np.zeros_like(_f64(coords)), _f64(g).copy()
     A, M = heat_matrices(coords, conn, log_a, dt)
     mask = np.ones(A.shape[0], dtype=bool)
     mask[np.asarray(constrained, dtype=np.int64)] = False
-    N = U.shape[0] - 1
     c = dt * np.exp(_f64(log_a))
-    lam = _interior_solve(A, mask, _f64(g))
+    solve = _InteriorSolver(A, mask)
+    lam = solve(_f64(g))
     dloga = np.zeros(conn.shape[0])
     dcoords = np.zeros_like(_f64(coords))
     for n in range(N, 0, -1):
@@ -342,7 +355,7 @@ def heat_adjoint(coords, conn, log_a, U, dt, g, constrained):
         dloga -= dl
         dcoords -= dx
         if n > 1:
-            lam = _interior_solve(A, mask, M @ lam)
+            lam = solve(M @ lam)
     du0 = M @ lam
     return dloga, dcoords, du0
 

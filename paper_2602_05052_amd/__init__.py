@@ -51,6 +51,18 @@ class _Info(ctypes.Structure):
                 ("d_row_ptr", ctypes.c_void_p), ("d_col_idx", ctypes.c_void_p), ("device_bytes", ctypes.c_size_t)]
 
 
+class ServerResult(ctypes.Structure):
+    _fields_ = [("request_id", ctypes.c_int64), ("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("relres", ctypes.c_double), ("bad_element", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class _ServerInfo(ctypes.Structure):
+    _fields_ = [("n_queued", ctypes.c_int64), ("n_active", ctypes.c_int64), ("n_slots", ctypes.c_int64),
+                ("n_groups", ctypes.c_int64), ("n_results", ctypes.c_int64), ("hbm_used", ctypes.c_size_t),
+                ("hbm_budget", ctypes.c_size_t)]
+
+
 _vp, _i32p, _i64, _i32 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, ctypes.c_int32
 _SIGS = {
     "tg_last_error": (ctypes.c_char_p, []),
@@ -71,6 +83,21 @@ _SIGS = {
     "tg_spmv": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "tg_pcg": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, ctypes.c_double, _i32, _i32, _i32p,
                               ctypes.POINTER(ctypes.c_double), _vp]),
+    "tg_adjoint_p1": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i32, _vp, _vp, _vp, _vp, _vp, _i64,
+                                     ctypes.c_double, _vp, _vp, _vp, _vp]),
+    "tg_heat_rollout": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_double, _i32, _vp, _vp,
+                                       ctypes.c_double, _i32, _i32, ctypes.POINTER(_i64),
+                                       ctypes.POINTER(ctypes.c_double), _vp, _vp]),
+    "tg_heat_adjoint": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_double, _i32, _vp, _vp, _vp, _vp,
+                                       _vp, ctypes.c_double, _i32, _i32, ctypes.POINTER(_i64),
+                                       ctypes.POINTER(ctypes.c_double), _vp, _vp]),
+    "tg_server_create": (ctypes.c_int, [ctypes.c_size_t, _i32, _i32, _vp, ctypes.POINTER(_vp)]),
+    "tg_server_submit": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp,
+                                        ctypes.c_double, _i32, ctypes.POINTER(_i64)]),
+    "tg_server_step": (ctypes.c_int, [_vp, _i32p, _i32p]),
+    "tg_server_poll": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ServerResult), _i32p]),
+    "tg_server_query": (ctypes.c_int, [_vp, ctypes.POINTER(_ServerInfo)]),
+    "tg_server_destroy": (None, [_vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -320,12 +347,15 @@ def check_status(status) -> int | None:
 
 
 def apply_dirichlet(pattern: Pattern, values, rhs=None, g=None, stream=None):
-    """Symmetric elimination of the pattern's constrained DoFs, in place (tg_apply_dirichlet)."""
-    torch = _torch()
-    code = _dtype_code(values.dtype)
-    vp = _dev(values, values.dtype, (pattern.nnz,), "values")
-    rp = _dev(rhs, values.dtype, (pattern.n_dofs,), "rhs") if rhs is not None else None
-    gp = _dev(g, values.dtype, (pattern.n_dofs,), "g") if g is not None else None
+    """Symmetric elimination of the pattern's constrained DoFs, in place (tg_apply_dirichlet).
+
+    With values=None (and g=None) only rhs is touched: its constrained entries are set to 0.
+    """
+    ref = values if values is not None else rhs
+    code = _dtype_code(ref.dtype)
+    vp = _dev(values, ref.dtype, (pattern.nnz,), "values") if values is not None else None
+    rp = _dev(rhs, ref.dtype, (pattern.n_dofs,), "rhs") if rhs is not None else None
+    gp = _dev(g, ref.dtype, (pattern.n_dofs,), "g") if g is not None else None
     _check(_lib.tg_apply_dirichlet(pattern.handle, code, vp, rp, gp, _stream_handle(stream)))
     return values, rhs
 
@@ -358,3 +388,176 @@ def pcg(pattern: Pattern, values, rhs, rtol: float = 1e-8, max_iter: int = 10000
     if st != TG_OK and not (st == TG_E_NOCONV and not raise_on_noconv):
         _check(st)
     return x, it.value, rr.value
+
+
+def adjoint_p1(pattern: Pattern, form: int, coords, coef, lam, u, w=None, scale: float = 1.0, dlogc=True,
+               dcoords=True, status=None, stream=None):
+    """Derivatives of Phi = scale * sum_m lam_m^T (A u_m - M w_m) (tg_adjoint_p1).
+
+    lam, u, w : [n_dofs] or [B, n_dofs] tensors of one dtype (w may be None); coef [E] of that dtype
+    (None for MASS).  dlogc / dcoords: True to allocate, a preallocated FP64 tensor, or None/False to
+    skip.  Returns (dlogc [E] or None, dcoords [n_vertices, dim] or None), both FP64.
+    """
+    torch = _torch()
+    code = _dtype_code(lam.dtype)
+    tdt = _torch_dtype(code)
+    n = pattern.n_dofs
+    B = 1 if lam.dim() == 1 else lam.shape[0]
+    shape = (n,) if lam.dim() == 1 else (B, n)
+    cp = _dev(coords, torch.float64, (pattern.n_vertices, pattern.dim), "coords")
+    coef_p = _dev(coef, tdt, (pattern.n_elements,), "coef") if form != MASS else None
+    lp = _dev(lam, tdt, shape, "lam")
+    up = _dev(u, tdt, shape, "u")
+    wp = _dev(w, tdt, shape, "w") if w is not None else None
+    dev = coords.device
+    if dlogc is True:
+        dlogc = torch.empty(pattern.n_elements, dtype=torch.float64, device=dev)
+    if dcoords is True:
+        dcoords = torch.empty(pattern.n_vertices, pattern.dim, dtype=torch.float64, device=dev)
+    dlp = _dev(dlogc, torch.float64, (pattern.n_elements,), "dlogc") if dlogc is not None and dlogc is not False else None
+    dxp = (_dev(dcoords, torch.float64, (pattern.n_vertices, pattern.dim), "dcoords")
+           if dcoords is not None and dcoords is not False else None)
+    sp = _dev(status, torch.int32, (1,), "status") if status is not None else None
+    _check(_lib.tg_adjoint_p1(pattern.handle, form, code, B, cp, coef_p, lp, up, wp, n, float(scale), dlp, dxp, sp,
+                              _stream_handle(stream)))
+    return (dlogc if dlp is not None else None), (dcoords if dxp is not None else None)
+
+
+def heat_rollout(pattern: Pattern, coords, log_a, u0, dt: float, nsteps: int, rtol: float = 1e-10,
+                 max_iter: int = 10000, check_every: int = 10, states=None, status=None, stream=None):
+    """Implicit-Euler rollout (tg_heat_rollout).  u0 [n_dofs] of the compute dtype; returns
+    (states [nsteps+1, n_dofs], total PCG iterations, worst true relative residual)."""
+    torch = _torch()
+    code = _dtype_code(u0.dtype)
+    n = pattern.n_dofs
+    cp = _dev(coords, torch.float64, (pattern.n_vertices, pattern.dim), "coords")
+    ap = _dev(log_a, torch.float64, (pattern.n_elements,), "log_a")
+    up = _dev(u0, u0.dtype, (n,), "u0")
+    if states is None:
+        states = torch.empty(nsteps + 1, n, dtype=u0.dtype, device=u0.device)
+    xp = _dev(states, u0.dtype, (nsteps + 1, n), "states")
+    sp = _dev(status, torch.int32, (1,), "status") if status is not None else None
+    it = ctypes.c_int64(0)
+    rr = ctypes.c_double(0.0)
+    _check(_lib.tg_heat_rollout(pattern.handle, code, cp, ap, float(dt), int(nsteps), up, xp, float(rtol),
+                                int(max_iter), int(check_every), ctypes.byref(it), ctypes.byref(rr), sp,
+                                _stream_handle(stream)))
+    return states, it.value, rr.value
+
+
+def heat_adjoint(pattern: Pattern, coords, log_a, states, g, dt: float, rtol: float = 1e-10, max_iter: int = 10000,
+                 check_every: int = 10, want=(True, True, True), status=None, stream=None):
+    """Discrete adjoint of heat_rollout for dL/du^N = g (tg_heat_adjoint).  Returns
+    (dL/dlog_a [E] FP64, dL/dcoords [n_vertices, dim] FP64, dL/du0 [n_dofs] of the dtype, iters, relres);
+    outputs not asked for in `want` come back as None."""
+    torch = _torch()
+    code = _dtype_code(states.dtype)
+    n = pattern.n_dofs
+    nsteps = states.shape[0] - 1
+    dev = coords.device
+    cp = _dev(coords, torch.float64, (pattern.n_vertices, pattern.dim), "coords")
+    ap = _dev(log_a, torch.float64, (pattern.n_elements,), "log_a")
+    xp = _dev(states, states.dtype, (nsteps + 1, n), "states")
+    gp = _dev(g, states.dtype, (n,), "g")
+    dla = torch.empty(pattern.n_elements, dtype=torch.float64, device=dev) if want[0] else None
+    dx = torch.empty(pattern.n_vertices, pattern.dim, dtype=torch.float64, device=dev) if want[1] else None
+    du0 = torch.empty(n, dtype=states.dtype, device=dev) if want[2] else None
+    sp = _dev(status, torch.int32, (1,), "status") if status is not None else None
+    it = ctypes.c_int64(0)
+    rr = ctypes.c_double(0.0)
+    _check(_lib.tg_heat_adjoint(pattern.handle, code, cp, ap, float(dt), int(nsteps), xp, gp,
+                                dla.data_ptr() if dla is not None else None,
+                                dx.data_ptr() if dx is not None else None,
+                                du0.data_ptr() if du0 is not None else None, float(rtol), int(max_iter),
+                                int(check_every), ctypes.byref(it), ctypes.byref(rr), sp, _stream_handle(stream)))
+    return dla, dx, du0, it.value, rr.value
+
+
+class Server:
+    """Continuous-batching request server (tg_server_*): assemble + Dirichlet + PCG requests, grouped by
+    (pattern, dtype) into batched CG launches; requests join and leave between iterations.
+
+        srv = Server(hbm_budget=8 << 30, max_slots=16, check_every=10)
+        rid = srv.submit(pat, LAPLACE, coords, a, f, x=x)   # x receives the solution
+        while srv.pending(): srv.step()
+        for r in srv.poll(): ...                           # dicts: request_id, status, iters, relres, ...
+
+    Every tensor handed to submit() is kept referenced until its result is polled.
+    """
+
+    def __init__(self, hbm_budget: int = 8 << 30, max_slots: int = 16, check_every: int = 10, stream=None):
+        self._h = _vp()
+        self._stream = stream
+        _check(_lib.tg_server_create(int(hbm_budget), int(max_slots), int(check_every), _stream_handle(stream),
+                                     ctypes.byref(self._h)))
+        self._keep = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.tg_server_destroy(h)
+            self._h = None
+
+    def submit(self, pattern: Pattern, form: int, coords, coef, load, x=None, g=None, rtol: float = 1e-8,
+               max_iter: int = 10000, dtype=None) -> int:
+        torch = _torch()
+        if dtype is None:
+            dtype = coef.dtype
+        code = _dtype_code(dtype)
+        tdt = _torch_dtype(code)
+        E = pattern.n_elements
+        cp = _dev(coords, torch.float64, (pattern.n_vertices, pattern.dim), "coords")
+        if form == ELASTICITY:
+            coef_p = _dev(coef, tdt, (2, E), "coef")
+            load_p = _dev(load, tdt, (E, 3), "load")
+        else:
+            coef_p = _dev(coef, tdt, (E,), "coef")
+            load_p = _dev(load, tdt, (E,), "load")
+        if x is None:
+            x = torch.empty(pattern.n_dofs, dtype=tdt, device=coords.device)
+        xp = _dev(x, tdt, (pattern.n_dofs,), "x")
+        gp = _dev(g, tdt, (pattern.n_dofs,), "g") if g is not None else None
+        rid = ctypes.c_int64(0)
+        _check(_lib.tg_server_submit(self._h, pattern.handle, form, code, cp, coef_p, load_p, gp, xp, float(rtol),
+                                     int(max_iter), ctypes.byref(rid)))
+        self._keep[rid.value] = (pattern, coords, coef, load, g, x)
+        return rid.value
+
+    def solution(self, request_id: int):
+        return self._keep[request_id][5]
+
+    def step(self):
+        """One scheduling round; returns (systems in flight, queued requests)."""
+        a, q = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(_lib.tg_server_step(self._h, ctypes.byref(a), ctypes.byref(q)))
+        return a.value, q.value
+
+    def info(self) -> dict:
+        i = _ServerInfo()
+        _check(_lib.tg_server_query(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in _ServerInfo._fields_}
+
+    def pending(self) -> bool:
+        i = self.info()
+        return i["n_queued"] + i["n_active"] > 0
+
+    def poll(self, max_results: int = 1024, release: bool = True):
+        """Finished requests as dicts (the solution tensor under "x")."""
+        buf = (ServerResult * max_results)()
+        n = ctypes.c_int32(0)
+        _check(_lib.tg_server_poll(self._h, max_results, buf, ctypes.byref(n)))
+        out = []
+        for r in buf[:n.value]:
+            d = {f: getattr(r, f) for f, _ in ServerResult._fields_ if f != "pad"}
+            keep = self._keep.pop(r.request_id) if release else self._keep[r.request_id]
+            d["x"] = keep[5]
+            out.append(d)
+        return out
+
+    def drain(self):
+        """Step until nothing is queued or in flight; returns every result."""
+        res = []
+        while self.pending():
+            self.step()
+            res += self.poll()
+        return res + self.poll()

@@ -1,6 +1,7 @@
 // C ABI of libtg (declared in include/tg.h): argument checks, device upload
 // of the pattern, and dispatch to the kernels.  Nothing here throws across
 // the ABI: every entry point catches and converts to a tg_status.
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -34,10 +35,12 @@ hipError_t upload(const std::vector<V> &h, V **d, size_t &bytes) {
 void free_device(tg::DevicePattern &d) {
     void *ptrs[] = {d.conn,    d.inc_ptr, d.inc,      d.blk_row,     d.blk_desc, d.node_rp, d.node_ci, d.seg_ptr,
                     d.slot,    d.row_ptr, d.col_idx,  d.diag_pos,    d.constrained,
-                    d.work,    d.partials, d.state, d.dir_rows};
+                    d.work,    d.partials, d.state, d.dir_rows,  d.pcg_slot, d.pcg_list};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    if (d.ws) (void)hipFree(d.ws);
     if (d.host_state) (void)hipHostFree(d.host_state);
+    if (d.host_pcg_slot) (void)hipHostFree(d.host_pcg_slot);
     d = tg::DevicePattern{};
 }
 
@@ -80,6 +83,19 @@ tg_status create_device(tg_pattern &pt) {
         bytes += sizeof(PcgState);
     }
     if (e == hipSuccess) e = hipHostMalloc((void **)&d.host_state, sizeof(PcgState), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&d.host_pcg_slot, sizeof(PcgSlot), hipHostMallocDefault);
+    if (e == hipSuccess) {
+        e = hipMalloc((void **)&d.pcg_slot, sizeof(PcgSlot));
+        bytes += sizeof(PcgSlot);
+    }
+    if (e == hipSuccess) {
+        e = hipMalloc((void **)&d.pcg_list, sizeof(int32_t));
+        bytes += sizeof(int32_t);
+    }
+    if (e == hipSuccess) {
+        const int32_t zero = 0;
+        e = hipMemcpy(d.pcg_list, &zero, sizeof(int32_t), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         const tg_status st = (e == hipErrorOutOfMemory) ? TG_E_NOMEM : TG_E_HIP;
         const std::string msg = std::string("device setup of the pattern failed: ") + hipGetErrorString(e);
@@ -207,9 +223,16 @@ void tg_pattern_destroy(tg_pattern *p) {
     delete p;
 }
 
-static tg_status assemble_impl(const tg_pattern *p, tg_form form, tg_dtype dtype, int32_t nbatch,
-                               const double *d_coords, const void *d_coef, const void *d_load, void *d_values,
-                               void *d_rhs, int32_t *d_status, void *stream) {
+}  // extern "C"
+
+namespace tg {
+
+tg_status api_fail(tg_status st, const std::string &msg) { return fail(st, msg); }
+tg_status api_ok() { return ok(); }
+tg_status api_check_pattern(const tg_pattern *p) { return check_device_pattern(p); }
+
+tg_status validate_assemble(const tg_pattern *p, tg_form form, tg_dtype dtype, int32_t nbatch, const double *d_coords,
+                            const void *d_coef, const void *d_values) {
     tg_status st = check_device_pattern(p);
     if (st != TG_OK) return st;
     if (!valid_dtype(dtype)) return fail(TG_E_ARG, "invalid dtype");
@@ -222,25 +245,47 @@ static tg_status assemble_impl(const tg_pattern *p, tg_form form, tg_dtype dtype
     if (nb * h.nnz * elt >= lim || (uint64_t)h.nv * h.dim * 8 >= lim || nb * h.E * 5 * elt >= lim ||
         nb * h.n_dofs * elt >= lim || (uint64_t)h.E * h.k * h.k * 2 >= lim)
         return fail(TG_E_ARG, "an array of this call exceeds 4 GiB, beyond the kernels' 32-bit offsets");
-    hipError_t e;
     if (form == TG_LAPLACE || form == TG_MASS || form == TG_MASS_LAPLACE) {
         if (!scalar_p1) return fail(TG_E_ARG, "LAPLACE, MASS and MASS_LAPLACE need a P1 scalar pattern (order 1, ncomp 1)");
         if (form != TG_MASS && !d_coef) return fail(TG_E_ARG, "this form needs d_coef");
         if (form == TG_MASS && nbatch != 1) return fail(TG_E_ARG, "MASS has no coefficients to batch");
-        e = tg::launch_assemble_p1(*p, form, dtype, nbatch, d_coords, d_coef, form == TG_MASS ? nullptr : d_load,
-                                   d_values, d_rhs, d_status, (hipStream_t)stream);
     } else if (form == TG_ELASTICITY) {
         if (h.order != 2 || h.ncomp != 3) return fail(TG_E_ARG, "ELASTICITY needs a P2 vector pattern (3, 2, 3)");
         if (!d_coef) return fail(TG_E_ARG, "ELASTICITY needs d_coef (lambda, mu)");
         if (nbatch != 1) return fail(TG_E_ARG, "batched ELASTICITY is not supported");
-        e = tg::launch_assemble_p2(*p, dtype, d_coords, d_coef, d_load, d_values, d_rhs, d_status,
-                                   (hipStream_t)stream);
     } else {
         return fail(TG_E_ARG, "invalid form");
     }
+    return TG_OK;
+}
+
+hipError_t launch_assemble(const tg_pattern *p, tg_form form, tg_dtype dtype, int32_t nbatch, const double *d_coords,
+                           const void *d_coef, const void *d_load, void *d_values, void *d_rhs, int32_t *d_status,
+                           hipStream_t s) {
+    if (form == TG_ELASTICITY)
+        return tg::launch_assemble_p2(*p, dtype, d_coords, d_coef, d_load, d_values, d_rhs, d_status, s);
+    return tg::launch_assemble_p1(*p, form, dtype, nbatch, d_coords, d_coef, form == TG_MASS ? nullptr : d_load,
+                                  d_values, d_rhs, d_status, s);
+}
+
+}  // namespace tg
+
+namespace {
+
+tg_status assemble_impl(const tg_pattern *p, tg_form form, tg_dtype dtype, int32_t nbatch, const double *d_coords,
+                        const void *d_coef, const void *d_load, void *d_values, void *d_rhs, int32_t *d_status,
+                        void *stream) {
+    const tg_status st = tg::validate_assemble(p, form, dtype, nbatch, d_coords, d_coef, d_values);
+    if (st != TG_OK) return st;
+    const hipError_t e = tg::launch_assemble(p, form, dtype, nbatch, d_coords, d_coef, d_load, d_values, d_rhs,
+                                             d_status, (hipStream_t)stream);
     if (e != hipSuccess) return fail(TG_E_HIP, std::string("assembly launch failed: ") + hipGetErrorString(e));
     return ok();
 }
+
+}  // namespace
+
+extern "C" {
 
 tg_status tg_assemble(const tg_pattern *p, tg_form form, tg_dtype dtype, const double *d_coords, const void *d_coef,
                       const void *d_load, void *d_values, void *d_rhs, int32_t *d_status, void *stream) {
@@ -260,7 +305,7 @@ tg_status tg_apply_dirichlet(const tg_pattern *p, tg_dtype dtype, void *d_values
     tg_status st = check_device_pattern(p);
     if (st != TG_OK) return st;
     if (!valid_dtype(dtype)) return fail(TG_E_ARG, "invalid dtype");
-    if (!d_values) return fail(TG_E_ARG, "d_values is required");
+    if (!d_values && (d_g || !d_rhs)) return fail(TG_E_ARG, "d_values is required unless only d_rhs is given");
     const hipError_t e = tg::launch_dirichlet(*p, dtype, d_values, d_rhs, d_g, (hipStream_t)stream);
     if (e != hipSuccess) return fail(TG_E_HIP, std::string("dirichlet launch failed: ") + hipGetErrorString(e));
     return ok();
@@ -288,6 +333,215 @@ tg_status tg_pcg(const tg_pattern *p, tg_dtype dtype, const void *d_values, cons
     st = tg::run_pcg(*p, dtype, d_values, d_rhs, d_x, rtol, max_iter, check_every, iters, relres,
                      (hipStream_t)stream, msg);
     if (st != TG_OK) return fail(st, msg);
+    return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- adjoint and heat rollout
+
+namespace {
+
+// Grows the pattern's scratch to at least `bytes` (previous contents are lost).
+tg_status ensure_workspace(const tg_pattern *p, size_t bytes) {
+    tg::DevicePattern &d = const_cast<tg_pattern *>(p)->dev;
+    if (d.ws_bytes >= bytes) return TG_OK;
+    if (d.ws) (void)hipFree(d.ws);
+    d.ws = nullptr;
+    d.ws_bytes = 0;
+    const hipError_t e = hipMalloc(&d.ws, bytes);
+    if (e != hipSuccess) {
+        d.ws = nullptr;
+        return fail(e == hipErrorOutOfMemory ? TG_E_NOMEM : TG_E_HIP,
+                    std::string("workspace allocation failed: ") + hipGetErrorString(e));
+    }
+    d.ws_bytes = bytes;
+    return TG_OK;
+}
+
+// Consecutive 256-byte aligned pieces of one allocation.
+struct Carve {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return at;
+    }
+};
+
+bool p1_scalar(const tg_pattern *p) { return p->host.order == 1 && p->host.ncomp == 1; }
+
+tg_status check_heat(const tg_pattern *p, tg_dtype dtype, const double *d_coords, const double *d_log_a, double dt,
+                     int32_t nsteps, double rtol, int32_t max_iter, int32_t check_every) {
+    tg_status st = check_device_pattern(p);
+    if (st != TG_OK) return st;
+    if (!valid_dtype(dtype)) return fail(TG_E_ARG, "invalid dtype");
+    if (!p1_scalar(p)) return fail(TG_E_ARG, "the heat rollout needs a P1 scalar pattern (order 1, ncomp 1)");
+    if (!d_coords || !d_log_a) return fail(TG_E_ARG, "d_coords and d_log_a are required");
+    if (!(dt > 0.0) || nsteps < 0) return fail(TG_E_ARG, "need dt > 0 and nsteps >= 0");
+    if (!(rtol > 0.0) || max_iter < 1 || check_every < 1)
+        return fail(TG_E_ARG, "need rtol > 0, max_iter >= 1, check_every >= 1");
+    const tg::HostPattern &h = p->host;
+    const uint64_t elt = dtype == TG_F64 ? 8 : 4, lim = (uint64_t)1 << 32;
+    if ((uint64_t)(nsteps + 1) * h.n_dofs * elt >= lim || (uint64_t)h.nnz * elt >= lim ||
+        (uint64_t)h.E * h.k * h.dim * 8 >= lim || (uint64_t)h.nv * h.dim * 8 >= lim)
+        return fail(TG_E_ARG, "an array of this call exceeds 4 GiB, beyond the kernels' 32-bit offsets");
+    return TG_OK;
+}
+
+// Coefficient c = dt exp(log_a), then M and A = M + K(c) with Dirichlet rows/columns in A.
+hipError_t heat_matrices(const tg_pattern *p, tg_dtype dtype, const double *coords, const double *log_a, double dt,
+                         void *coef, void *vals_m, void *vals_a, int32_t *status, hipStream_t s) {
+    hipError_t e = tg::launch_scaled_exp(dtype, p->host.E, dt, log_a, coef, s);
+    if (e == hipSuccess)
+        e = tg::launch_assemble_p1(*p, TG_MASS, dtype, 1, coords, nullptr, nullptr, vals_m, nullptr, status, s);
+    if (e == hipSuccess)
+        e = tg::launch_assemble_p1(*p, TG_MASS_LAPLACE, dtype, 1, coords, coef, nullptr, vals_a, nullptr, status,
+                                   s);
+    if (e == hipSuccess) e = tg::launch_dirichlet(*p, dtype, vals_a, nullptr, nullptr, s);
+    return e;
+}
+
+// One implicit solve A x = rhs on the free DoFs (rhs is zeroed on the constrained ones first).
+tg_status heat_solve(const tg_pattern *p, tg_dtype dtype, const void *vals_a, void *rhs, void *x, double rtol,
+                     int32_t max_iter, int32_t check_every, int64_t &iters, double &worst, hipStream_t s) {
+    hipError_t e = tg::launch_dirichlet(*p, dtype, nullptr, rhs, nullptr, s);
+    if (e != hipSuccess) return fail(TG_E_HIP, std::string("dirichlet launch failed: ") + hipGetErrorString(e));
+    int32_t it = 0;
+    double rr = 0.0;
+    std::string msg;
+    const tg_status st = tg::run_pcg(*p, dtype, vals_a, rhs, x, rtol, max_iter, check_every, &it, &rr, s, msg);
+    iters += it;
+    if (rr > worst) worst = rr;
+    if (st != TG_OK) return fail(st, msg);
+    return TG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tg_status tg_adjoint_p1(const tg_pattern *p, tg_form form, tg_dtype dtype, int32_t nbatch, const double *d_coords,
+                        const void *d_coef, const void *d_lam, const void *d_u, const void *d_w, int64_t stride,
+                        double scale, double *d_dlogc, double *d_dcoords, int32_t *d_status, void *stream) {
+    tg_status st = check_device_pattern(p);
+    if (st != TG_OK) return st;
+    if (!valid_dtype(dtype)) return fail(TG_E_ARG, "invalid dtype");
+    if (!p1_scalar(p)) return fail(TG_E_ARG, "tg_adjoint_p1 needs a P1 scalar pattern (order 1, ncomp 1)");
+    if (form != TG_LAPLACE && form != TG_MASS && form != TG_MASS_LAPLACE) return fail(TG_E_ARG, "invalid form");
+    if (!d_coords || !d_lam || !d_u) return fail(TG_E_ARG, "d_coords, d_lam and d_u are required");
+    if (form != TG_MASS && !d_coef) return fail(TG_E_ARG, "this form needs d_coef");
+    if (!d_dlogc && !d_dcoords) return fail(TG_E_ARG, "nothing to compute: d_dlogc and d_dcoords are NULL");
+    const tg::HostPattern &h = p->host;
+    if (nbatch < 1) return fail(TG_E_ARG, "nbatch must be >= 1");
+    if (stride < h.n_dofs) return fail(TG_E_ARG, "stride must be >= n_dofs");
+    const uint64_t elt = dtype == TG_F64 ? 8 : 4, lim = (uint64_t)1 << 32;
+    if (((uint64_t)(nbatch - 1) * stride + h.n_dofs) * elt >= lim || (uint64_t)h.E * h.k * h.dim * 8 >= lim ||
+        (uint64_t)h.nv * h.dim * 8 >= lim)
+        return fail(TG_E_ARG, "an array of this call exceeds 4 GiB, beyond the kernels' 32-bit offsets");
+    st = ensure_workspace(p, std::max<size_t>(256, (size_t)h.E * h.k * h.dim * sizeof(double)));
+    if (st != TG_OK) return st;
+    const hipError_t e =
+        tg::launch_adjoint_p1(*p, form, dtype, nbatch, d_coords, d_coef, d_lam, d_u, d_w, stride, scale, d_dlogc,
+                              d_dcoords, (double *)p->dev.ws, d_status, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(TG_E_HIP, std::string("adjoint launch failed: ") + hipGetErrorString(e));
+    return ok();
+}
+
+tg_status tg_heat_rollout(const tg_pattern *p, tg_dtype dtype, const double *d_coords, const double *d_log_a,
+                          double dt, int32_t nsteps, const void *d_u0, void *d_states, double rtol, int32_t max_iter,
+                          int32_t check_every, int64_t *iters, double *relres, int32_t *d_status, void *stream) {
+    tg_status st = check_heat(p, dtype, d_coords, d_log_a, dt, nsteps, rtol, max_iter, check_every);
+    if (st != TG_OK) return st;
+    if (!d_u0 || !d_states) return fail(TG_E_ARG, "d_u0 and d_states are required");
+    const tg::HostPattern &h = p->host;
+    const size_t elt = dtype == TG_F64 ? 8 : 4, n = (size_t)h.n_dofs;
+    Carve cv;
+    const size_t o_coef = cv.take(h.E * elt), o_m = cv.take(h.nnz * elt), o_a = cv.take(h.nnz * elt),
+                 o_rhs = cv.take(n * elt);
+    st = ensure_workspace(p, cv.off);
+    if (st != TG_OK) return st;
+    char *ws = (char *)p->dev.ws;
+    const hipStream_t s = (hipStream_t)stream;
+    char *states = (char *)d_states;
+    hipError_t e = hipMemcpyAsync(states, d_u0, n * elt, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && nsteps > 0)
+        e = heat_matrices(p, dtype, d_coords, d_log_a, dt, ws + o_coef, ws + o_m, ws + o_a, d_status, s);
+    if (e != hipSuccess) return fail(TG_E_HIP, std::string("heat setup failed: ") + hipGetErrorString(e));
+    int64_t it = 0;
+    double worst = 0.0;
+    for (int32_t k = 0; k < nsteps; ++k) {
+        e = tg::launch_spmv(*p, dtype, ws + o_m, states + (size_t)k * n * elt, ws + o_rhs, s);
+        if (e != hipSuccess) return fail(TG_E_HIP, std::string("spmv launch failed: ") + hipGetErrorString(e));
+        st = heat_solve(p, dtype, ws + o_a, ws + o_rhs, states + (size_t)(k + 1) * n * elt, rtol, max_iter,
+                        check_every, it, worst, s);
+        if (st != TG_OK) break;
+    }
+    if (iters) *iters = it;
+    if (relres) *relres = worst;
+    return st == TG_OK ? ok() : st;
+}
+
+tg_status tg_heat_adjoint(const tg_pattern *p, tg_dtype dtype, const double *d_coords, const double *d_log_a,
+                          double dt, int32_t nsteps, const void *d_states, const void *d_g, double *d_dlog_a,
+                          double *d_dcoords, void *d_du0, double rtol, int32_t max_iter, int32_t check_every,
+                          int64_t *iters, double *relres, int32_t *d_status, void *stream) {
+    tg_status st = check_heat(p, dtype, d_coords, d_log_a, dt, nsteps, rtol, max_iter, check_every);
+    if (st != TG_OK) return st;
+    if (!d_states || !d_g) return fail(TG_E_ARG, "d_states and d_g are required");
+    if (!d_dlog_a && !d_dcoords && !d_du0) return fail(TG_E_ARG, "no output requested");
+    const tg::HostPattern &h = p->host;
+    const size_t elt = dtype == TG_F64 ? 8 : 4, n = (size_t)h.n_dofs;
+    const hipStream_t s = (hipStream_t)stream;
+    if (iters) *iters = 0;
+    if (relres) *relres = 0.0;
+    if (nsteps == 0) {  // u^N = u^0: the gradient is g itself
+        hipError_t e = hipSuccess;
+        if (d_dlog_a && h.E) e = hipMemsetAsync(d_dlog_a, 0, h.E * sizeof(double), s);
+        if (e == hipSuccess && d_dcoords && h.nv) e = hipMemsetAsync(d_dcoords, 0, h.nv * h.dim * sizeof(double), s);
+        if (e == hipSuccess && d_du0) e = hipMemcpyAsync(d_du0, d_g, n * elt, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return fail(TG_E_HIP, std::string("copy failed: ") + hipGetErrorString(e));
+        return ok();
+    }
+    Carve cv;
+    const size_t o_coef = cv.take(h.E * elt), o_m = cv.take(h.nnz * elt), o_a = cv.take(h.nnz * elt),
+                 o_rhs = cv.take(n * elt), o_lam = cv.take((size_t)nsteps * n * elt),
+                 o_scr = cv.take((size_t)h.E * h.k * h.dim * sizeof(double));
+    st = ensure_workspace(p, cv.off);
+    if (st != TG_OK) return st;
+    char *ws = (char *)p->dev.ws;
+    char *lam = ws + o_lam;  // lam[k] holds lambda^{k+1}
+    hipError_t e = heat_matrices(p, dtype, d_coords, d_log_a, dt, ws + o_coef, ws + o_m, ws + o_a, d_status, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ws + o_rhs, d_g, n * elt, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return fail(TG_E_HIP, std::string("heat setup failed: ") + hipGetErrorString(e));
+    int64_t it = 0;
+    double worst = 0.0;
+    // A lambda^N = g;  A lambda^k = M lambda^{k+1}  (A and M symmetric)
+    st = heat_solve(p, dtype, ws + o_a, ws + o_rhs, lam + (size_t)(nsteps - 1) * n * elt, rtol, max_iter,
+                    check_every, it, worst, s);
+    for (int32_t k = nsteps - 1; st == TG_OK && k >= 1; --k) {
+        e = tg::launch_spmv(*p, dtype, ws + o_m, lam + (size_t)k * n * elt, ws + o_rhs, s);
+        if (e != hipSuccess) {
+            st = fail(TG_E_HIP, std::string("spmv launch failed: ") + hipGetErrorString(e));
+            break;
+        }
+        st = heat_solve(p, dtype, ws + o_a, ws + o_rhs, lam + (size_t)(k - 1) * n * elt, rtol, max_iter,
+                        check_every, it, worst, s);
+    }
+    if (iters) *iters = it;
+    if (relres) *relres = worst;
+    if (st != TG_OK) return st;
+    // dL/dtheta = -sum_k dPhi_k/dtheta with Phi_k = lambda^k^T (A u^k - M u^{k-1})
+    if (d_dlog_a || d_dcoords) {
+        e = tg::launch_adjoint_p1(*p, TG_MASS_LAPLACE, dtype, nsteps, d_coords, ws + o_coef, lam,
+                                  (const char *)d_states + n * elt, d_states, (int64_t)n, -1.0, d_dlog_a, d_dcoords,
+                                  (double *)(ws + o_scr), d_status, s);
+        if (e != hipSuccess) return fail(TG_E_HIP, std::string("adjoint launch failed: ") + hipGetErrorString(e));
+    }
+    if (d_du0) {  // dL/du^0 = M lambda^1
+        e = tg::launch_spmv(*p, dtype, ws + o_m, lam, d_du0, s);
+        if (e != hipSuccess) return fail(TG_E_HIP, std::string("spmv launch failed: ") + hipGetErrorString(e));
+    }
     return ok();
 }
 

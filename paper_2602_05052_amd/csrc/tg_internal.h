@@ -75,6 +75,21 @@ struct PcgState {
     int32_t iters;  // iteration at which it held
 };
 
+// One CG system in flight.  The solo solver (tg_pcg) uses one; the request
+// server one per slot.  Lives in device memory; the kernels of a batched
+// launch read slots[list[blockIdx.y]].
+struct PcgSlot {
+    const void *values;  // T[nnz], Dirichlet applied
+    const void *b;       // T[n]
+    void *x;             // T[n], the iterate (output)
+    void *work;          // T[6n]: r, z, pA, pB, q, dinv
+    double *partials;    // [kNumPartials][kMaxGrid]
+    PcgState *state;
+    double rtol2;
+    int32_t start;       // launch step of this system's iteration 0 (iteration = step - start)
+    int32_t max_iter;    // no update past this iteration (the stop test still runs there)
+};
+
 constexpr int kVecThreads = 1024;  // threads per block of the PCG kernels
 constexpr int kMaxGrid = 512;      // blocks of the PCG kernels (grid-stride beyond): 2 per CU
 // Per-block partial sums of the PCG kernels: [PQ | RZ0 | RZ1 | RR | BB], kMaxGrid doubles each.
@@ -101,7 +116,13 @@ struct DevicePattern {
     int64_t n_dir_rows = 0;
     PcgState *state = nullptr;
     PcgState *host_state = nullptr;  // pinned mirror
+    PcgSlot *pcg_slot = nullptr;       // the solo solver's slot (device) ...
+    PcgSlot *host_pcg_slot = nullptr;  // ... and its pinned staging copy
+    int32_t *pcg_list = nullptr;       // device {0}
     size_t bytes = 0;
+    // Scratch for the adjoint and the heat rollout, grown on demand (ensure_workspace).
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
     int spmv_group = 4;  // lanes per CSR row in the SpMV
     int n_cu = 1;        // compute units of the pattern's device (persistent grids)
 };
@@ -126,6 +147,34 @@ hipError_t launch_dirichlet(const tg_pattern &p, tg_dtype dtype, void *values, v
                             hipStream_t s);
 hipError_t launch_spmv(const tg_pattern &p, tg_dtype dtype, const void *values, const void *x, void *y,
                        hipStream_t s);
+// Adjoint of P1 assembly (tg_adjoint.hip): dlogc [E] (may be NULL) and dcoords [nv][dim]
+// (may be NULL) of scale * sum_m lam_m^T (A u_m - M w_m); scratch holds E*(dim+1)*dim doubles.
+hipError_t launch_adjoint_p1(const tg_pattern &p, tg_form form, tg_dtype dtype, int nbatch, const double *coords,
+                             const void *coef, const void *lam, const void *u, const void *w, int64_t stride,
+                             double scale, double *dlogc, double *dcoords, double *scratch, int32_t *status,
+                             hipStream_t s);
+// y[i] = dt * exp(x[i]) in dtype (FP64 input).
+hipError_t launch_scaled_exp(tg_dtype dtype, int64_t n, double dt, const double *x, void *y, hipStream_t s);
+// Batched PCG over the slots listed in `list` (device int32[count]); every slot
+// holds a system on pattern p in dtype.  Iteration = launch: one pcg_spmv and
+// one pcg_update launch per step (tg_solve.hip).
+hipError_t launch_pcg_init(const tg_pattern &p, tg_dtype dtype, const PcgSlot *slots, const int32_t *list, int count,
+                           hipStream_t s);
+hipError_t launch_pcg_step(const tg_pattern &p, tg_dtype dtype, const PcgSlot *slots, const int32_t *list, int count,
+                           int step, hipStream_t s);
+// Per-block partials of ||b - K x||^2 into each listed slot's RR partials; returns the block count.
+hipError_t launch_pcg_residual(const tg_pattern &p, tg_dtype dtype, const PcgSlot *slots, const int32_t *list,
+                               int count, int *n_partials, hipStream_t s);
+// ABI helpers shared by the entry-point files (tg_api.cpp): the thread's last
+// error message, pattern and argument checks, and the assembly dispatch.
+tg_status api_fail(tg_status st, const std::string &msg);
+tg_status api_ok();
+tg_status api_check_pattern(const tg_pattern *p);
+tg_status validate_assemble(const tg_pattern *p, tg_form form, tg_dtype dtype, int32_t nbatch, const double *d_coords,
+                            const void *d_coef, const void *d_values);
+hipError_t launch_assemble(const tg_pattern *p, tg_form form, tg_dtype dtype, int32_t nbatch, const double *d_coords,
+                           const void *d_coef, const void *d_load, void *d_values, void *d_rhs, int32_t *d_status,
+                           hipStream_t s);
 // Runs the whole PCG; returns TG_OK / TG_E_NOCONV / TG_E_HIP with *msg on failure.
 tg_status run_pcg(const tg_pattern &p, tg_dtype dtype, const void *values, const void *rhs, void *x, double rtol,
                   int32_t max_iter, int32_t check_every, int32_t *iters, double *relres, hipStream_t s,

@@ -21,7 +21,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 
 
 def test_library_exports_every_declared_symbol():
-    decl = set(re.findall(r"^(?:const char \*|tg_status |void )(tg_[a-z_]+)\(", open(HEADER).read(), re.M))
+    decl = set(re.findall(r"^(?:const char \*|tg_status |void )(tg_[a-z0-9_]+)\(", open(HEADER).read(), re.M))
     assert decl, "no declarations found"
     lib = ctypes.CDLL(tg.library_path())
     for name in decl:
@@ -176,6 +176,15 @@ def test_argument_errors():
     st = tg._lib.tg_assemble(pat.handle, tg.LAPLACE, tg.F64, 8, 8, 8, 8, 8, None, None)
     assert st == tg.TG_E_STATE
     assert tg._lib.tg_pcg(pat.handle, tg.F64, 8, 8, 8, 1e-8, 10, 1, None, None, None) == tg.TG_E_STATE
+    assert tg._lib.tg_adjoint_p1(pat.handle, tg.LAPLACE, tg.F64, 1, 8, 8, 8, 8, None, 8, 1.0, 8, 8, None,
+                                 None) == tg.TG_E_STATE
+    assert tg._lib.tg_heat_rollout(pat.handle, tg.F64, 8, 8, 1e-3, 2, 8, 8, 1e-8, 10, 1, None, None, None,
+                                   None) == tg.TG_E_STATE
+    assert tg._lib.tg_heat_adjoint(pat.handle, tg.F64, 8, 8, 1e-3, 2, 8, 8, 8, 8, 8, 1e-8, 10, 1, None, None,
+                                   None, None) == tg.TG_E_STATE
+    # NULL pattern
+    assert tg._lib.tg_adjoint_p1(None, tg.LAPLACE, tg.F64, 1, 8, 8, 8, 8, None, 8, 1.0, 8, 8, None,
+                                 None) == tg.TG_E_ARG
 
 
 def test_valence_over_capacity_rejected():
