@@ -73,11 +73,15 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle timing sample")
-    ap.add_argument("--workload", choices=["poisson3d", "elasticity", "heat", "batched"], default="poisson3d",
+    ap.add_argument("--workload", choices=["poisson3d", "elasticity", "heat", "batched", "serve"],
+                    default="poisson3d",
                     help="poisson3d: the benchmark line; elasticity: P2 32^3 assembly-only timing; heat: "
                          "differentiable 2D heat rollout 256^2 (forward + adjoint gradient); batched: B "
-                         "coefficient sets on the 64^3 pattern in one launch")
+                         "coefficient sets on the 64^3 pattern in one launch; serve: a stream of assemble+solve "
+                         "requests through the continuous-batching server")
     ap.add_argument("--batch", type=int, default=8, help="coefficient sets for --workload batched")
+    ap.add_argument("--requests", type=int, default=64, help="requests for --workload serve")
+    ap.add_argument("--slots", type=int, default=16, help="slots per group for --workload serve")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -101,6 +105,8 @@ def main():
         return run_heat(args, dev)
     if args.workload == "batched":
         return run_batched(args, dev)
+    if args.workload == "serve":
+        return run_serve(args, dev)
 
     # ---------------------------------------------------------------- inputs (resident in HBM)
     d = meshgen.poisson_inputs(3, args.n, seed=0)
@@ -493,6 +499,71 @@ def run_batched(args, dev):
     out = {"workload": f"3D Poisson P1 64^3 x 6 Kuhn, {B} coefficient sets (a=exp(N(0,1)), f=U(-1,1)) on one "
                        f"pattern, cold (1 GiB flush before each launch)",
            "batch": B, "elements": E, "nnz": pat.nnz, **res}
+    print(json.dumps(out))
+
+
+def run_serve(args, dev):
+    """A stream of independent assemble + Dirichlet + PCG(1e-8) requests, half 3D Poisson 32^3 (196,608 tets) and
+    half 2D Poisson 128^2 (32,768 triangles), each with its own a = exp(N(0,1)) and f = U(-1,1), all submitted at
+    t = 0: served by the continuous-batching server against the same requests run one after another."""
+    import numpy as np
+    import torch
+
+    import meshgen
+    import paper_2602_05052_amd as tg
+
+    R = args.requests
+    meshes = [meshgen.poisson_inputs(3, 32, seed=0), meshgen.poisson_inputs(2, 128, seed=0)]
+    pats = [tg.Pattern(m["conn"], len(m["coords"])) for m in meshes]
+    coords = [torch.from_numpy(m["coords"]).to(dev) for m in meshes]
+    rng = np.random.default_rng(9)
+    reqs = []
+    for k in range(R):
+        j = k % 2
+        E = len(meshes[j]["conn"])
+        reqs.append((j, torch.from_numpy(np.exp(rng.standard_normal(E))).to(dev),
+                     torch.from_numpy(rng.uniform(-1, 1, E)).to(dev)))
+    xs = [torch.empty(pats[j].n_dofs, dtype=torch.float64, device=dev) for j, _, _ in reqs]
+    s = torch.cuda.Stream(device=dev)
+
+    def sequential():
+        its = 0
+        with torch.cuda.stream(s):
+            for (j, a, f), x in zip(reqs, xs):
+                vals, rhs = tg.assemble(pats[j], tg.LAPLACE, coords[j], a, f, stream=s)
+                tg.apply_dirichlet(pats[j], vals, rhs, stream=s)
+                _, it, _ = tg.pcg(pats[j], vals, rhs, rtol=1e-8, x=x, check_every=10, stream=s)
+                its += it
+        torch.cuda.synchronize()
+        return its
+
+    def served():
+        srv = tg.Server(hbm_budget=16 << 30, max_slots=args.slots, check_every=10, stream=s)
+        for (j, a, f), x in zip(reqs, xs):
+            srv.submit(pats[j], tg.LAPLACE, coords[j], a, f, x=x, rtol=1e-8)
+        res = srv.drain()
+        torch.cuda.synchronize()
+        return res
+
+    sequential()
+    served()  # warm-up: slot allocation and code paths
+    t0 = time.perf_counter()
+    its = sequential()
+    t_seq = time.perf_counter() - t0
+    ref = [x.clone() for x in xs]
+    t0 = time.perf_counter()
+    res = served()
+    t_srv = time.perf_counter() - t0
+    same = all(torch.equal(a, b) for a, b in zip(ref, xs))
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+    ok = sum(r["status"] == tg.TG_OK for r in res)
+    out = {"workload": f"{R} assemble+Dirichlet+PCG(1e-8) requests, half 3D Poisson 32^3 x 6 tets, half 2D Poisson "
+                       f"128^2 x 2 triangles, own coefficients each, all submitted at t=0",
+           "requests": R, "slots_per_group": args.slots, "completed_ok": int(ok),
+           "served_requests_per_s": R / t_srv, "sequential_requests_per_s": R / t_seq,
+           "speedup": t_seq / t_srv, "latency_ms_p50": float(np.percentile(lat, 50)) * 1e3,
+           "latency_ms_p99": float(np.percentile(lat, 99)) * 1e3, "pcg_iterations_total": int(its),
+           "bitwise_equal_to_sequential": bool(same)}
     print(json.dumps(out))
 
 

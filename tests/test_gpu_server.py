@@ -1,0 +1,178 @@
+"""GPU tests of the request server (continuous batching of assemble + Dirichlet + PCG).
+
+The acceptance bar: every request's solution and iteration count equal, bitwise, those of
+the same request run alone (tg_assemble + tg_apply_dirichlet + tg_pcg), however the
+requests were mixed, joined and retired; plus the true residual against the oracle's
+matrix for one request per group.
+"""
+import numpy as np
+import pytest
+
+import meshgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+tg = pytest.importorskip("paper_2602_05052_amd")
+
+
+def _cuda(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def _solo(pat, form, coords, coef, load, g, rtol, max_iter, dtype):
+    vals, rhs = tg.assemble(pat, form, coords, coef, load, dtype=dtype)
+    tg.apply_dirichlet(pat, vals, rhs, g=g)
+    x, it, rr = tg.pcg(pat, vals, rhs, rtol=rtol, max_iter=max_iter, check_every=10, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    return x, it, rr
+
+
+def _requests():
+    """(pattern, form, coords, coef, load, g, rtol, max_iter, dtype, mesh) for a mixed stream."""
+    out = []
+    p3 = meshgen.poisson_inputs(3, 10, seed=0)
+    p2 = meshgen.poisson_inputs(2, 40, seed=1)
+    el = meshgen.elasticity_inputs(3, seed=2)
+    pats = {
+        "p3": tg.Pattern(p3["conn"], len(p3["coords"])),
+        "p2": tg.Pattern(p2["conn"], len(p2["coords"])),
+        "el": tg.Pattern(el["conn"], len(el["coords"]), dim=3, order=2, ncomp=3),
+    }
+    rng = np.random.default_rng(42)
+    for k in range(15):
+        kind = ["p3", "p2", "el"][k % 3]
+        dtype = torch.float64 if k % 4 != 3 else torch.float32
+        if kind == "el":
+            m = el
+            coef = _cuda(np.stack([rng.uniform(0.5, 2, len(m["conn"])), rng.uniform(0.5, 2, len(m["conn"]))]), dtype)
+            load = _cuda(rng.standard_normal((len(m["conn"]), 3)), dtype)
+            form = tg.ELASTICITY
+        else:
+            m = p3 if kind == "p3" else p2
+            coef = _cuda(np.exp(rng.standard_normal(len(m["conn"]))), dtype)
+            load = _cuda(rng.uniform(-1, 1, len(m["conn"])), dtype)
+            form = tg.LAPLACE
+        pat = pats[kind]
+        g = _cuda(rng.standard_normal(pat.n_dofs), dtype) if k % 5 == 1 else None
+        rtol = 1e-8 if dtype == torch.float64 else 1e-5
+        out.append((pat, form, _cuda(m["coords"]), coef, load, g, rtol, 5000, dtype, m))
+    return out
+
+
+@pytest.mark.parametrize("max_slots,check_every", [(2, 7), (16, 10), (1, 1)])
+def test_mixed_stream_equals_solo_bitwise(max_slots, check_every):
+    print(f"server mix max_slots={max_slots} check_every={check_every}", flush=True)
+    reqs = _requests()
+    srv = tg.Server(hbm_budget=4 << 30, max_slots=max_slots, check_every=check_every)
+    ids = []
+    for i, (pat, form, coords, coef, load, g, rtol, mi, dtype, _) in enumerate(reqs):
+        ids.append(srv.submit(pat, form, coords, coef, load, g=g, rtol=rtol, max_iter=mi))
+        if i % 4 == 3:
+            srv.step()  # requests keep arriving while others are in flight
+    res = {r["request_id"]: r for r in srv.drain()}
+    assert sorted(res) == sorted(ids)
+    info = srv.info()
+    assert info["n_queued"] == 0 and info["n_active"] == 0
+    for rid, (pat, form, coords, coef, load, g, rtol, mi, dtype, m) in zip(ids, reqs):
+        r = res[rid]
+        assert r["status"] == tg.TG_OK, r
+        assert r["bad_element"] == -1 and r["t_done"] >= r["t_submit"]
+        x, it, rr = _solo(pat, form, coords, coef, load, g, rtol, mi, dtype)
+        assert r["iters"] == it
+        assert torch.equal(r["x"], x), rid
+        assert r["relres"] == rr
+        assert rr <= rtol * (1.5 if dtype == torch.float64 else 20.0)
+
+
+def test_server_result_against_oracle():
+    d = meshgen.poisson_inputs(3, 10, seed=3)
+    pat = tg.Pattern(d["conn"], len(d["coords"]))
+    srv = tg.Server(max_slots=4, check_every=5)
+    rid = srv.submit(pat, tg.LAPLACE, _cuda(d["coords"]), _cuda(d["a"]), _cuda(d["f"]), rtol=1e-10)
+    (r,) = srv.drain()
+    assert r["request_id"] == rid and r["status"] == tg.TG_OK
+    A = oracle.assemble_p1(d["coords"], d["conn"], d["a"], d["f"])
+    bnd = meshgen.boundary_vertices(d["coords"])
+    assert oracle.relres_lin(A, r["x"].cpu().numpy(), bnd) <= 2e-10
+    ref = oracle.condensed_solve(A, bnd)
+    assert oracle.relerr(r["x"].cpu().numpy(), ref) <= 1e-8
+
+
+def test_server_noconv_matches_solo():
+    d = meshgen.poisson_inputs(3, 10, seed=4)
+    pat = tg.Pattern(d["conn"], len(d["coords"]))
+    coords, a, f = _cuda(d["coords"]), _cuda(d["a"]), _cuda(d["f"])
+    srv = tg.Server(max_slots=4, check_every=3)
+    rid_short = srv.submit(pat, tg.LAPLACE, coords, a, f, rtol=1e-12, max_iter=5)
+    rid_long = srv.submit(pat, tg.LAPLACE, coords, a, f, rtol=1e-12, max_iter=4000)
+    res = {r["request_id"]: r for r in srv.drain()}
+    assert res[rid_short]["status"] == tg.TG_E_NOCONV and res[rid_short]["iters"] == 5
+    x5, it5, rr5 = _solo(pat, tg.LAPLACE, coords, a, f, None, 1e-12, 5, torch.float64)
+    assert it5 == 5 and torch.equal(res[rid_short]["x"], x5) and res[rid_short]["relres"] == rr5
+    xl, itl, _ = _solo(pat, tg.LAPLACE, coords, a, f, None, 1e-12, 4000, torch.float64)
+    assert res[rid_long]["status"] == tg.TG_OK and res[rid_long]["iters"] == itl
+    assert torch.equal(res[rid_long]["x"], xl)
+
+
+def test_server_budget_admission():
+    d = meshgen.poisson_inputs(2, 20, seed=5)
+    pat = tg.Pattern(d["conn"], len(d["coords"]))
+    coords, a, f = _cuda(d["coords"]), _cuda(d["a"]), _cuda(d["f"])
+    slot = (pat.nnz + 7 * pat.n_dofs) * 8 + 5 * 512 * 8
+    # too small for one slot: the request completes with TG_E_NOMEM
+    srv = tg.Server(hbm_budget=slot // 2, max_slots=4)
+    srv.submit(pat, tg.LAPLACE, coords, a, f)
+    (r,) = srv.drain()
+    assert r["status"] == tg.TG_E_NOMEM
+    # room for two slots (plus the group tables): six requests run two at a time
+    srv = tg.Server(hbm_budget=2 * slot + 4096, max_slots=8, check_every=4)
+    for _ in range(6):
+        srv.submit(pat, tg.LAPLACE, coords, a, f)
+    peak = 0
+    res = []
+    while srv.pending():
+        active, _ = srv.step()
+        peak = max(peak, active)
+        res += srv.poll()
+    assert len(res) == 6 and all(r["status"] == tg.TG_OK for r in res)
+    assert srv.info()["n_slots"] == 2 and peak <= 2
+    xs = [r["x"] for r in res]
+    assert all(torch.equal(xs[0], x) for x in xs[1:])
+
+
+def test_server_degenerate_request():
+    d = meshgen.poisson_inputs(2, 4, seed=6)
+    coords = d["coords"].copy()
+    conn = d["conn"]
+    # move vertex 6 onto vertex 7: every element holding both becomes degenerate
+    coords[6] = coords[7]
+    bad = [e for e, t in enumerate(conn) if 6 in t and 7 in t]
+    pat = tg.Pattern(conn, len(coords))
+    srv = tg.Server(max_slots=2, check_every=4)
+    srv.submit(pat, tg.LAPLACE, _cuda(coords), _cuda(d["a"]), _cuda(d["f"]), max_iter=12)
+    good = meshgen.poisson_inputs(2, 4, seed=6)
+    srv.submit(pat, tg.LAPLACE, _cuda(good["coords"]), _cuda(good["a"]), _cuda(good["f"]))
+    r_bad, r_good = sorted(srv.drain(), key=lambda r: r["request_id"])
+    assert r_bad["status"] == tg.TG_E_DEGENERATE and r_bad["bad_element"] in bad
+    assert r_good["status"] == tg.TG_OK
+
+
+def test_server_argument_errors():
+    d = meshgen.poisson_inputs(2, 3, seed=0)
+    pat = tg.Pattern(d["conn"], len(d["coords"]))
+    coords, a, f = _cuda(d["coords"]), _cuda(d["a"]), _cuda(d["f"])
+    with pytest.raises(tg.TGError, match="max_slots"):
+        tg.Server(max_slots=0)
+    srv = tg.Server()
+    with pytest.raises(tg.TGError, match="rtol"):
+        srv.submit(pat, tg.LAPLACE, coords, a, f, rtol=0.0)
+    with pytest.raises(tg.TGError, match="max_iter"):
+        srv.submit(pat, tg.LAPLACE, coords, a, f, max_iter=0)
+    x = torch.empty(pat.n_dofs, dtype=torch.float64, device="cuda")
+    assert tg._lib.tg_server_submit(srv._h, pat.handle, tg.MASS, tg.F64, coords.data_ptr(), None, f.data_ptr(),
+                                    None, x.data_ptr(), 1e-8, 10, None) == tg.TG_E_ARG
+    assert tg._lib.tg_server_submit(srv._h, pat.handle, tg.LAPLACE, tg.F64, coords.data_ptr(), a.data_ptr(), None,
+                                    None, x.data_ptr(), 1e-8, 10, None) == tg.TG_E_ARG
+    assert not srv.pending() and srv.drain() == []
