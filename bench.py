@@ -34,13 +34,63 @@ METRIC = "assembled elements/s + HBM GB/s (FP64 vs FP32); p50/p99 assemble+solve
 
 
 def source_hash() -> str:
-    """Hash of the kernel sources; a stored counter measurement is used only if it matches."""
+    """Hash of the device code and of the pattern builder (which fixes blocks and routing); a stored
+    counter measurement is used only while it matches."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2602_05052_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+        if f.endswith((".hip", ".h")) or f == "tg_pattern.cpp":
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
+
+
+def kernel_key(name: str) -> str:
+    """'void tg::(anonymous namespace)::p1_assemble_kernel<3, double, 0, true, false>(...)' ->
+    'p1_assemble_kernel<3,double,0,true,false>'."""
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "").replace("tg::", "")
+    depth = 0
+    for i, ch in enumerate(name):
+        depth += (ch == "<") - (ch == ">")
+        if ch == "(" and depth == 0:
+            name = name[:i]
+            break
+    return name.replace(" ", "")
+
+
+def traffic_from_pmc(fetch_csv: str, write_csv: str, out_json: str, copy_kernel: str = "CUDAFunctorOnSelf_add"):
+    """HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each
+    scaled so that the 1 GiB read-modify-write `add_` of the cold protocol reads 1 GiB and writes 1 GiB."""
+    import csv
+    from collections import defaultdict
+
+    def load(path, counter):
+        per = defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return per
+
+    fetch, write = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    cal_f = [v for k, vs in fetch.items() if copy_kernel in k for v in vs]
+    cal_w = [v for k, vs in write.items() if copy_kernel in k for v in vs]
+    fs, ws = gib_kib / (sum(cal_f) / len(cal_f)), gib_kib / (sum(cal_w) / len(cal_w))
+    rec = {"_calibration": {"kernel": copy_kernel, "bytes_read": 1 << 30, "bytes_written": 1 << 30,
+                            "fetch_kib": sum(cal_f) / len(cal_f), "write_kib": sum(cal_w) / len(cal_w),
+                            "fetch_scale": fs, "write_scale": ws}}
+    for name in fetch:
+        if copy_kernel in name or name not in write or "tg::" not in name:
+            continue
+        f = sum(fetch[name]) / len(fetch[name])
+        w = sum(write[name]) / len(write[name])
+        rec[kernel_key(name)] = {"source_hash": source_hash(), "fetch_kib_raw": f, "write_kib_raw": w,
+                                 "fetch_scale": fs, "write_scale": ws,
+                                 "bytes_per_launch": int(round((f * fs + w * ws) * 1024)),
+                                 "dispatches": len(fetch[name])}
+    with open(out_json, "w") as fh:
+        json.dump(rec, fh, indent=1, sort_keys=True)
+    return rec
 
 
 def stored_traffic(kernel: str):
@@ -82,7 +132,17 @@ def main():
     ap.add_argument("--batch", type=int, default=8, help="coefficient sets for --workload batched")
     ap.add_argument("--requests", type=int, default=64, help="requests for --workload serve")
     ap.add_argument("--slots", type=int, default=16, help="slots per group for --workload serve")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc runs of this script and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        rec = traffic_from_pmc(*args.traffic_from, os.path.join(ROOT, "profiles", "traffic.json"))
+        for k, v in sorted(rec.items()):
+            if not k.startswith("_"):
+                print(f"| `{k}` | {v['dispatches']} | {v['fetch_kib_raw']:.1f} | {v['write_kib_raw']:.1f} | "
+                      f"{v['bytes_per_launch'] / 1e6:.1f} MB |")
+        print(json.dumps(rec["_calibration"]))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
@@ -190,7 +250,7 @@ def main():
     bmin32, balg32 = p1_bytes(nv, 3, E, pat.nnz, pat.n_dofs, 4, 2)
     mean_asm = float(t_asm.mean())
     gbs = balg64 / mean_asm / 1e9
-    traffic = stored_traffic("p1_assemble_kernel<3,double,laplace>")
+    traffic = stored_traffic("p1_assemble_kernel<3,double,0,true,false>")
 
     out = {
         "metric": METRIC,

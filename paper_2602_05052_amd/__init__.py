@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 
 import numpy as np
 
@@ -75,6 +76,8 @@ _SIGS = {
     "tg_pattern_copy_element_nodes": (ctypes.c_int, [_vp, _i32p]),
     "tg_pattern_copy_routing": (ctypes.c_int, [_vp, _i32p, _i32p, _i32p, _i32p, _i32p,
                                                ctypes.POINTER(ctypes.c_uint16)]),
+    "tg_pattern_copy_block_vertices": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), _i32p, _i32p,
+                                                      ctypes.POINTER(ctypes.c_uint32)]),
     "tg_pattern_destroy": (None, [_vp]),
     "tg_assemble": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tg_assemble_batched": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -214,10 +217,10 @@ class Pattern:
         self.device_bytes = info.device_bytes
         self.host_only = host_only
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.tg_pattern_destroy, _finalizing=sys.is_finalizing):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            _lib.tg_pattern_destroy(h)
+        if h is not None and h.value and not _finalizing():  # at exit the process releases everything
+            _destroy(h)
             self._h = None
 
     @property
@@ -252,6 +255,18 @@ class Pattern:
             self._h, *(out[k].ctypes.data_as(_i32p) for k in ("inc_ptr", "inc", "blk_row", "node_rp", "seg_ptr")),
             out["slot"].ctypes.data_as(ctypes.POINTER(ctypes.c_uint16))))
         return out
+
+    def block_vertices(self):
+        """P1: (blk_vptr [B+1], blk_vert, pair_lv [P]) of the kernel's per-block coordinate staging."""
+        nvert = ctypes.c_int64(0)
+        _check(_lib.tg_pattern_copy_block_vertices(self._h, ctypes.byref(nvert), None, None, None))
+        vptr = np.zeros(self.n_blocks + 1, dtype=np.int32)
+        vert = np.zeros(max(1, nvert.value), dtype=np.int32)
+        lv = np.zeros(max(1, self.n_elements * self.k), dtype=np.uint32)
+        _check(_lib.tg_pattern_copy_block_vertices(
+            self._h, None, vptr.ctypes.data_as(_i32p), vert.ctypes.data_as(_i32p),
+            lv.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+        return vptr, vert[:nvert.value], lv[:self.n_elements * self.k]
 
     def row_ptr_device(self):
         torch = _torch()
@@ -492,10 +507,10 @@ class Server:
                                      ctypes.byref(self._h)))
         self._keep = {}
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.tg_server_destroy, _finalizing=sys.is_finalizing):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            _lib.tg_server_destroy(h)
+        if h is not None and h.value and not _finalizing():  # at exit the process releases everything
+            _destroy(h)
             self._h = None
 
     def submit(self, pattern: Pattern, form: int, coords, coef, load, x=None, g=None, rtol: float = 1e-8,

@@ -34,6 +34,7 @@ hipError_t upload(const std::vector<V> &h, V **d, size_t &bytes) {
 
 void free_device(tg::DevicePattern &d) {
     void *ptrs[] = {d.conn,    d.inc_ptr, d.inc,      d.blk_row,     d.blk_desc, d.node_rp, d.node_ci, d.seg_ptr,
+                    d.blk_vert, d.pair_lv,
                     d.slot,    d.row_ptr, d.col_idx,  d.diag_pos,    d.constrained,
                     d.work,    d.partials, d.state, d.dir_rows,  d.pcg_slot, d.pcg_list};
     for (void *p : ptrs)
@@ -57,6 +58,8 @@ tg_status create_device(tg_pattern &pt) {
     TG_UP(inc, inc);
     TG_UP(blk_row, blk_row);
     TG_UP(blk_desc, blk_desc);
+    TG_UP(blk_vert, blk_vert);
+    TG_UP(pair_lv, pair_lv);
     TG_UP(node_rp, node_rp);
     TG_UP(node_ci, node_ci);
     TG_UP(seg_ptr, seg_ptr);
@@ -214,6 +217,22 @@ tg_status tg_pattern_copy_routing(const tg_pattern *p, int32_t *h_inc_ptr, int32
     cp(h_node_rp, h.node_rp);
     cp(h_seg_ptr, h.seg_ptr);
     cp(h_slot, h.slot);
+    return ok();
+}
+
+tg_status tg_pattern_copy_block_vertices(const tg_pattern *p, int64_t *n_vert, int32_t *h_blk_vptr,
+                                         int32_t *h_blk_vert, uint32_t *h_pair_lv) {
+    if (!p) return fail(TG_E_ARG, "pattern is NULL");
+    const tg::HostPattern &h = p->host;
+    if (h.order != 1) return fail(TG_E_ARG, "block vertex lists exist for P1 patterns only");
+    if (n_vert) *n_vert = (int64_t)h.blk_vert.size();
+    if (h_blk_vptr) {
+        const int64_t nb = h.n_blocks();
+        for (int64_t b = 0; b < nb; ++b) h_blk_vptr[b] = h.blk_desc[b * 8 + 6];
+        h_blk_vptr[nb] = (int32_t)h.blk_vert.size();
+    }
+    if (h_blk_vert) std::memcpy(h_blk_vert, h.blk_vert.data(), sizeof(int32_t) * h.blk_vert.size());
+    if (h_pair_lv) std::memcpy(h_pair_lv, h.pair_lv.data(), sizeof(uint32_t) * h.pair_lv.size());
     return ok();
 }
 

@@ -215,25 +215,66 @@ __device__ __forceinline__ void p1_row(const P1Geom<D> &g, int a, double c, doub
 // writes values[m nnz + p] and rhs[m N + i]; the geometry and the routing are
 // read once for the whole batch.  Every member runs exactly the arithmetic
 // of a single call, so it is bitwise equal to assembling it alone.
+// Per-block LDS copy of the vertex coordinates: VS doubles per vertex (16-byte
+// records), placed after the BlockLds arrays.
+template <int D>
+struct VertLds {
+    static constexpr int VS = D == 3 ? 4 : 2;
+    __host__ __device__ static size_t offset(size_t block_lds_bytes) { return (block_lds_bytes + 15) & ~(size_t)15; }
+    __host__ __device__ static size_t bytes(int nverts) { return sizeof(double) * VS * (size_t)nverts; }
+};
+
+// Vertex l of the block's list -> LDS (coordinates are AoS [Nv][D] FP64).
+template <int D>
+__device__ __forceinline__ void stage_vertex(const double *__restrict__ coords, unsigned v, double *lx) {
+    if constexpr (D == 3) {
+        const double x0 = ldg(coords, 3u * v), x1 = ldg(coords, 3u * v + 1u), x2 = ldg(coords, 3u * v + 2u);
+        *reinterpret_cast<double2 *>(lx) = make_double2(x0, x1);
+        lx[2] = x2;
+    } else {
+        *reinterpret_cast<double2 *>(lx) = ldg(reinterpret_cast<const double2 *>(coords), v);
+    }
+}
+
+// The element's vertices from the block's LDS copy; lv holds one 8-bit local id per vertex.
+template <int D>
+__device__ __forceinline__ void lds_vertices(const double *lx, uint32_t lv, double (&x)[D + 1][D]) {
+    constexpr int VS = VertLds<D>::VS;
+#pragma unroll
+    for (int a = 0; a <= D; ++a) {
+        const double *r = lx + ((lv >> (8 * a)) & 255u) * VS;
+        const double2 xy = *reinterpret_cast<const double2 *>(r);
+        x[a][0] = xy.x;
+        x[a][1] = xy.y;
+        if constexpr (D == 3) x[a][2] = r[2];
+    }
+}
+
 template <int D, typename T, int FORM, bool LOAD, bool BATCHED>
-__global__ __launch_bounds__(kP1Threads) void p1_assemble_kernel(
+__global__ __launch_bounds__(kP1Threads, 8) void p1_assemble_kernel(
     const int32_t *__restrict__ blk_desc, const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc,
-    const int32_t *__restrict__ seg_ptr, const uint16_t *__restrict__ slot, const int32_t *__restrict__ conn,
-    const double *__restrict__ coords, const T *__restrict__ coef, const T *__restrict__ load,
-    T *__restrict__ values, T *__restrict__ rhs, int32_t *__restrict__ status, int nblk, int mp, int me,
-    int nbatch, unsigned n_elem, unsigned nnz, unsigned n_rows) {
+    const int32_t *__restrict__ seg_ptr, const uint16_t *__restrict__ slot, const int32_t *__restrict__ blk_vert,
+    const uint32_t *__restrict__ pair_lv, const double *__restrict__ coords, const T *__restrict__ coef,
+    const T *__restrict__ load, T *__restrict__ values, T *__restrict__ rhs, int32_t *__restrict__ status, int nblk,
+    int mp, int me, int nbatch, unsigned n_elem, unsigned nnz, unsigned n_rows) {
     constexpr int K = D + 1;
+    constexpr int VS = VertLds<D>::VS;
     constexpr bool COEF = FORM != kMass;
     extern __shared__ __align__(16) unsigned char smem[];
     BlockLds<T> L(smem, mp, me, K, 1, K);
+    double *Lx = reinterpret_cast<double *>(smem + VertLds<D>::offset(BlockLds<T>::bytes(mp, me, K, 1, K)));
 
     const int blk = xcd_swizzle(blockIdx.x, nblk);
     const int4 dsc = ldg(reinterpret_cast<const int4 *>(blk_desc), 2u * blk);
-    const int2 dsv = ldg(reinterpret_cast<const int2 *>(blk_desc), 4u * blk + 2u);
-    const int r0 = dsc.x, r1 = dsc.y, q0 = dsc.z, q1 = dsc.w, v0 = dsv.x, v1 = dsv.y;
-    const int np = q1 - q0, nent = v1 - v0;
+    const int4 dsv = ldg(reinterpret_cast<const int4 *>(blk_desc), 2u * blk + 1u);
+    const int r0 = dsc.x, r1 = dsc.y, q0 = dsc.z, q1 = dsc.w, v0 = dsv.x, v1 = dsv.y, w0 = dsv.z, w1 = dsv.w;
+    const int np = q1 - q0, nent = v1 - v0, nvb = w1 - w0;
     const unsigned s0 = (unsigned)q0 * K;  // the block's slots are slot[s0 .. s0 + np K)
     const int tid = threadIdx.x;
+
+    // ---- the block's vertices -> LDS (each vertex once per block)
+    for (int l = tid; l < nvb; l += kP1Threads)
+        stage_vertex<D>(coords, (unsigned)ldg(blk_vert, (unsigned)(w0 + l)), Lx + l * VS);
 
     // The block's share of the routing, fetched first (independent of the Map's
     // load chain) and written to LDS after the Map: one unit of K slots and one
@@ -258,15 +299,20 @@ __global__ __launch_bounds__(kP1Threads) void p1_assemble_kernel(
     const bool own = tid < np;
     unsigned e = 0;
     int a = 0;
+    uint32_t lv = 0;
+    if (own) {
+        const unsigned code = (unsigned)ldg(inc, (unsigned)(q0 + tid));
+        lv = ldg(pair_lv, (unsigned)(q0 + tid));
+        e = code / K;
+        a = (int)(code - e * K);
+    }
+    __syncthreads();  // the vertex copy is complete
     P1Geom<D> g;
     g.adet = 1.0;
     g.bad = false;
     if (own) {
-        const unsigned code = (unsigned)ldg(inc, (unsigned)(q0 + tid));
-        e = code / K;
-        a = (int)(code - e * K);
         double x[K][D];
-        load_vertices<D>(conn, coords, (int)e, x);
+        lds_vertices<D>(Lx, lv, x);
         p1_geometry<D>(x, g);
     }
 
@@ -289,7 +335,7 @@ __global__ __launch_bounds__(kP1Threads) void p1_assemble_kernel(
             const unsigned code = (unsigned)ldg(inc, (unsigned)(q0 + t));
             const unsigned ee = code / K;
             double x[K][D];
-            load_vertices<D>(conn, coords, (int)ee, x);
+            lds_vertices<D>(Lx, ldg(pair_lv, (unsigned)(q0 + t)), x);
             P1Geom<D> gg;
             p1_geometry<D>(x, gg);
             const double c = COEF ? (double)ldg(coef, eo + ee) : 1.0;
@@ -515,17 +561,18 @@ static hipError_t launch_p1_t(const tg_pattern &p, int nbatch, const double *coo
     const HostPattern &h = p.host;
     const int nblk = (int)h.n_blocks();
     const int mp = h.max_block_pairs, me = h.max_block_entries;
-    const size_t lds = BlockLds<T>::bytes(mp, me, D + 1, 1, D + 1);
+    const size_t lds = VertLds<D>::offset(BlockLds<T>::bytes(mp, me, D + 1, 1, D + 1)) +
+                       VertLds<D>::bytes(h.max_block_verts);
     if (nbatch == 1)
         hipLaunchKernelGGL((p1_assemble_kernel<D, T, FORM, LOAD, false>), dim3(nblk), dim3(kP1Threads), lds, s,
-                           d.blk_desc, d.inc_ptr, d.inc, d.seg_ptr, d.slot, d.conn, coords, (const T *)coef,
-                           (const T *)load, (T *)values, (T *)rhs, status, nblk, mp, me, 1, (unsigned)h.E,
-                           (unsigned)h.nnz, (unsigned)h.n_dofs);
+                           d.blk_desc, d.inc_ptr, d.inc, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, coords,
+                           (const T *)coef, (const T *)load, (T *)values, (T *)rhs, status, nblk, mp, me, 1,
+                           (unsigned)h.E, (unsigned)h.nnz, (unsigned)h.n_dofs);
     else
         hipLaunchKernelGGL((p1_assemble_kernel<D, T, FORM, LOAD, true>), dim3(nblk), dim3(kP1Threads), lds, s,
-                           d.blk_desc, d.inc_ptr, d.inc, d.seg_ptr, d.slot, d.conn, coords, (const T *)coef,
-                           (const T *)load, (T *)values, (T *)rhs, status, nblk, mp, me, nbatch, (unsigned)h.E,
-                           (unsigned)h.nnz, (unsigned)h.n_dofs);
+                           d.blk_desc, d.inc_ptr, d.inc, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, coords,
+                           (const T *)coef, (const T *)load, (T *)values, (T *)rhs, status, nblk, mp, me, nbatch,
+                           (unsigned)h.E, (unsigned)h.nnz, (unsigned)h.n_dofs);
     return hipGetLastError();
 }
 

@@ -189,14 +189,54 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
     // ---- row blocks: consecutive rows while the pairs fit the target (and, for
     // P1, the node-level entries fit one thread each); a single row may exceed
     // the target up to the capacity
+    // the target up to the capacity.  P1 blocks also keep their elements'
+    // distinct vertices within kP1BlockVerts (8-bit local ids).
     const int target = p1 ? kP1BlockTarget : kP2BlockTarget;
     const int entry_target = p1 ? kP1Threads - 1 : INT32_MAX;
     hp.blk_row.clear();
     hp.blk_row.push_back(0);
+    std::vector<int64_t> vstamp(p1 ? hp.nv : 0, -1);
+    // distinct vertices that row r adds to the block stamped `stamp` (marks them)
+    auto row_new_verts = [&](int64_t r, int64_t stamp, std::vector<int32_t> *added) {
+        int n = 0;
+        for (int32_t t = hp.inc_ptr[r]; t < hp.inc_ptr[r + 1]; ++t) {
+            const int64_t e = hp.inc[t] / k;
+            for (int b = 0; b < k; ++b) {
+                const int32_t v = hp.elem_nodes[e * k + b];
+                if (vstamp[v] != stamp) {
+                    vstamp[v] = stamp;
+                    ++n;
+                    if (added) added->push_back(v);
+                }
+            }
+        }
+        return n;
+    };
+    std::vector<int32_t> added;
     for (int64_t i = 0; i < N;) {
         const int32_t first = hp.inc_ptr[i], first_entry = hp.node_rp[i];
         int64_t j = i + 1;
-        while (j < N && hp.inc_ptr[j + 1] - first <= target && hp.node_rp[j + 1] - first_entry <= entry_target) ++j;
+        if (p1) {
+            int nverts = row_new_verts(i, i, nullptr);
+            if (nverts > kP1BlockVerts) {
+                msg = "the elements of node " + std::to_string(i) + " have " + std::to_string(nverts) +
+                      " distinct vertices, more than the kernel block capacity " + std::to_string(kP1BlockVerts);
+                return TG_E_ARG;
+            }
+            while (j < N && hp.inc_ptr[j + 1] - first <= target && hp.node_rp[j + 1] - first_entry <= entry_target) {
+                added.clear();
+                const int extra = row_new_verts(j, i, &added);
+                if (nverts + extra > kP1BlockVerts) {
+                    for (int32_t v : added) vstamp[v] = -1;  // row j starts the next block
+                    break;
+                }
+                nverts += extra;
+                ++j;
+            }
+        } else {
+            while (j < N && hp.inc_ptr[j + 1] - first <= target && hp.node_rp[j + 1] - first_entry <= entry_target)
+                ++j;
+        }
         hp.blk_row.push_back((int32_t)j);
         i = j;
     }
@@ -245,6 +285,43 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
         dsc[5] = hp.node_rp[r1];
         hp.max_block_pairs = std::max(hp.max_block_pairs, hp.inc_ptr[r1] - hp.inc_ptr[r0]);
         hp.max_block_entries = std::max(hp.max_block_entries, hp.node_rp[r1] - hp.node_rp[r0]);
+    }
+    // ---- P1: block vertex lists and the per-pair block-local vertex ids
+    hp.blk_vert.clear();
+    hp.pair_lv.clear();
+    hp.max_block_verts = 0;
+    if (p1) {
+        hp.pair_lv.assign((size_t)E * k, 0u);
+        std::vector<int32_t> local(hp.nv, -1), verts;
+        for (int64_t b = 0; b + 1 < (int64_t)hp.blk_row.size(); ++b) {
+            int32_t *dsc = &hp.blk_desc[b * 8];
+            const int32_t q0 = dsc[2], q1 = dsc[3];
+            verts.clear();
+            for (int32_t t = q0; t < q1; ++t) {
+                const int64_t e = hp.inc[t] / k;
+                for (int a = 0; a < k; ++a) verts.push_back(hp.elem_nodes[e * k + a]);
+            }
+            std::sort(verts.begin(), verts.end());
+            verts.erase(std::unique(verts.begin(), verts.end()), verts.end());
+            if ((int)verts.size() > kP1BlockVerts) {  // the greedy partition above prevents this
+                msg = "internal error: block vertex capacity exceeded";
+                return TG_E_ARG;
+            }
+            dsc[6] = (int32_t)hp.blk_vert.size();
+            for (size_t l = 0; l < verts.size(); ++l) {
+                local[verts[l]] = (int32_t)l;
+                hp.blk_vert.push_back(verts[l]);
+            }
+            dsc[7] = (int32_t)hp.blk_vert.size();
+            hp.max_block_verts = std::max(hp.max_block_verts, (int32_t)verts.size());
+            for (int32_t t = q0; t < q1; ++t) {
+                const int64_t e = hp.inc[t] / k;
+                uint32_t w = 0;
+                for (int a = 0; a < k; ++a) w |= (uint32_t)local[hp.elem_nodes[e * k + a]] << (8 * a);
+                hp.pair_lv[t] = w;
+            }
+            for (int32_t v : verts) local[v] = -1;
+        }
     }
     hp.nnz = hp.nnz_nodes * ncomp * ncomp;
 

@@ -194,3 +194,33 @@ def test_valence_over_capacity_rejected():
     conn = np.array([[0, 1 + i, 1 + (i + 1) % m] for i in range(m)], dtype=np.int32)
     with pytest.raises(tg.TGError, match="block capacity"):
         tg.Pattern(conn, m + 1, host_only=True)
+
+
+@pytest.mark.parametrize("dim,n,shuffle", [(3, 12, False), (3, 6, True), (2, 64, False), (2, 20, True)])
+def test_block_vertex_staging_in_bounds(dim, n, shuffle):
+    """The P1 kernel stages each block's vertices in LDS: every pair's local ids must lie inside its
+    block's list (at most 256 entries) and name exactly its element's vertices in local order."""
+    d = meshgen.poisson_inputs(dim, n, seed=0)
+    coords, conn = d["coords"], d["conn"]
+    if shuffle:
+        coords, conn = meshgen.shuffle_numbering(coords, conn, seed=3)[:2]
+    pat = tg.Pattern(conn, len(coords), host_only=True)
+    vptr, vert, lv = pat.block_vertices()
+    r = pat.routing()
+    k = dim + 1
+    assert vptr[0] == 0 and vptr[-1] == len(vert) and np.all(np.diff(vptr) >= 1)
+    assert np.diff(vptr).max() <= 256
+    pair_block = np.repeat(np.arange(pat.n_blocks), np.diff(r["inc_ptr"][r["blk_row"]]))
+    e = r["inc"] // k
+    for a in range(k):
+        loc = (lv >> (8 * a)) & 255
+        assert np.all(loc < np.diff(vptr)[pair_block])
+        np.testing.assert_array_equal(vert[vptr[pair_block] + loc], conn[e, a])
+    if k == 3:
+        assert np.all(lv >> 24 == 0)
+    for b in range(pat.n_blocks):  # ascending and distinct within a block
+        seg = vert[vptr[b]:vptr[b + 1]]
+        assert np.all(np.diff(seg) > 0)
+    with pytest.raises(tg.TGError):
+        p2 = meshgen.elasticity_inputs(1, seed=0)
+        tg.Pattern(p2["conn"], len(p2["coords"]), dim=3, order=2, ncomp=3, host_only=True).block_vertices()
