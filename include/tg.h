@@ -374,8 +374,8 @@ typedef struct {
     size_t hbm_used, hbm_budget;
 } tg_server_info;
 
-/* hbm_budget_bytes: cap on slot memory (per slot: nnz + 7 n_dofs values of the
- * dtype + 20 KB); max_slots: slots per group (1..65535); check_every: CG
+/* hbm_budget_bytes: cap on slot memory (per slot: nnz + 10 n_dofs values of the
+ * dtype + 28 KB); max_slots: slots per group (1..65535); check_every: CG
  * iterations per tg_server_step (>= 1). */
 tg_status tg_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t check_every, void *stream,
                            tg_server **out);

@@ -72,7 +72,7 @@ tg_status create_device(tg_pattern &pt) {
 #undef TG_UP
     d.n_dir_rows = (int64_t)h.dirichlet_rows.size();
     if (e == hipSuccess) {
-        const size_t wb = 6 * (size_t)h.n_dofs * sizeof(double);
+        const size_t wb = (size_t)kPcgWorkVectors * h.n_dofs * sizeof(double);
         e = hipMalloc((void **)&d.work, wb);
         bytes += wb;
     }

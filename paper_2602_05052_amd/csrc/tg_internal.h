@@ -73,13 +73,15 @@ struct HostPattern {
 tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t E, const int32_t *conn,
                              const int32_t *dirichlet, int64_t n_dirichlet, HostPattern &hp, std::string &msg);
 
-// PCG device state (one per pattern).
+// PCG device state (one per system).
 struct PcgState {
-    double bb;      // b.b
-    double rr;      // true residual r.r after the final check
-    double tol2;    // rtol^2 * b.b
-    int32_t done;   // 1 once the stop test held
-    int32_t iters;  // iteration at which it held
+    double bb;        // b.b
+    double rr;        // true residual r.r after the final check
+    double tol2;      // rtol^2 * b.b
+    int32_t done;     // 1 once the stop test held
+    int32_t iters;    // iteration at which it held
+    double alpha[2];  // step length of iteration i, kept at [i & 1] for iteration i + 1
+    double gamma[2];  // r.u of iteration i, kept at [i & 1]
 };
 
 // One CG system in flight.  The solo solver (tg_pcg) uses one; the request
@@ -89,7 +91,7 @@ struct PcgSlot {
     const void *values;  // T[nnz], Dirichlet applied
     const void *b;       // T[n]
     void *x;             // T[n], the iterate (output)
-    void *work;          // T[6n]: r, z, pA, pB, q, dinv
+    void *work;          // T[kPcgWorkVectors n]: records {r, w, s, dinv} x 2 (by parity), p
     double *partials;    // [kNumPartials][kMaxGrid]
     PcgState *state;
     double rtol2;
@@ -99,8 +101,11 @@ struct PcgSlot {
 
 constexpr int kVecThreads = 1024;  // threads per block of the PCG kernels
 constexpr int kMaxGrid = 512;      // blocks of the PCG kernels (grid-stride beyond): 2 per CU
-// Per-block partial sums of the PCG kernels: [PQ | RZ0 | RZ1 | RR | BB], kMaxGrid doubles each.
-constexpr int kPQ = 0, kRZ0 = 1, kRR = 3, kBB = 4, kNumPartials = 5;
+// Per-block partial sums of the PCG kernels, kMaxGrid doubles each: r.u, w.u and r.r
+// of an iterate at kGam/kDel/kRr + 3 (iteration & 1), and the true residual at kResid.
+constexpr int kGam = 0, kDel = 1, kRr = 2, kResid = 6, kNumPartials = 7;
+// Krylov workspace of one system, in vectors of n values of the dtype.
+constexpr int kPcgWorkVectors = 9;
 
 struct DevicePattern {
     int32_t *conn = nullptr;      // [E][dim+1]
@@ -118,9 +123,9 @@ struct DevicePattern {
     int32_t *col_idx = nullptr;   // [nnz]
     int32_t *diag_pos = nullptr;  // [n_dofs]
     uint8_t *constrained = nullptr;  // [n_dofs]
-    // PCG workspace: 6 vectors of n_dofs doubles (used as T), partials, state.
+    // PCG workspace: kPcgWorkVectors vectors of n_dofs doubles (used as T), partials, state.
     double *work = nullptr;
-    double *partials = nullptr;  // [kNumPartials][kMaxGrid]: (p.q), (r.z) x2, (r.r), (b.b) partials
+    double *partials = nullptr;  // [kNumPartials][kMaxGrid]
     int32_t *dir_rows = nullptr; // rows that are constrained or have a constrained column
     int64_t n_dir_rows = 0;
     PcgState *state = nullptr;
@@ -165,8 +170,7 @@ hipError_t launch_adjoint_p1(const tg_pattern &p, tg_form form, tg_dtype dtype, 
 // y[i] = dt * exp(x[i]) in dtype (FP64 input).
 hipError_t launch_scaled_exp(tg_dtype dtype, int64_t n, double dt, const double *x, void *y, hipStream_t s);
 // Batched PCG over the slots listed in `list` (device int32[count]); every slot
-// holds a system on pattern p in dtype.  Iteration = launch: one pcg_spmv and
-// one pcg_update launch per step (tg_solve.hip).
+// holds a system on pattern p in dtype.  One launch per iteration (tg_solve.hip).
 hipError_t launch_pcg_init(const tg_pattern &p, tg_dtype dtype, const PcgSlot *slots, const int32_t *list, int count,
                            hipStream_t s);
 hipError_t launch_pcg_step(const tg_pattern &p, tg_dtype dtype, const PcgSlot *slots, const int32_t *list, int count,

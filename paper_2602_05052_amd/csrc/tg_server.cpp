@@ -8,8 +8,8 @@
 // workspace, partial sums, state) that live as long as the server.  Between
 // CG iterations the scheduler retires finished systems and admits queued
 // requests into the freed slots (their assembly, Dirichlet elimination and CG
-// initialisation run then); every iteration is one pcg_spmv and one
-// pcg_update launch over all active slots of a group (blockIdx.y = slot).
+// initialisation run then); every iteration is one launch over all active
+// slots of a group (blockIdx.y = slot).
 // The per-slot reductions never mix: a slot's scalars come from its own
 // partials in the same fixed order as a solo tg_pcg on the same kernels, so a
 // request's solution is bitwise the same whether it ran alone or in a mix.
@@ -122,7 +122,7 @@ tg_status make_group(tg_server *srv, const tg_pattern *p, tg_dtype dtype, Group 
     g->dtype = dtype;
     g->max_slots = srv->max_slots;
     const size_t elt = dtype == TG_F64 ? 8 : 4, n = (size_t)p->host.n_dofs, S = (size_t)srv->max_slots;
-    g->slot_bytes = ((size_t)p->host.nnz + 7 * n) * elt + kPartialBytes;
+    g->slot_bytes = ((size_t)p->host.nnz + (1 + tg::kPcgWorkVectors) * n) * elt + kPartialBytes;
     const size_t table = S * (sizeof(PcgSlot) + sizeof(PcgState) + 4 * sizeof(int32_t));
     hipError_t e = hipMalloc((void **)&g->d_slots, S * sizeof(PcgSlot));
     if (e == hipSuccess) e = hipMalloc((void **)&g->d_states, S * sizeof(PcgState));
@@ -152,7 +152,7 @@ int take_slot(tg_server *srv, Group &g, tg_status &st) {
     SlotMem m;
     hipError_t e = hipMalloc(&m.values, std::max<size_t>(1, g.p->host.nnz) * elt);
     if (e == hipSuccess) e = hipMalloc(&m.b, std::max<size_t>(1, n) * elt);
-    if (e == hipSuccess) e = hipMalloc(&m.work, std::max<size_t>(1, 6 * n) * elt);
+    if (e == hipSuccess) e = hipMalloc(&m.work, std::max<size_t>(1, tg::kPcgWorkVectors * n) * elt);
     if (e == hipSuccess) e = hipMalloc((void **)&m.partials, kPartialBytes);
     if (e != hipSuccess) {
         (void)hipFree(m.values);
@@ -261,7 +261,7 @@ tg_status retire(tg_server *srv, Group &g) {
         e = tg::launch_pcg_residual(*g.p, g.dtype, g.d_slots, g.d_lists + 2 * S, (int)fin.size(), &ns, str);
     std::vector<double> parts(fin.size() * (size_t)std::max(ns, 1));
     for (size_t i = 0; i < fin.size() && e == hipSuccess; ++i)
-        e = hipMemcpyAsync(parts.data() + i * ns, g.mem[fin[i]].partials + (size_t)tg::kRR * tg::kMaxGrid,
+        e = hipMemcpyAsync(parts.data() + i * ns, g.mem[fin[i]].partials + (size_t)tg::kResid * tg::kMaxGrid,
                            ns * sizeof(double), hipMemcpyDeviceToHost, str);
     if (e == hipSuccess && !keep.empty())
         e = hipMemcpyAsync(g.d_lists, g.h_lists, keep.size() * sizeof(int32_t), hipMemcpyHostToDevice, str);

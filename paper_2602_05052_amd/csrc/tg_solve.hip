@@ -2,14 +2,10 @@
 // CSR system (TensorGalerkin Sec. B.1.2: Jacobi-preconditioned Krylov solve of
 // the condensed system, stopped on ||K u - f|| / ||f||).
 //
-// One CG iteration is two kernels of at most 512 blocks of 1024 threads:
-//   pcg_spmv   : stop test on r.r, beta = r.z / r.z_prev, p = z + beta p
-//                (formed on the fly into the other half of a double buffer),
-//                q = K p and per-block partials of p.q;
-//   pcg_update : alpha = r.z / p.q, x += alpha p, r -= alpha q, z = D^{-1} r,
-//                per-block partials of r.z and r.r.
-// Every scalar (alpha, beta, the stop decision) is recomputed by every block
-// from the previous kernel's partials, summed in one fixed order, so all
+// One CG iteration is one kernel of at most 512 blocks of 1024 threads (the
+// single-reduction form described with the PCG kernels below).  Every scalar
+// (alpha, beta, the stop decision) is recomputed by every block from the
+// previous launch's per-block partials, summed in one fixed order, so all
 // blocks agree bitwise and the solver is reproducible with no atomics, no
 // fences and no extra launches.
 #include <algorithm>
@@ -35,6 +31,36 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     for (int w = 0; w < kWaves; ++w) r += sh[w];
     __syncthreads();
     return r;
+}
+
+// Block sums of three values in the same fixed order as block_sum, delivered to
+// thread 0 only (the writer of the block's partials).  sh: 3 kWaves doubles.
+__device__ __forceinline__ void block_sum3_first(double &a, double &b, double &c, double *sh) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+        c += __shfl_xor(c, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        const int w = threadIdx.x >> 6;
+        sh[w] = a;
+        sh[kWaves + w] = b;
+        sh[2 * kWaves + w] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ra = 0.0, rb = 0.0, rc = 0.0;
+#pragma unroll 2
+        for (int w = 0; w < kWaves; ++w) {
+            ra += sh[w];
+            rb += sh[kWaves + w];
+            rc += sh[2 * kWaves + w];
+        }
+        a = ra;
+        b = rb;
+        c = rc;
+    }
 }
 
 // Sum of partials[0 .. n), n <= kVecThreads, identical in every block.
@@ -71,19 +97,14 @@ __global__ __launch_bounds__(256) void dirichlet_kernel(int nrows, const int32_t
     }
 }
 
-// Row i of K y, accumulated in FP64 by a group of G lanes in a fixed pattern,
-// where y_j = z_j + beta p_j if DIR, else y_j = x_j.
-template <typename T, int G, bool DIR>
+// Row i of K x, accumulated in FP64 by a group of G lanes in a fixed pattern
+// (VP, XP: pointers to T in any address space).
+template <int G, typename VP, typename XP>
 __device__ __forceinline__ double row_dot(int i, int lane, const int32_t *__restrict__ row_ptr,
-                                          const int32_t *__restrict__ col_idx, const T *__restrict__ values,
-                                          const T *__restrict__ x, const T *__restrict__ p, T beta) {
+                                          const int32_t *__restrict__ col_idx, VP values, XP x) {
     const int p0 = row_ptr[i], p1 = row_ptr[i + 1];
     double acc = 0.0;
-    for (int q = p0 + lane; q < p1; q += G) {
-        const int j = col_idx[q];
-        const T y = DIR ? x[j] + beta * p[j] : x[j];
-        acc += (double)values[q] * (double)y;
-    }
+    for (int q = p0 + lane; q < p1; q += G) acc += (double)values[q] * (double)x[col_idx[q]];
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
     return acc;
@@ -96,90 +117,177 @@ __global__ __launch_bounds__(256) void spmv_kernel(int n, const int32_t *__restr
     const int lane = threadIdx.x % G;
     const int rows_per_grid = gridDim.x * (256 / G);
     for (int i = blockIdx.x * (256 / G) + threadIdx.x / G; i < n; i += rows_per_grid) {
-        const double v = row_dot<T, G, false>(i, lane, row_ptr, col_idx, values, x, nullptr, (T)0);
+        const double v = row_dot<G>(i, lane, row_ptr, col_idx, values, x);
         if (lane == 0) y[i] = (T)v;
     }
 }
 
 // ---------------------------------------------------------------- PCG kernels
+// Preconditioned CG in the single-reduction form of Chronopoulos and Gear:
+// besides r, u = D^{-1} r, p and x it carries w = K u and s = K p, updated by
+// recurrences, so that the two inner products of an iteration, r.u and w.u,
+// come out of the same pass as the SpMV:
+//   beta_i  = gamma_i / gamma_{i-1},  alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1})
+//   p = u + beta p;  s = w + beta s;  x += alpha p;  r -= alpha s;  u = D^{-1} r;  w = K u
+//   gamma_{i+1} = r.u,  delta_{i+1} = w.u  (and r.r for the stop test)
+// with gamma_i = r_i.u_i, delta_i = w_i.u_i, beta_0 = 0, alpha_0 = gamma_0 / delta_0.
+// In exact arithmetic it produces the iterates of standard PCG.
+//
 // Each launch serves the slots slots[list[blockIdx.y]] (one CG system each, all
 // on the same pattern); blockIdx.x strides over the rows.  A slot's iteration
 // is step - start, so systems that joined at different steps share launches.
-// Slot workspace (T elements of n each): r, z, pA, pB, q, dinv.
+// One iteration is one launch: the SpMV needs the new u at neighbouring rows,
+// which every block recomputes from the previous iteration's record
+// {r, w, s, dinv} of that row with the same expressions its owner uses, so the
+// values agree bitwise and no grid-wide barrier is needed.  Records are double
+// buffered by iteration parity (the owner writes the new record while
+// neighbours still read the old one).
+
+// A slot's arrays are reached through pointers read from memory, which the
+// compiler cannot place in an address space; casting them to the global one
+// gives global (not flat) memory instructions.
+#define TG_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ TG_GLOBAL T *gl(T *p) {
+    return (TG_GLOBAL T *)p;
+}
+
+template <typename T>
+struct Rec {  // the per-row record gathered by the SpMV
+    T r, w, s, d;
+};
 
 template <typename T>
 struct SlotVecs {
-    T *r, *z, *pA, *pB, *q, *dinv;
+    TG_GLOBAL Rec<T> *rec0, *rec1;  // records of even and odd iterates
+    TG_GLOBAL T *p;
     __device__ __forceinline__ SlotVecs(const PcgSlot &S, int n) {
-        r = (T *)S.work;
-        z = r + n;
-        pA = z + n;
-        pB = pA + n;
-        q = pB + n;
-        dinv = q + n;
+        rec0 = gl((Rec<T> *)S.work);
+        rec1 = rec0 + n;
+        p = (TG_GLOBAL T *)(rec1 + n);
     }
+    __device__ __forceinline__ TG_GLOBAL Rec<T> *rec(int parity) const { return parity ? rec1 : rec0; }
 };
 
+// One record as one aligned 32-byte (FP64) or 16-byte (FP32) access.
+template <typename T>
+struct alignas(4 * sizeof(T)) Rec4 {
+    T v[4];
+};
+
+template <typename T>
+__device__ __forceinline__ Rec<T> load_rec(const TG_GLOBAL Rec<T> *__restrict__ a, int i) {
+    const TG_GLOBAL Rec4<T> *q = reinterpret_cast<const TG_GLOBAL Rec4<T> *>(a + i);
+    return Rec<T>{q->v[0], q->v[1], q->v[2], q->v[3]};
+}
+
+template <typename T>
+__device__ __forceinline__ void store_rec(TG_GLOBAL Rec<T> *__restrict__ a, int i, T r, T w, T s, T d) {
+    TG_GLOBAL Rec4<T> *q = reinterpret_cast<TG_GLOBAL Rec4<T> *>(a + i);
+    q->v[0] = r;
+    q->v[1] = w;
+    q->v[2] = s;
+    q->v[3] = d;
+}
+
+// The one definition of the recurrences, shared by a row's owner and by every
+// block that needs the row's new u as an SpMV column.
+template <typename T>
+__device__ __forceinline__ T next_s(const Rec<T> &o, T beta) { return o.w + beta * o.s; }
+template <typename T>
+__device__ __forceinline__ T next_r(const Rec<T> &o, T s_new, T alpha) { return o.r - alpha * s_new; }
+template <typename T>
+__device__ __forceinline__ T next_u(const Rec<T> &o, T beta, T alpha) {
+    return o.d * next_r(o, next_s(o, beta), alpha);
+}
+
+// x = 0, p = 0, r = b, s = 0, dinv = 1 / diag (record of parity 0; w follows).
 template <typename T>
 __global__ __launch_bounds__(kVecThreads) void pcg_init_kernel(int n, const PcgSlot *__restrict__ slots,
                                                                const int32_t *__restrict__ list,
                                                                const int32_t *__restrict__ diag_pos) {
-    __shared__ double sh[kWaves];
     const PcgSlot S = slots[list[blockIdx.y]];
     const SlotVecs<T> v(S, n);
-    const T *__restrict__ b = (const T *)S.b;
-    const T *__restrict__ values = (const T *)S.values;
-    T *__restrict__ x = (T *)S.x;
-    double rz = 0.0, bb = 0.0;
+    const TG_GLOBAL T *__restrict__ b = gl((const T *)S.b);
+    const TG_GLOBAL T *__restrict__ values = gl((const T *)S.values);
+    TG_GLOBAL T *__restrict__ x = gl((T *)S.x);
     for (int i = blockIdx.x * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads) {
-        const T bi = b[i];
-        const T di = (T)1 / values[diag_pos[i]];
-        const T zi = di * bi;
         x[i] = (T)0;
-        v.r[i] = bi;
-        v.z[i] = zi;
-        v.pA[i] = (T)0;
-        v.dinv[i] = di;
-        rz += (double)bi * (double)zi;
-        bb += (double)bi * (double)bi;
-    }
-    rz = block_sum(rz, sh);
-    bb = block_sum(bb, sh);
-    if (threadIdx.x == 0) {
-        part(S.partials, kRZ0)[blockIdx.x] = rz;
-        part(S.partials, kBB)[blockIdx.x] = bb;
+        v.p[i] = (T)0;
+        store_rec(v.rec0, i, b[i], (T)0, (T)0, (T)1 / values[diag_pos[i]]);
     }
 }
 
-// Stop test on the residual of the last update, then p_new = z + beta p_old,
-// q = K p_new and partials of p.q.  CHECK_ONLY launches stop after the test,
-// and so does iteration max_iter.  n_prev: number of partials written by the
-// previous kernel (init or update).
+// w_0 = K u_0 with u_0 = dinv r_0, and partials of r.u, w.u, r.r (parity 0).
+// Reads the r and dinv fields of neighbouring records and writes only the w
+// field of its own rows.
+template <typename T, int G>
+__global__ __launch_bounds__(kVecThreads, 8) void pcg_init_spmv_kernel(int n, const int32_t *__restrict__ row_ptr,
+                                                                    const int32_t *__restrict__ col_idx,
+                                                                    const PcgSlot *__restrict__ slots,
+                                                                    const int32_t *__restrict__ list) {
+    __shared__ double sh[3 * kWaves];
+    const PcgSlot S = slots[list[blockIdx.y]];
+    const SlotVecs<T> v(S, n);
+    TG_GLOBAL Rec<T> *__restrict__ rec = v.rec0;
+    const TG_GLOBAL T *__restrict__ values = gl((const T *)S.values);
+    const int lane = threadIdx.x % G;
+    const int rows_per_grid = gridDim.x * (kVecThreads / G);
+    double gam = 0.0, del = 0.0, rr = 0.0;
+    for (int i = blockIdx.x * (kVecThreads / G) + threadIdx.x / G; i < n; i += rows_per_grid) {
+        const int p0 = row_ptr[i], p1 = row_ptr[i + 1];
+        double acc = 0.0;
+#pragma unroll 2
+        for (int q = p0 + lane; q < p1; q += G) {
+            const int j = col_idx[q];
+            acc += (double)values[q] * (double)(rec[j].d * rec[j].r);
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+        if (lane == 0) {
+            const T ri = rec[i].r, ui = rec[i].d * ri, wi = (T)acc;
+            rec[i].w = wi;
+            gam += (double)ri * (double)ui;
+            del += (double)wi * (double)ui;
+            rr += (double)ri * (double)ri;
+        }
+    }
+    block_sum3_first(gam, del, rr, sh);
+    if (threadIdx.x == 0) {
+        part(S.partials, kGam)[blockIdx.x] = gam;
+        part(S.partials, kDel)[blockIdx.x] = del;
+        part(S.partials, kRr)[blockIdx.x] = rr;
+    }
+}
+
+// Iteration `it` of the system: stop test on r.r of the current iterate, then
+// the updates of every owned row and w = K u for them, with the partials of
+// the next iterate.  CHECK_ONLY launches stop after the test, and so does
+// iteration max_iter.  n_prev: number of partials written by the previous launch.
 template <typename T, int G, bool CHECK_ONLY>
-__global__ __launch_bounds__(kVecThreads) void pcg_spmv_kernel(int n, const int32_t *__restrict__ row_ptr,
+__global__ __launch_bounds__(kVecThreads, 8) void pcg_iter_kernel(int n, const int32_t *__restrict__ row_ptr,
                                                                const int32_t *__restrict__ col_idx,
                                                                const PcgSlot *__restrict__ slots,
                                                                const int32_t *__restrict__ list, int step,
                                                                int n_prev) {
-    __shared__ double sh[kWaves];
+    __shared__ double sh[3 * kWaves];
     const PcgSlot S = slots[list[blockIdx.y]];
     PcgState *__restrict__ st = S.state;
     const int it = step - S.start;
     if (st->done) return;  // written only by earlier launches: the same value for every wave
-    double tol2, rr;
+    const int cur = 3 * (it & 1), nxt = 3 * ((it + 1) & 1);
+    const double rr_cur = sum_partials(part(S.partials, kRr + cur), n_prev, sh);
+    double tol2;
     if (it == 0) {
-        const double bb = sum_partials(part(S.partials, kBB), n_prev, sh);
-        tol2 = S.rtol2 * bb;
-        rr = bb;
+        tol2 = S.rtol2 * rr_cur;
         if (blockIdx.x == 0 && threadIdx.x == 0) {
-            st->bb = bb;
+            st->bb = rr_cur;
             st->tol2 = tol2;
         }
     } else {
         tol2 = st->tol2;
-        rr = sum_partials(part(S.partials, kRR), n_prev, sh);
     }
-    if (rr <= tol2) {  // the same decision in every block
+    if (rr_cur <= tol2) {  // the same decision in every block
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st->done = 1;
             st->iters = it;
@@ -187,63 +295,60 @@ __global__ __launch_bounds__(kVecThreads) void pcg_spmv_kernel(int n, const int3
         return;
     }
     if (CHECK_ONLY || it >= S.max_iter) return;
-    const SlotVecs<T> v(S, n);
-    const T *__restrict__ values = (const T *)S.values;
-    const T *__restrict__ p_old = (it & 1) ? v.pB : v.pA;
-    T *__restrict__ p_new = (it & 1) ? v.pA : v.pB;
-    T beta = (T)0;
-    if (it > 0) {
-        const double rz = sum_partials(part(S.partials, kRZ0 + (it & 1)), n_prev, sh);
-        const double rz_prev = sum_partials(part(S.partials, kRZ0 + ((it + 1) & 1)), n_prev, sh);
-        beta = (T)(rz / rz_prev);
+    const double gam = sum_partials(part(S.partials, kGam + cur), n_prev, sh);
+    const double del = sum_partials(part(S.partials, kDel + cur), n_prev, sh);
+    double alpha_d, beta_d;
+    if (it == 0) {
+        beta_d = 0.0;
+        alpha_d = gam / del;
+    } else {
+        const double gam_prev = st->gamma[(it + 1) & 1], alpha_prev = st->alpha[(it + 1) & 1];
+        beta_d = gam / gam_prev;
+        alpha_d = gam / (del - beta_d * gam / alpha_prev);
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {  // read by the next launch only
+        st->alpha[it & 1] = alpha_d;
+        st->gamma[it & 1] = gam;
+    }
+    const T alpha = (T)alpha_d, beta = (T)beta_d;
+    const SlotVecs<T> v(S, n);
+    const TG_GLOBAL Rec<T> *__restrict__ ra = v.rec(it & 1);
+    TG_GLOBAL Rec<T> *__restrict__ rb = v.rec((it + 1) & 1);
+    const TG_GLOBAL T *__restrict__ values = gl((const T *)S.values);
+    TG_GLOBAL T *__restrict__ x = gl((T *)S.x);
     const int lane = threadIdx.x % G;
     const int rows_per_grid = gridDim.x * (kVecThreads / G);
-    double pq = 0.0;
+    double gn = 0.0, dn = 0.0, rn = 0.0;
     for (int i = blockIdx.x * (kVecThreads / G) + threadIdx.x / G; i < n; i += rows_per_grid) {
-        const double acc = row_dot<T, G, true>(i, lane, row_ptr, col_idx, values, v.z, p_old, beta);
+        const int p0 = row_ptr[i], p1 = row_ptr[i + 1];
+        double acc = 0.0;
+#pragma unroll 2
+        for (int q = p0 + lane; q < p1; q += G) {
+            const int j = col_idx[q];
+            acc += (double)values[q] * (double)next_u(load_rec(ra, j), beta, alpha);
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
         if (lane == 0) {
-            const T pi = v.z[i] + beta * p_old[i];
-            const T qi = (T)acc;
-            p_new[i] = pi;
-            v.q[i] = qi;
-            pq += (double)pi * (double)qi;
+            const Rec<T> o = load_rec(ra, i);
+            const T pi = o.d * o.r + beta * v.p[i];  // u_i + beta p
+            const T si = next_s(o, beta);
+            const T ri = next_r(o, si, alpha);
+            const T ui = o.d * ri;
+            const T wi = (T)acc;
+            x[i] += alpha * pi;
+            v.p[i] = pi;
+            store_rec(rb, i, ri, wi, si, o.d);
+            gn += (double)ri * (double)ui;
+            dn += (double)wi * (double)ui;
+            rn += (double)ri * (double)ri;
         }
     }
-    pq = block_sum(pq, sh);
-    if (threadIdx.x == 0) part(S.partials, kPQ)[blockIdx.x] = pq;
-}
-
-// alpha = r.z / p.q; x += alpha p; r -= alpha q; z = D^{-1} r; partials of r.z (next buffer) and r.r
-template <typename T>
-__global__ __launch_bounds__(kVecThreads) void pcg_update_kernel(int n, const PcgSlot *__restrict__ slots,
-                                                                 const int32_t *__restrict__ list, int step,
-                                                                 int n_pq, int n_rz) {
-    __shared__ double sh[kWaves];
-    const PcgSlot S = slots[list[blockIdx.y]];
-    const int it = step - S.start;
-    if (S.state->done || it >= S.max_iter) return;  // done: written only by earlier launches
-    const SlotVecs<T> v(S, n);
-    const T *__restrict__ p = (it & 1) ? v.pA : v.pB;  // the p_new of this iteration's spmv
-    T *__restrict__ x = (T *)S.x;
-    const double pq = sum_partials(part(S.partials, kPQ), n_pq, sh);
-    const double rz = sum_partials(part(S.partials, kRZ0 + (it & 1)), n_rz, sh);
-    const T a = (T)(rz / pq);
-    double rzn = 0.0, rr = 0.0;
-    for (int i = blockIdx.x * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads) {
-        const T ri = v.r[i] - a * v.q[i];
-        x[i] += a * p[i];
-        const T zi = v.dinv[i] * ri;
-        v.r[i] = ri;
-        v.z[i] = zi;
-        rzn += (double)ri * (double)zi;
-        rr += (double)ri * (double)ri;
-    }
-    rzn = block_sum(rzn, sh);
-    rr = block_sum(rr, sh);
+    block_sum3_first(gn, dn, rn, sh);
     if (threadIdx.x == 0) {
-        part(S.partials, kRZ0 + ((it + 1) & 1))[blockIdx.x] = rzn;
-        part(S.partials, kRR)[blockIdx.x] = rr;
+        part(S.partials, kGam + nxt)[blockIdx.x] = gn;
+        part(S.partials, kDel + nxt)[blockIdx.x] = dn;
+        part(S.partials, kRr + nxt)[blockIdx.x] = rn;
     }
 }
 
@@ -255,21 +360,21 @@ __global__ __launch_bounds__(kVecThreads) void residual_kernel(int n, const int3
                                                                const int32_t *__restrict__ list) {
     __shared__ double sh[kWaves];
     const PcgSlot S = slots[list[blockIdx.y]];
-    const T *__restrict__ values = (const T *)S.values;
-    const T *__restrict__ x = (const T *)S.x;
-    const T *__restrict__ b = (const T *)S.b;
+    const TG_GLOBAL T *__restrict__ values = gl((const T *)S.values);
+    const TG_GLOBAL T *__restrict__ x = gl((const T *)S.x);
+    const TG_GLOBAL T *__restrict__ b = gl((const T *)S.b);
     const int lane = threadIdx.x % G;
     const int rows_per_grid = gridDim.x * (kVecThreads / G);
     double acc = 0.0;
     for (int i = blockIdx.x * (kVecThreads / G) + threadIdx.x / G; i < n; i += rows_per_grid) {
-        const double v = row_dot<T, G, false>(i, lane, row_ptr, col_idx, values, x, nullptr, (T)0);
+        const double v = row_dot<G>(i, lane, row_ptr, col_idx, values, x);
         if (lane == 0) {
             const double ri = (double)b[i] - v;
             acc += ri * ri;
         }
     }
     acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) part(S.partials, kRR)[blockIdx.x] = acc;
+    if (threadIdx.x == 0) part(S.partials, kResid)[blockIdx.x] = acc;
 }
 
 int vec_blocks(int64_t n) {
@@ -320,25 +425,25 @@ void launch_init_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *li
     const int n = (int)pt.host.n_dofs;
     hipLaunchKernelGGL(pcg_init_kernel<T>, dim3(vec_blocks(n), count), dim3(kVecThreads), 0, s, n, slots, list,
                        pt.dev.diag_pos);
+    hipLaunchKernelGGL((pcg_init_spmv_kernel<T, G>), dim3(spmv_blocks<G>(n), count), dim3(kVecThreads), 0, s, n,
+                       pt.dev.row_ptr, pt.dev.col_idx, slots, list);
 }
 
 template <typename T, int G>
 void launch_step_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *list, int count, int step,
                    hipStream_t s) {
     const int n = (int)pt.host.n_dofs;
-    const int nb = vec_blocks(n), ns = spmv_blocks<G>(n);
-    hipLaunchKernelGGL((pcg_spmv_kernel<T, G, false>), dim3(ns, count), dim3(kVecThreads), 0, s, n,
-                       pt.dev.row_ptr, pt.dev.col_idx, slots, list, step, nb);
-    hipLaunchKernelGGL(pcg_update_kernel<T>, dim3(nb, count), dim3(kVecThreads), 0, s, n, slots, list, step, ns,
-                       nb);
+    const int ns = spmv_blocks<G>(n);
+    hipLaunchKernelGGL((pcg_iter_kernel<T, G, false>), dim3(ns, count), dim3(kVecThreads), 0, s, n, pt.dev.row_ptr,
+                       pt.dev.col_idx, slots, list, step, ns);
 }
 
 template <typename T, int G>
 void launch_check_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *list, int count, int step,
                     hipStream_t s) {
     const int n = (int)pt.host.n_dofs;
-    hipLaunchKernelGGL((pcg_spmv_kernel<T, G, true>), dim3(1, count), dim3(kVecThreads), 0, s, n, pt.dev.row_ptr,
-                       pt.dev.col_idx, slots, list, step, vec_blocks(n));
+    hipLaunchKernelGGL((pcg_iter_kernel<T, G, true>), dim3(1, count), dim3(kVecThreads), 0, s, n, pt.dev.row_ptr,
+                       pt.dev.col_idx, slots, list, step, spmv_blocks<G>(n));
 }
 
 template <typename T, int G>
@@ -442,7 +547,7 @@ tg_status run_pcg(const tg_pattern &pt, tg_dtype dtype, const void *values, cons
     TG_CHECK(launch_pcg_residual(pt, dtype, d.pcg_slot, d.pcg_list, 1, &ns, s));
     std::vector<double> host_parts(ns);
     TG_CHECK(hipMemcpyAsync(d.host_state, d.state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-    TG_CHECK(hipMemcpyAsync(host_parts.data(), d.partials + (size_t)kRR * kMaxGrid, sizeof(double) * ns,
+    TG_CHECK(hipMemcpyAsync(host_parts.data(), d.partials + (size_t)kResid * kMaxGrid, sizeof(double) * ns,
                             hipMemcpyDeviceToHost, s));
     TG_CHECK(hipStreamSynchronize(s));
 #undef TG_CHECK
