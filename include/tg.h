@@ -160,13 +160,14 @@ tg_status tg_pattern_copy_element_nodes(const tg_pattern *p, int32_t *h_nodes);
  *       block.
  */
 /*
- * P1 patterns: the coordinate staging of the fused kernel.  Row block b reads
- * the coordinates of its elements' distinct vertices
+ * The coordinate staging of the fused kernels.  Row block b reads the
+ * coordinates of its elements' distinct vertices
  * h_blk_vert[h_blk_vptr[b] .. h_blk_vptr[b+1]) (ascending, at most 256) into
  * LDS once; pair t (in S_vec order) finds the vertices of its element at the
- * block-local positions (h_pair_lv[t] >> 8a) & 255, a = 0..dim.  *n_vert
- * receives the length of h_blk_vert (call with NULL arrays first).  Any array
- * may be NULL; h_blk_vptr [B+1], h_pair_lv [P].  TG_E_ARG for P2 patterns.
+ * block-local positions (h_pair_lv[t] >> 8a) & 255, a = 0..dim (for P2 the
+ * element's 4 vertex nodes).  *n_vert receives the length of h_blk_vert (call
+ * with NULL arrays first).  Any array may be NULL; h_blk_vptr [B+1],
+ * h_pair_lv [P].
  */
 tg_status tg_pattern_copy_block_vertices(const tg_pattern *p, int64_t *n_vert, int32_t *h_blk_vptr,
                                          int32_t *h_blk_vert, uint32_t *h_pair_lv);

@@ -257,7 +257,7 @@ class Pattern:
         return out
 
     def block_vertices(self):
-        """P1: (blk_vptr [B+1], blk_vert, pair_lv [P]) of the kernel's per-block coordinate staging."""
+        """(blk_vptr [B+1], blk_vert, pair_lv [P]) of the kernels' per-block coordinate staging."""
         nvert = ctypes.c_int64(0)
         _check(_lib.tg_pattern_copy_block_vertices(self._h, ctypes.byref(nvert), None, None, None))
         vptr = np.zeros(self.n_blocks + 1, dtype=np.int32)

@@ -224,7 +224,6 @@ tg_status tg_pattern_copy_block_vertices(const tg_pattern *p, int64_t *n_vert, i
                                          int32_t *h_blk_vert, uint32_t *h_pair_lv) {
     if (!p) return fail(TG_E_ARG, "pattern is NULL");
     const tg::HostPattern &h = p->host;
-    if (h.order != 1) return fail(TG_E_ARG, "block vertex lists exist for P1 patterns only");
     if (n_vert) *n_vert = (int64_t)h.blk_vert.size();
     if (h_blk_vptr) {
         const int64_t nb = h.n_blocks();

@@ -250,8 +250,18 @@ __device__ __forceinline__ void lds_vertices(const double *lx, uint32_t lv, doub
     }
 }
 
+// Minimum waves per SIMD the register allocation must allow: 8 for the
+// single-set Laplace kernels (they fit in 64 VGPRs without spilling), 7 for the
+// mass forms, 5 for the batched kernels (they keep the pair's geometry live
+// across the member loop).
+template <typename T, int FORM, bool BATCHED>
+constexpr int p1_waves_per_eu() {
+    return BATCHED ? 5 : (FORM == 0 ? 8 : 7);
+}
+
 template <int D, typename T, int FORM, bool LOAD, bool BATCHED>
-__global__ __launch_bounds__(kP1Threads, 8) void p1_assemble_kernel(
+__global__ __launch_bounds__(kP1Threads) __attribute__((amdgpu_waves_per_eu(p1_waves_per_eu<T, FORM, BATCHED>())))
+void p1_assemble_kernel(
     const int32_t *__restrict__ blk_desc, const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc,
     const int32_t *__restrict__ seg_ptr, const uint16_t *__restrict__ slot, const int32_t *__restrict__ blk_vert,
     const uint32_t *__restrict__ pair_lv, const double *__restrict__ coords, const T *__restrict__ coef,
@@ -300,11 +310,14 @@ __global__ __launch_bounds__(kP1Threads, 8) void p1_assemble_kernel(
     unsigned e = 0;
     int a = 0;
     uint32_t lv = 0;
+    double c_next = 1.0, f_next = 0.0;  // coefficients of the next member, fetched ahead
     if (own) {
         const unsigned code = (unsigned)ldg(inc, (unsigned)(q0 + tid));
         lv = ldg(pair_lv, (unsigned)(q0 + tid));
         e = code / K;
         a = (int)(code - e * K);
+        if (BATCHED && COEF) c_next = (double)ldg(coef, e);
+        if (BATCHED && LOAD) f_next = (double)ldg(load, e);
     }
     __syncthreads();  // the vertex copy is complete
     P1Geom<D> g;
@@ -319,10 +332,17 @@ __global__ __launch_bounds__(kP1Threads, 8) void p1_assemble_kernel(
     const int nmem = BATCHED ? nbatch : 1;
     for (int m = 0; m < nmem; ++m) {
         const unsigned eo = (unsigned)m * n_elem;
+        double c = c_next, f = f_next;
+        if (!BATCHED && own) {
+            if (COEF) c = (double)ldg(coef, e);
+            if (LOAD) f = (double)ldg(load, e);
+        }
+        if (BATCHED && own && m + 1 < nmem) {  // the next member's coefficients, fetched ahead
+            if (COEF) c_next = (double)ldg(coef, eo + n_elem + e);
+            if (LOAD) f_next = (double)ldg(load, eo + n_elem + e);
+        }
         // ---- Map: row a of the local matrix (and F_e[a]) for member m
         if (own) {
-            const double c = COEF ? (double)ldg(coef, eo + e) : 1.0;
-            const double f = LOAD ? (double)ldg(load, eo + e) : 0.0;
             T row[K], fa;
             p1_row<D, T, FORM>(g, a, c, f, row, fa);
 #pragma unroll
@@ -388,30 +408,42 @@ __global__ __launch_bounds__(kP1Threads, 8) void p1_assemble_kernel(
 
 // ---------------------------------------------------------------- P2 elasticity
 
-constexpr int kP2LanesPerPair = 4;
+constexpr int kP2LanesPerPair = 8;
 
-// grad(phi_n) at Keast point q (compile time) for P2 node n (run time):
-// vertex p: (4 lambda_p - 1) grad(lambda_p); edge (i,j): 4 (lambda_j grad(lambda_i)
-// + lambda_i grad(lambda_j)).  Written as sum_p c_p grad(lambda_p) with the
-// coefficients chosen by comparisons against the compile-time p, so no array
-// is indexed with a run-time value (that would go through scratch memory).
-// Nodes: vertices 0..3, then edges (0,1),(0,2),(0,3),(1,2),(1,3),(2,3).
-template <typename T, int Q>
-__device__ __forceinline__ void p2_grad(int n, const T (&g)[4][3], T hi, T lo, T (&out)[3]) {
+// Vertices (i, j) of P2 local node n (vertices 0..3, then edges (0,1),(0,2),(0,3),
+// (1,2),(1,3),(2,3)); a vertex node has i = j = n.
+__device__ __forceinline__ void p2_node(int n, int &i, int &j) {
     const bool vtx = n < 4;
-    const int i = vtx ? n : (n < 7 ? 0 : (n < 9 ? 1 : 2));
-    const int j = vtx ? n : (n == 4 ? 1 : (n == 5 || n == 7) ? 2 : 3);
-    const T li = (i == Q) ? hi : lo;  // lambda_i at the point
-    const T lj = (j == Q) ? hi : lo;
-    const T ci = vtx ? (T)4 * li - (T)1 : (T)4 * lj;  // coefficient of grad(lambda_i)
-    const T cj = vtx ? (T)0 : (T)4 * li;              // coefficient of grad(lambda_j)
+    i = vtx ? n : (n < 7 ? 0 : (n < 9 ? 1 : 2));
+    j = vtx ? n : (n == 4 ? 1 : (n == 5 || n == 7) ? 2 : 3);
+}
+
+// grad(phi_n) at the 4 Keast points: vertex p: (4 lambda_p - 1) grad(lambda_p);
+// edge (i,j): 4 (lambda_j grad(lambda_i) + lambda_i grad(lambda_j)), with
+// lambda_p = hi at point p and lo elsewhere.  g: the pair's grad(lambda_p), [4][3].
+template <typename T>
+__device__ __forceinline__ void p2_node_grads(int n, const T (&g)[4][3], T (&out)[4][3]) {
+    using R = Deg2Rule<3>;
+    int i, j;
+    p2_node(n, i, j);
+    const bool vtx = n < 4;
+    // rows i and j of g, selected without a run-time index into the register array
+    T gi[3] = {}, gj[3] = {};
 #pragma unroll
-    for (int c = 0; c < 3; ++c) out[c] = 0;
+    for (int p = 0; p < 4; ++p)
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const T cp = (p == i) ? ci : ((p == j) ? cj : (T)0);
+        for (int c = 0; c < 3; ++c) {
+            gi[c] = (p == i) ? g[p][c] : gi[c];
+            gj[c] = (p == j) ? g[p][c] : gj[c];
+        }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) out[c] += cp * g[p][c];
+    for (int q = 0; q < 4; ++q) {
+        const T li = (i == q) ? (T)R::hi : (T)R::lo;  // lambda_i at the point
+        const T lj = (j == q) ? (T)R::hi : (T)R::lo;
+        const T ci = vtx ? (T)4 * li - (T)1 : (T)4 * lj;  // coefficient of grad(lambda_i)
+        const T cj = vtx ? (T)0 : (T)4 * li;              // coefficient of grad(lambda_j)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[q][c] = ci * gi[c] + cj * gj[c];
     }
 }
 
@@ -435,36 +467,46 @@ __device__ __forceinline__ double p2_ref_integral(int n) {
 
 template <typename T>
 __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
-    const int32_t *__restrict__ blk_row, const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc,
+    const int32_t *__restrict__ blk_desc, const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc,
     const int32_t *__restrict__ node_rp, const int32_t *__restrict__ seg_ptr, const uint16_t *__restrict__ slot,
-    const int32_t *__restrict__ conn, const double *__restrict__ coords, const T *__restrict__ coef,
-    const T *__restrict__ load, T *__restrict__ values, T *__restrict__ rhs, int32_t *__restrict__ status, int nblk,
-    int E, int mp, int me) {
+    const int32_t *__restrict__ blk_vert, const uint32_t *__restrict__ pair_lv, const double *__restrict__ coords,
+    const T *__restrict__ coef, const T *__restrict__ load, T *__restrict__ values, T *__restrict__ rhs,
+    int32_t *__restrict__ status, int nblk, int E, int mp, int me) {
     constexpr int K = 10;
+    constexpr int VS = VertLds<3>::VS;
     extern __shared__ __align__(16) unsigned char smem[];
     BlockLds<T> L(smem, mp, me, 9 * K, 3, K);
+    double *Lx = reinterpret_cast<double *>(smem + VertLds<3>::offset(BlockLds<T>::bytes(mp, me, 9 * K, 3, K)));
     __shared__ int sRp[kP2BlockCap + 1];
 
     const int blk = xcd_swizzle(blockIdx.x, nblk);
-    const int r0 = blk_row[blk], r1 = blk_row[blk + 1];
-    const int q0 = inc_ptr[r0], q1 = inc_ptr[r1];
-    const int rp0 = node_rp[r0], rp1 = node_rp[r1];
-    const int np = q1 - q0, nent = rp1 - rp0;
+    const int4 dsc = ldg(reinterpret_cast<const int4 *>(blk_desc), 2u * blk);
+    const int4 dsv = ldg(reinterpret_cast<const int4 *>(blk_desc), 2u * blk + 1u);
+    const int r0 = dsc.x, r1 = dsc.y, q0 = dsc.z, q1 = dsc.w, rp0 = dsv.x, rp1 = dsv.y, w0 = dsv.z, w1 = dsv.w;
+    const int np = q1 - q0, nent = rp1 - rp0, nvb = w1 - w0;
     const int nrows = r1 - r0;
     const int s0 = q0 * K;
     for (int r = threadIdx.x; r <= nrows; r += kP2Threads) sRp[r] = node_rp[r0 + r] - rp0;
     for (int t = threadIdx.x; t <= nent; t += kP2Threads) L.seg[t] = seg_ptr[rp0 + t] - s0;
     for (int t = threadIdx.x; t < np * K / 2; t += kP2Threads)  // s0 and np K are even: 4-byte copies
         reinterpret_cast<uint32_t *>(L.slot)[t] = reinterpret_cast<const uint32_t *>(slot + s0)[t];
+    for (int t = threadIdx.x; t < nvb * 3; t += kP2Threads) {  // one coordinate per lane
+        const int l = t / 3, c = t - 3 * l;
+        Lx[l * VS + c] = ldg(coords, 3u * (unsigned)ldg(blk_vert, (unsigned)(w0 + l)) + (unsigned)c);
+    }
+    __syncthreads();
 
-    // ---- Map: block row a of K_e (10 blocks of 3x3), split over 4 lanes by column node
+    // ---- Map: block row a of K_e (10 blocks of 3x3), kP2LanesPerPair lanes per pair
+    // split by column node b; each lane forms the pair's geometry itself (no
+    // extra barrier).  grad(phi_n) at Keast point q is c_i(q) grad(lambda_i) +
+    // c_j(q) grad(lambda_j) for the node's vertices i, j (see p2_node).
     using R = Deg2Rule<3>;
     for (int u = threadIdx.x; u < np * kP2LanesPerPair; u += kP2Threads) {
         const int t = u / kP2LanesPerPair, sub = u - t * kP2LanesPerPair;
         const int code = inc[q0 + t];
         const int e = code / K, a = code - e * K;
         double x[4][3], Gd[4][3];
-        load_vertices<3>(conn, coords, e, x);
+        lds_vertices<3>(Lx, ldg(pair_lv, (unsigned)(q0 + t)), x);
         const double lam_d = (double)coef[e], mu_d = (double)coef[(size_t)E + e];
         const double det = p1_gradients<3>(x, Gd);
         const double adet = fabs(det);
@@ -474,22 +516,15 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
         for (int p = 0; p < 4; ++p)
 #pragma unroll
             for (int c = 0; c < 3; ++c) g[p][c] = (T)Gd[p][c];
-        const T hi = (T)R::hi, lo = (T)R::lo;
         const T w = (T)(adet * R::w);
         const T lam = (T)lam_d, mu = (T)mu_d;
         T ga[4][3];
-        p2_grad<T, 0>(a, g, hi, lo, ga[0]);
-        p2_grad<T, 1>(a, g, hi, lo, ga[1]);
-        p2_grad<T, 2>(a, g, hi, lo, ga[2]);
-        p2_grad<T, 3>(a, g, hi, lo, ga[3]);
+        p2_node_grads<T>(a, g, ga);
         for (int b = sub; b < K; b += kP2LanesPerPair) {
             // D_ab = sum_q w_q |det J| grad(phi_a) grad(phi_b)^T
-            T Dm[3][3] = {};
             T gb[4][3];
-            p2_grad<T, 0>(b, g, hi, lo, gb[0]);
-            p2_grad<T, 1>(b, g, hi, lo, gb[1]);
-            p2_grad<T, 2>(b, g, hi, lo, gb[2]);
-            p2_grad<T, 3>(b, g, hi, lo, gb[3]);
+            p2_node_grads<T>(b, g, gb);
+            T Dm[3][3] = {};
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -519,25 +554,27 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     }
     __syncthreads();
 
-    // ---- Reduce: the block's scalar values are the contiguous range [9 rp0, 9 rp1)
-    const int nval = 9 * nent;
-    T *out = values + 9 * (size_t)rp0;
-    for (int v = threadIdx.x; v < nval; v += kP2Threads) {
-        int lo_r = 0, hi_r = nrows - 1;  // last row with 9 * sRp[r] <= v
-        while (lo_r < hi_r) {
-            const int mid = (lo_r + hi_r + 1) >> 1;
-            if (9 * sRp[mid] <= v) lo_r = mid;
-            else hi_r = mid - 1;
+    // ---- Reduce: one lane per node-level entry sums its routed 3x3 blocks (ascending
+    // element order, components in parallel) and writes the 9 scalars.  Entry pe of
+    // row r, column position jpos, lands at 9 sRp[r] + c (3 m) + 3 jpos + cc of the
+    // block's contiguous value range (the 3 DoF rows of a node share its columns).
+    for (int pe = threadIdx.x; pe < nent; pe += kP2Threads) {
+        int r = 0;
+        while (sRp[r + 1] <= pe) ++r;
+        const int m = sRp[r + 1] - sRp[r], jpos = pe - sRp[r];
+        T acc[9];
+#pragma unroll
+        for (int z = 0; z < 9; ++z) acc[z] = 0;
+        for (int u = L.seg[pe]; u < L.seg[pe + 1]; ++u) {
+            const T *src = L.K + (int)L.slot[u] * 9;
+#pragma unroll
+            for (int z = 0; z < 9; ++z) acc[z] += src[z];
         }
-        const int r = lo_r;
-        const int m = sRp[r + 1] - sRp[r];
-        const int off = v - 9 * sRp[r];
-        const int c = off / (3 * m);
-        const int rem = off - c * 3 * m;
-        const int jpos = rem / 3;
-        const int cc = rem - 3 * jpos;
-        const int pe = sRp[r] + jpos;  // node-level entry within the block
-        out[v] = segment_sum<T, 9>(L.K, L.slot, L.seg[pe], L.seg[pe + 1], c * 3 + cc);
+        T *o = values + 9 * (size_t)rp0 + 9 * sRp[r] + 3 * jpos;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) o[c * 3 * m + cc] = acc[c * 3 + cc];
     }
     if (rhs && load) {
         for (int u = threadIdx.x; u < 3 * nrows; u += kP2Threads) {
@@ -611,16 +648,19 @@ hipError_t launch_assemble_p2(const tg_pattern &p, tg_dtype dtype, const double 
     const int nblk = (int)p.host.n_blocks();
     const int E = (int)p.host.E;
     const int mp = p.host.max_block_pairs, me = p.host.max_block_entries;
+    const size_t verts = VertLds<3>::bytes(p.host.max_block_verts);
     if (dtype == TG_F64)
         hipLaunchKernelGGL(p2_elasticity_kernel<double>, dim3(nblk), dim3(kP2Threads),
-                           BlockLds<double>::bytes(mp, me, 90, 3, 10), s, d.blk_row, d.inc_ptr, d.inc, d.node_rp,
-                           d.seg_ptr, d.slot, d.conn, coords, (const double *)coef, (const double *)load,
-                           (double *)values, (double *)rhs, status, nblk, E, mp, me);
+                           VertLds<3>::offset(BlockLds<double>::bytes(mp, me, 90, 3, 10)) + verts, s, d.blk_desc,
+                           d.inc_ptr, d.inc, d.node_rp, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, coords,
+                           (const double *)coef, (const double *)load, (double *)values, (double *)rhs, status, nblk,
+                           E, mp, me);
     else
         hipLaunchKernelGGL(p2_elasticity_kernel<float>, dim3(nblk), dim3(kP2Threads),
-                           BlockLds<float>::bytes(mp, me, 90, 3, 10), s, d.blk_row, d.inc_ptr, d.inc, d.node_rp,
-                           d.seg_ptr, d.slot, d.conn, coords, (const float *)coef, (const float *)load,
-                           (float *)values, (float *)rhs, status, nblk, E, mp, me);
+                           VertLds<3>::offset(BlockLds<float>::bytes(mp, me, 90, 3, 10)) + verts, s, d.blk_desc,
+                           d.inc_ptr, d.inc, d.node_rp, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, coords,
+                           (const float *)coef, (const float *)load, (float *)values, (float *)rhs, status, nblk, E,
+                           mp, me);
     return hipGetLastError();
 }
 

@@ -18,9 +18,9 @@ namespace tg {
 constexpr int kP1Threads = 256;
 constexpr int kP1BlockTarget = 256;
 constexpr int kP1BlockCap = 512;
-constexpr int kP1BlockVerts = 256;  // distinct vertices of a P1 block (8-bit local ids)
+constexpr int kP1BlockVerts = 256;  // distinct vertices of a block (8-bit local ids)
 constexpr int kP2Threads = 256;
-constexpr int kP2BlockTarget = 64;
+constexpr int kP2BlockTarget = 32;
 constexpr int kP2BlockCap = 64;
 
 // Host-side topology of one mesh: numbering, node-level CSR and the routing
@@ -42,8 +42,8 @@ struct HostPattern {
     // Row blocks for the fused kernels.
     std::vector<int32_t> blk_row;   // [n_blocks+1]
     std::vector<int32_t> blk_desc;  // [n_blocks][8]: r0, r1, q0, q1, v0, v1, w0, w1 (rows, pairs, node entries, vertices)
-    // P1 only: the distinct vertices of each block's elements (ascending), and per
-    // pair the block-local ids of its element's vertices, one byte each in local
+    // The distinct vertices of each block's elements (ascending), and per pair
+    // the block-local ids of its element's vertices, one byte each in local
     // vertex order (the Map reads coordinates from a per-block LDS copy).
     std::vector<int32_t> blk_vert;  // [sum of block vertex counts]
     std::vector<uint32_t> pair_lv;  // [n_pairs]
@@ -63,7 +63,7 @@ struct HostPattern {
     // Largest row block, for sizing the kernels' LDS.
     int32_t max_block_pairs = 0;
     int32_t max_block_entries = 0;  // node-level CSR entries
-    int32_t max_block_verts = 0;    // P1: distinct vertices
+    int32_t max_block_verts = 0;    // distinct vertices
 
     int64_t n_pairs() const { return (int64_t)inc.size(); }
     int64_t n_blocks() const { return (int64_t)blk_row.size() - 1; }
@@ -113,8 +113,8 @@ struct DevicePattern {
     int32_t *inc = nullptr;       // [n_pairs]
     int32_t *blk_row = nullptr;   // [n_blocks+1]
     int32_t *blk_desc = nullptr;  // [n_blocks][8]
-    int32_t *blk_vert = nullptr;  // P1: block vertex lists
-    uint32_t *pair_lv = nullptr;  // P1: [n_pairs] packed block-local vertex ids
+    int32_t *blk_vert = nullptr;  // block vertex lists
+    uint32_t *pair_lv = nullptr;  // [n_pairs] packed block-local vertex ids
     int32_t *node_rp = nullptr;   // [n_nodes+1]
     int32_t *node_ci = nullptr;   // [nnz_nodes]
     int32_t *seg_ptr = nullptr;   // [nnz_nodes+1]

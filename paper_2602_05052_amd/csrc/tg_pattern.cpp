@@ -286,11 +286,14 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
         hp.max_block_pairs = std::max(hp.max_block_pairs, hp.inc_ptr[r1] - hp.inc_ptr[r0]);
         hp.max_block_entries = std::max(hp.max_block_entries, hp.node_rp[r1] - hp.node_rp[r0]);
     }
-    // ---- P1: block vertex lists and the per-pair block-local vertex ids
+    // ---- block vertex lists and the per-pair block-local ids of the element's
+    // vertices (its first dim + 1 nodes; P2 blocks hold at most 64 pairs, so
+    // at most 256 vertices)
     hp.blk_vert.clear();
     hp.pair_lv.clear();
     hp.max_block_verts = 0;
-    if (p1) {
+    {
+        const int kv = dim + 1;
         hp.pair_lv.assign((size_t)E * k, 0u);
         std::vector<int32_t> local(hp.nv, -1), verts;
         for (int64_t b = 0; b + 1 < (int64_t)hp.blk_row.size(); ++b) {
@@ -299,11 +302,11 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
             verts.clear();
             for (int32_t t = q0; t < q1; ++t) {
                 const int64_t e = hp.inc[t] / k;
-                for (int a = 0; a < k; ++a) verts.push_back(hp.elem_nodes[e * k + a]);
+                for (int a = 0; a < kv; ++a) verts.push_back(hp.elem_nodes[e * k + a]);
             }
             std::sort(verts.begin(), verts.end());
             verts.erase(std::unique(verts.begin(), verts.end()), verts.end());
-            if ((int)verts.size() > kP1BlockVerts) {  // the greedy partition above prevents this
+            if ((int)verts.size() > kP1BlockVerts) {  // the block partition above prevents this
                 msg = "internal error: block vertex capacity exceeded";
                 return TG_E_ARG;
             }
@@ -317,7 +320,7 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
             for (int32_t t = q0; t < q1; ++t) {
                 const int64_t e = hp.inc[t] / k;
                 uint32_t w = 0;
-                for (int a = 0; a < k; ++a) w |= (uint32_t)local[hp.elem_nodes[e * k + a]] << (8 * a);
+                for (int a = 0; a < kv; ++a) w |= (uint32_t)local[hp.elem_nodes[e * k + a]] << (8 * a);
                 hp.pair_lv[t] = w;
             }
             for (int32_t v : verts) local[v] = -1;

@@ -63,10 +63,42 @@ __device__ __forceinline__ void block_sum3_first(double &a, double &b, double &c
     }
 }
 
-// Sum of partials[0 .. n), n <= kVecThreads, identical in every block.
-__device__ __forceinline__ double sum_partials(const double *__restrict__ partials, int n, double *sh) {
-    return block_sum((int)threadIdx.x < n ? partials[threadIdx.x] : 0.0, sh);
+// Sums of three partial arrays [0 .. n), n <= kVecThreads, identical in every
+// block and in the same order as sum_partials, with one pair of barriers.
+// sh: 3 kWaves doubles.
+__device__ __forceinline__ void sum_partials3(const double *__restrict__ p0, const double *__restrict__ p1,
+                                              const double *__restrict__ p2, int n, double *sh, double &a,
+                                              double &b, double &c) {
+    const bool in = (int)threadIdx.x < n;
+    a = in ? p0[threadIdx.x] : 0.0;
+    b = in ? p1[threadIdx.x] : 0.0;
+    c = in ? p2[threadIdx.x] : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+        c += __shfl_xor(c, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        const int w = threadIdx.x >> 6;
+        sh[w] = a;
+        sh[kWaves + w] = b;
+        sh[2 * kWaves + w] = c;
+    }
+    __syncthreads();
+    double ra = 0.0, rb = 0.0, rc = 0.0;
+#pragma unroll 2
+    for (int w = 0; w < kWaves; ++w) {
+        ra += sh[w];
+        rb += sh[kWaves + w];
+        rc += sh[2 * kWaves + w];
+    }
+    __syncthreads();
+    a = ra;
+    b = rb;
+    c = rc;
 }
+
 
 __device__ __forceinline__ double *part(double *base, int which) { return base + (size_t)which * kMaxGrid; }
 
@@ -276,7 +308,9 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_iter_kernel(int n, const i
     const int it = step - S.start;
     if (st->done) return;  // written only by earlier launches: the same value for every wave
     const int cur = 3 * (it & 1), nxt = 3 * ((it + 1) & 1);
-    const double rr_cur = sum_partials(part(S.partials, kRr + cur), n_prev, sh);
+    double rr_cur, gam, del;
+    sum_partials3(part(S.partials, kRr + cur), part(S.partials, kGam + cur), part(S.partials, kDel + cur), n_prev,
+                  sh, rr_cur, gam, del);
     double tol2;
     if (it == 0) {
         tol2 = S.rtol2 * rr_cur;
@@ -295,8 +329,6 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_iter_kernel(int n, const i
         return;
     }
     if (CHECK_ONLY || it >= S.max_iter) return;
-    const double gam = sum_partials(part(S.partials, kGam + cur), n_prev, sh);
-    const double del = sum_partials(part(S.partials, kDel + cur), n_prev, sh);
     double alpha_d, beta_d;
     if (it == 0) {
         beta_d = 0.0;
@@ -321,6 +353,16 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_iter_kernel(int n, const i
     double gn = 0.0, dn = 0.0, rn = 0.0;
     for (int i = blockIdx.x * (kVecThreads / G) + threadIdx.x / G; i < n; i += rows_per_grid) {
         const int p0 = row_ptr[i], p1 = row_ptr[i + 1];
+        // the row's own record, p and x do not depend on the SpMV: fetch them first
+        // (up to 16 lanes per row; wider groups need the registers for the SpMV)
+        constexpr bool kEarly = G <= 16;
+        Rec<T> o{};
+        T p_old = 0, x_old = 0;
+        if (kEarly && lane == 0) {
+            o = load_rec(ra, i);
+            p_old = v.p[i];
+            x_old = x[i];
+        }
         double acc = 0.0;
 #pragma unroll 2
         for (int q = p0 + lane; q < p1; q += G) {
@@ -330,13 +372,17 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_iter_kernel(int n, const i
 #pragma unroll
         for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
         if (lane == 0) {
-            const Rec<T> o = load_rec(ra, i);
-            const T pi = o.d * o.r + beta * v.p[i];  // u_i + beta p
+            if (!kEarly) {
+                o = load_rec(ra, i);
+                p_old = v.p[i];
+                x_old = x[i];
+            }
+            const T pi = o.d * o.r + beta * p_old;  // u_i + beta p
             const T si = next_s(o, beta);
             const T ri = next_r(o, si, alpha);
             const T ui = o.d * ri;
             const T wi = (T)acc;
-            x[i] += alpha * pi;
+            x[i] = x_old + alpha * pi;
             v.p[i] = pi;
             store_rec(rb, i, ri, wi, si, o.d);
             gn += (double)ri * (double)ui;

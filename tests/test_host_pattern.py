@@ -221,6 +221,21 @@ def test_block_vertex_staging_in_bounds(dim, n, shuffle):
     for b in range(pat.n_blocks):  # ascending and distinct within a block
         seg = vert[vptr[b]:vptr[b + 1]]
         assert np.all(np.diff(seg) > 0)
-    with pytest.raises(tg.TGError):
-        p2 = meshgen.elasticity_inputs(1, seed=0)
-        tg.Pattern(p2["conn"], len(p2["coords"]), dim=3, order=2, ncomp=3, host_only=True).block_vertices()
+
+
+@pytest.mark.parametrize("n", [1, 3])
+def test_block_vertex_staging_p2(n):
+    """P2 blocks stage the 4 vertex nodes of their elements the same way."""
+    d = meshgen.elasticity_inputs(n, seed=0)
+    pat = tg.Pattern(d["conn"], len(d["coords"]), dim=3, order=2, ncomp=3, host_only=True)
+    vptr, vert, lv = pat.block_vertices()
+    r = pat.routing()
+    nodes = pat.element_nodes()
+    assert np.diff(vptr).max() <= 256 and np.all(np.diff(vptr) >= 1)
+    pair_block = np.repeat(np.arange(pat.n_blocks), np.diff(r["inc_ptr"][r["blk_row"]]))
+    e = r["inc"] // 10
+    for a in range(4):
+        loc = (lv >> (8 * a)) & 255
+        assert np.all(loc < np.diff(vptr)[pair_block])
+        np.testing.assert_array_equal(vert[vptr[pair_block] + loc], nodes[e, a])
+        np.testing.assert_array_equal(nodes[e, a], d["conn"][e, a])
