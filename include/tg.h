@@ -25,7 +25,9 @@
  *     that must stay alive until the work enqueued on `stream` has completed;
  *   - `stream` is a hipStream_t (NULL = the default stream); kernels are
  *     enqueued on it and the call returns without waiting unless stated;
- *   - the library allocates device memory only in tg_pattern_create;
+ *   - the library allocates device memory in tg_pattern_create, for the
+ *     pattern's scratch on first use by tg_adjoint_p1 / tg_heat_* (grown on
+ *     demand, freed with the pattern), and for a server's slots;
  *   - all indices are 0-based int32; sizes are int64.
  */
 #ifndef TG_H
@@ -247,8 +249,10 @@ tg_status tg_spmv(const tg_pattern *p, tg_dtype dtype, const void *d_values, con
  * Solve K x = b with Jacobi-preconditioned conjugate gradients, x_0 = 0, and
  * stop when ||r_k||_2 / ||b||_2 <= rtol for the recursive residual r_k (the
  * criterion of Sec. B.1.2; CG replaces the paper's BiCGSTAB because every
- * configured system is symmetric positive definite).  Dot products and norms
- * are accumulated in FP64 in a fixed order (bitwise reproducible).
+ * configured system is symmetric positive definite).  CG runs in the
+ * single-reduction form of Chronopoulos and Gear (one kernel launch per
+ * iteration).  Dot products and norms are accumulated in FP64 in a fixed order
+ * (bitwise reproducible).
  *   d_values, d_rhs : device arrays of dtype (e.g. after tg_apply_dirichlet).
  *   d_x             : device [n_dofs] of dtype, output.
  *   check_every     : iterations between host checks of the stop test (>= 1);

@@ -89,25 +89,5 @@ __device__ __forceinline__ bool numerically_singular(const double (&x)[D + 1][D]
     return (bool)((int)!(det * det > tol * tol * prod) | (int)!finite(det));
 }
 
-template <int D>
-__device__ __forceinline__ void load_vertices(const int32_t *__restrict__ conn, const double *__restrict__ coords,
-                                              int e, double (&x)[D + 1][D]) {
-    unsigned v[D + 1];
-    if constexpr (D == 3) {
-        const int4 q = ldg(reinterpret_cast<const int4 *>(conn), (unsigned)e);
-        v[0] = (unsigned)q.x;
-        v[1] = (unsigned)q.y;
-        v[2] = (unsigned)q.z;
-        v[3] = (unsigned)q.w;
-    } else {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) v[a] = (unsigned)ldg(conn, 3u * (unsigned)e + a);
-    }
-#pragma unroll
-    for (int a = 0; a <= D; ++a)
-#pragma unroll
-        for (int c = 0; c < D; ++c) x[a][c] = ldg(coords, v[a] * D + c);
-}
-
 }  // namespace
 }  // namespace tg
