@@ -112,23 +112,26 @@ __device__ __forceinline__ T segment_sum(const T *__restrict__ src, const uint16
 
 // Dynamic LDS of one row block: local matrices, loads, and the block's share
 // of the routing (segment pointers and slot list, copied in with coalesced
-// loads, so the Reduce touches only LDS).
+// loads, so the Reduce touches only LDS), plus, for the P1 kernel, the
+// block-relative first pair of every row (mr rows, mr + 1 offsets).
 template <typename T>
 struct BlockLds {
     T *K;            // [mp * kk]  local matrix entries (kk = k, or 9 k for 3x3 blocks)
     T *F;            // [mp * nc]  local load entries
     int32_t *seg;    // [me + 1]   segment starts, relative to the block's first slot
     uint16_t *slot;  // [mp * k]   slots of the block, in CSR entry order
-    __device__ BlockLds(unsigned char *base, int mp, int me, int kk, int nc, int k) {
+    int32_t *ip;     // [mr + 1]   pair offsets of the block's rows (mr = 0: none)
+    __device__ BlockLds(unsigned char *base, int mp, int me, int kk, int nc, int k, int mr = 0) {
         K = reinterpret_cast<T *>(base);
         F = K + (size_t)mp * kk;
         seg = reinterpret_cast<int32_t *>(F + (size_t)mp * nc);
         slot = reinterpret_cast<uint16_t *>(seg + ((me + 2) & ~1));
-        (void)k;
+        ip = reinterpret_cast<int32_t *>(slot + (((size_t)mp * k + 1) & ~(size_t)1));
+        (void)mr;
     }
-    __host__ __device__ static size_t bytes(int mp, int me, int kk, int nc, int k) {
+    __host__ __device__ static size_t bytes(int mp, int me, int kk, int nc, int k, int mr = 0) {
         return sizeof(T) * (size_t)mp * (kk + nc) + sizeof(int32_t) * (size_t)((me + 2) & ~1) +
-               sizeof(uint16_t) * (size_t)mp * k;
+               sizeof(uint16_t) * (((size_t)mp * k + 1) & ~(size_t)1) + (mr > 0 ? sizeof(int32_t) * (mr + 1) : 0);
     }
 };
 
@@ -270,60 +273,92 @@ void p1_assemble_kernel(
     const int32_t *__restrict__ seg_ptr, const uint16_t *__restrict__ slot, const int32_t *__restrict__ blk_vert,
     const uint32_t *__restrict__ pair_lv, const double *__restrict__ coords, const T *__restrict__ coef,
     const T *__restrict__ load, T *__restrict__ values, T *__restrict__ rhs, int32_t *__restrict__ status, int nblk,
-    int mp, int me, int nbatch, unsigned n_elem, unsigned nnz, unsigned n_rows) {
+    int mp, int me, int mr, int nbatch, unsigned n_elem, unsigned nnz, unsigned n_rows) {
     constexpr int K = D + 1;
     constexpr int VS = VertLds<D>::VS;
     constexpr bool COEF = FORM != kMass;
+    static_assert(kP1BlockVerts <= kP1Threads, "one staged vertex per thread");
     extern __shared__ __align__(16) unsigned char smem[];
-    BlockLds<T> L(smem, mp, me, K, 1, K);
-    double *Lx = reinterpret_cast<double *>(smem + VertLds<D>::offset(BlockLds<T>::bytes(mp, me, K, 1, K)));
+    BlockLds<T> L(smem, mp, me, K, 1, K, mr);
+    double *Lx = reinterpret_cast<double *>(smem + VertLds<D>::offset(BlockLds<T>::bytes(mp, me, K, 1, K, mr)));
 
     const int blk = xcd_swizzle(blockIdx.x, nblk);
     const int4 dsc = ldg(reinterpret_cast<const int4 *>(blk_desc), 2u * blk);
     const int4 dsv = ldg(reinterpret_cast<const int4 *>(blk_desc), 2u * blk + 1u);
     const int r0 = dsc.x, r1 = dsc.y, q0 = dsc.z, q1 = dsc.w, v0 = dsv.x, v1 = dsv.y, w0 = dsv.z, w1 = dsv.w;
-    const int np = q1 - q0, nent = v1 - v0, nvb = w1 - w0;
+    const int np = q1 - q0, nent = v1 - v0, nvb = w1 - w0, nr = r1 - r0;
     const unsigned s0 = (unsigned)q0 * K;  // the block's slots are slot[s0 .. s0 + np K)
     const int tid = threadIdx.x;
+    const int nmem = BATCHED ? nbatch : 1;
 
-    // ---- the block's vertices -> LDS (each vertex once per block)
-    for (int l = tid; l < nvb; l += kP1Threads)
-        stage_vertex<D>(coords, (unsigned)ldg(blk_vert, (unsigned)(w0 + l)), Lx + l * VS);
+    if (np == 0) {  // rows of nodes that belong to no element: no values, zero loads
+        if (LOAD)
+            for (int m = 0; m < nmem; ++m)
+                for (int r = r0 + tid; r < r1; r += kP1Threads) stg(rhs, (unsigned)m * n_rows + (unsigned)r, (T)0);
+        return;
+    }
 
-    // The block's share of the routing, fetched first (independent of the Map's
-    // load chain) and written to LDS after the Map: one unit of K slots and one
-    // segment pointer per thread, the remainder of a large block afterwards.
+    // ---- Every load that needs only the block descriptor, issued back to back
+    // with clamped (always valid) indices and no branches, so that their
+    // latencies overlap: the vertex this thread stages, its pair's code and
+    // local vertex ids, the pair's K routing slots, one segment pointer and one
+    // row offset.  Then the loads that need one of them: the staged vertex's
+    // coordinates and the pair's coefficients.  Two memory latencies in all.
+    const int tp = min(tid, np - 1);
+    const unsigned vid = (unsigned)ldg(blk_vert, (unsigned)(w0 + min(tid, nvb - 1)));
+    const unsigned code = (unsigned)ldg(inc, (unsigned)(q0 + tp));
+    const uint32_t lv = ldg(pair_lv, (unsigned)(q0 + tp));
+    const int seg_reg = ldg(seg_ptr, (unsigned)(v0 + min(tid, nent)));
+    const int ip_reg = ldg(inc_ptr, (unsigned)(r0 + min(tid, nr)));
+    uint2 slot_w = make_uint2(0u, 0u);
     uint16_t slot_reg[K];
-    int seg_reg = 0;
-    if (tid < np) {
-        if constexpr (K == 4) {  // s0 is a multiple of 4 slots: one 8-byte load
-            const uint2 w = ldg(reinterpret_cast<const uint2 *>(slot), s0 / 4u + tid);
-            slot_reg[0] = (uint16_t)w.x;
-            slot_reg[1] = (uint16_t)(w.x >> 16);
-            slot_reg[2] = (uint16_t)w.y;
-            slot_reg[3] = (uint16_t)(w.y >> 16);
+    if constexpr (K == 4) {  // s0 is a multiple of 4 slots: one 8-byte load
+        slot_w = ldg(reinterpret_cast<const uint2 *>(slot), s0 / 4u + (unsigned)tp);
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) slot_reg[j] = ldg(slot, s0 + (unsigned)(K * tp + j));
+    }
+    double vxyz[D];
+    if constexpr (D == 3) {
+        vxyz[0] = ldg(coords, 3u * vid);
+        vxyz[1] = ldg(coords, 3u * vid + 1u);
+        vxyz[2] = ldg(coords, 3u * vid + 2u);
+    } else {
+        const double2 xy = ldg(reinterpret_cast<const double2 *>(coords), vid);
+        vxyz[0] = xy.x;
+        vxyz[1] = xy.y;
+    }
+    const unsigned e = code / K;
+    const int a = (int)(code - e * K);
+    T c_next = COEF ? ldg(coef, e) : (T)1;  // member 0's coefficients (then each next member's)
+    T f_next = LOAD ? ldg(load, e) : (T)0;
+
+    // ---- staged vertex and routing -> LDS
+    const bool own = tid < np;
+    if (tid < nvb) {
+        double *lx = Lx + tid * VS;
+        *reinterpret_cast<double2 *>(lx) = make_double2(vxyz[0], vxyz[1]);
+        if constexpr (D == 3) lx[2] = vxyz[2];
+    }
+    if (own) {
+        if constexpr (K == 4) {
+            *reinterpret_cast<uint2 *>(L.slot + 4 * tid) = slot_w;
         } else {
 #pragma unroll
-            for (int j = 0; j < K; ++j) slot_reg[j] = ldg(slot, s0 + (unsigned)(K * tid + j));
+            for (int j = 0; j < K; ++j) L.slot[K * tid + j] = slot_reg[j];
         }
     }
-    if (tid <= nent) seg_reg = ldg(seg_ptr, (unsigned)(v0 + tid));
+    if (tid <= nent) L.seg[tid] = seg_reg - (int)s0;
+    if (tid <= nr) L.ip[tid] = ip_reg - q0;
+    // remainders of large blocks (a single row with more pairs, entries or rows than threads)
+    for (int u = K * (tid + kP1Threads); u < np * K; u += K * kP1Threads)
+#pragma unroll
+        for (int j = 0; j < K; ++j) L.slot[u + j] = ldg(slot, s0 + (unsigned)(u + j));
+    for (int u = tid + kP1Threads; u <= nent; u += kP1Threads) L.seg[u] = ldg(seg_ptr, (unsigned)(v0 + u)) - (int)s0;
+    for (int u = tid + kP1Threads; u <= nr; u += kP1Threads) L.ip[u] = ldg(inc_ptr, (unsigned)(r0 + u)) - q0;
+    __syncthreads();  // vertices and routing are in LDS
 
     // ---- Map geometry of this thread's pair (kept for the whole batch)
-    const bool own = tid < np;
-    unsigned e = 0;
-    int a = 0;
-    uint32_t lv = 0;
-    double c_next = 1.0, f_next = 0.0;  // coefficients of the next member, fetched ahead
-    if (own) {
-        const unsigned code = (unsigned)ldg(inc, (unsigned)(q0 + tid));
-        lv = ldg(pair_lv, (unsigned)(q0 + tid));
-        e = code / K;
-        a = (int)(code - e * K);
-        if (BATCHED && COEF) c_next = (double)ldg(coef, e);
-        if (BATCHED && LOAD) f_next = (double)ldg(load, e);
-    }
-    __syncthreads();  // the vertex copy is complete
     P1Geom<D> g;
     g.adet = 1.0;
     g.bad = false;
@@ -333,17 +368,12 @@ void p1_assemble_kernel(
         p1_geometry<D>(x, g);
     }
 
-    const int nmem = BATCHED ? nbatch : 1;
     for (int m = 0; m < nmem; ++m) {
         const unsigned eo = (unsigned)m * n_elem;
-        double c = c_next, f = f_next;
-        if (!BATCHED && own) {
-            if (COEF) c = (double)ldg(coef, e);
-            if (LOAD) f = (double)ldg(load, e);
-        }
-        if (BATCHED && own && m + 1 < nmem) {  // the next member's coefficients, fetched ahead
-            if (COEF) c_next = (double)ldg(coef, eo + n_elem + e);
-            if (LOAD) f_next = (double)ldg(load, eo + n_elem + e);
+        const double c = (double)c_next, f = (double)f_next;
+        if (BATCHED && m + 1 < nmem) {  // the next member's coefficients, fetched ahead
+            if (COEF) c_next = ldg(coef, eo + n_elem + e);
+            if (LOAD) f_next = ldg(load, eo + n_elem + e);
         }
         // ---- Map: row a of the local matrix (and F_e[a]) for member m
         if (own) {
@@ -356,39 +386,20 @@ void p1_assemble_kernel(
             if (bad && status) atomicMin(status, (int)e);
         }
         for (int t = tid + kP1Threads; t < np; t += kP1Threads) {  // a single row with more pairs than threads
-            const unsigned code = (unsigned)ldg(inc, (unsigned)(q0 + t));
-            const unsigned ee = code / K;
+            const unsigned code_t = (unsigned)ldg(inc, (unsigned)(q0 + t));
+            const unsigned ee = code_t / K;
             double x[K][D];
             lds_vertices<D>(Lx, ldg(pair_lv, (unsigned)(q0 + t)), x);
             P1Geom<D> gg;
             p1_geometry<D>(x, gg);
-            const double c = COEF ? (double)ldg(coef, eo + ee) : 1.0;
-            const double f = LOAD ? (double)ldg(load, eo + ee) : 0.0;
+            const double ct = COEF ? (double)ldg(coef, eo + ee) : 1.0;
+            const double ft = LOAD ? (double)ldg(load, eo + ee) : 0.0;
             T row[K], fa;
-            p1_row<D, T, FORM>(gg, (int)(code - ee * K), c, f, row, fa);
+            p1_row<D, T, FORM>(gg, (int)(code_t - ee * K), ct, ft, row, fa);
 #pragma unroll
             for (int b = 0; b < K; ++b) L.K[b * np + t] = row[b];
             L.F[t] = fa;
-            if (((int)gg.bad | (int)!finite(c) | (int)!finite(f)) && status) atomicMin(status, (int)ee);
-        }
-        if (m == 0) {
-            // ---- routing -> LDS (registers first, then any remainder of a large block)
-            if (own) {
-                if constexpr (K == 4) {
-                    *reinterpret_cast<uint2 *>(L.slot + 4 * tid) =
-                        make_uint2((uint32_t)slot_reg[0] | ((uint32_t)slot_reg[1] << 16),
-                                   (uint32_t)slot_reg[2] | ((uint32_t)slot_reg[3] << 16));
-                } else {
-#pragma unroll
-                    for (int j = 0; j < K; ++j) L.slot[K * tid + j] = slot_reg[j];
-                }
-            }
-            for (int u = K * (tid + kP1Threads); u < np * K; u += K * kP1Threads)
-#pragma unroll
-                for (int j = 0; j < K; ++j) L.slot[u + j] = ldg(slot, s0 + (unsigned)(u + j));
-            if (tid <= nent) L.seg[tid] = seg_reg - (int)s0;
-            for (int u = tid + kP1Threads; u <= nent; u += kP1Threads)
-                L.seg[u] = ldg(seg_ptr, (unsigned)(v0 + u)) - (int)s0;
+            if (((int)gg.bad | (int)!finite(ct) | (int)!finite(ft)) && status) atomicMin(status, (int)ee);
         }
         __syncthreads();
 
@@ -399,11 +410,11 @@ void p1_assemble_kernel(
         // ---- Reduce: right-hand side (S_vec projection)
         if (LOAD) {
             const unsigned ro = (unsigned)m * n_rows;
-            for (int r = r0 + tid; r < r1; r += kP1Threads) {
-                const int u0 = ldg(inc_ptr, (unsigned)r) - q0, u1 = ldg(inc_ptr, (unsigned)r + 1u) - q0;
+            for (int r = tid; r < nr; r += kP1Threads) {
+                const int u0 = L.ip[r], u1 = L.ip[r + 1];
                 T acc = 0;
                 for (int u = u0; u < u1; ++u) acc += L.F[u];
-                stg(rhs, ro + (unsigned)r, acc);
+                stg(rhs, ro + (unsigned)(r0 + r), acc);
             }
         }
         if (m + 1 < nmem) __syncthreads();  // LDS is rewritten by the next member
@@ -601,18 +612,18 @@ static hipError_t launch_p1_t(const tg_pattern &p, int nbatch, const double *coo
     const DevicePattern &d = p.dev;
     const HostPattern &h = p.host;
     const int nblk = (int)h.n_blocks();
-    const int mp = h.max_block_pairs, me = h.max_block_entries;
-    const size_t lds = VertLds<D>::offset(BlockLds<T>::bytes(mp, me, D + 1, 1, D + 1)) +
+    const int mp = h.max_block_pairs, me = h.max_block_entries, mr = h.max_block_rows;
+    const size_t lds = VertLds<D>::offset(BlockLds<T>::bytes(mp, me, D + 1, 1, D + 1, mr)) +
                        VertLds<D>::bytes(h.max_block_verts);
     if (nbatch == 1)
         hipLaunchKernelGGL((p1_assemble_kernel<D, T, FORM, LOAD, false>), dim3(nblk), dim3(kP1Threads), lds, s,
                            d.blk_desc, d.inc_ptr, d.inc, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, coords,
-                           (const T *)coef, (const T *)load, (T *)values, (T *)rhs, status, nblk, mp, me, 1,
+                           (const T *)coef, (const T *)load, (T *)values, (T *)rhs, status, nblk, mp, me, mr, 1,
                            (unsigned)h.E, (unsigned)h.nnz, (unsigned)h.n_dofs);
     else
         hipLaunchKernelGGL((p1_assemble_kernel<D, T, FORM, LOAD, true>), dim3(nblk), dim3(kP1Threads), lds, s,
                            d.blk_desc, d.inc_ptr, d.inc, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, coords,
-                           (const T *)coef, (const T *)load, (T *)values, (T *)rhs, status, nblk, mp, me, nbatch,
+                           (const T *)coef, (const T *)load, (T *)values, (T *)rhs, status, nblk, mp, me, mr, nbatch,
                            (unsigned)h.E, (unsigned)h.nnz, (unsigned)h.n_dofs);
     return hipGetLastError();
 }

@@ -64,6 +64,7 @@ struct HostPattern {
     int32_t max_block_pairs = 0;
     int32_t max_block_entries = 0;  // node-level CSR entries
     int32_t max_block_verts = 0;    // distinct vertices
+    int32_t max_block_rows = 0;
 
     int64_t n_pairs() const { return (int64_t)inc.size(); }
     int64_t n_blocks() const { return (int64_t)blk_row.size() - 1; }

@@ -272,7 +272,7 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
     }
     hp.seg_ptr.push_back((int32_t)slot_fill);
     hp.nnz_nodes = (int64_t)hp.node_ci.size();
-    hp.max_block_pairs = hp.max_block_entries = 0;
+    hp.max_block_pairs = hp.max_block_entries = hp.max_block_rows = 0;
     hp.blk_desc.assign((hp.blk_row.size() - 1) * 8, 0);
     for (int64_t b = 0; b + 1 < (int64_t)hp.blk_row.size(); ++b) {
         const int32_t r0 = hp.blk_row[b], r1 = hp.blk_row[b + 1];
@@ -285,6 +285,7 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
         dsc[5] = hp.node_rp[r1];
         hp.max_block_pairs = std::max(hp.max_block_pairs, hp.inc_ptr[r1] - hp.inc_ptr[r0]);
         hp.max_block_entries = std::max(hp.max_block_entries, hp.node_rp[r1] - hp.node_rp[r0]);
+        hp.max_block_rows = std::max(hp.max_block_rows, r1 - r0);
     }
     // ---- block vertex lists and the per-pair block-local ids of the element's
     // vertices (its first dim + 1 nodes; P2 blocks hold at most 64 pairs, so
