@@ -333,23 +333,24 @@ void p1_assemble_kernel(
     T c_next = COEF ? ldg(coef, e) : (T)1;  // member 0's coefficients (then each next member's)
     T f_next = LOAD ? ldg(load, e) : (T)0;
 
-    // ---- staged vertex and routing -> LDS
+    // ---- staged vertex and routing -> LDS, also without branches: a thread past
+    // the end of a list writes the last element's value to the last element's
+    // place, the same value its owner writes there.  (A branch here lets the
+    // compiler sink the loads into it, behind a wait for every earlier load.)
     const bool own = tid < np;
-    if (tid < nvb) {
-        double *lx = Lx + tid * VS;
+    {
+        double *lx = Lx + min(tid, nvb - 1) * VS;
         *reinterpret_cast<double2 *>(lx) = make_double2(vxyz[0], vxyz[1]);
         if constexpr (D == 3) lx[2] = vxyz[2];
     }
-    if (own) {
-        if constexpr (K == 4) {
-            *reinterpret_cast<uint2 *>(L.slot + 4 * tid) = slot_w;
-        } else {
+    if constexpr (K == 4) {
+        *reinterpret_cast<uint2 *>(L.slot + 4 * tp) = slot_w;
+    } else {
 #pragma unroll
-            for (int j = 0; j < K; ++j) L.slot[K * tid + j] = slot_reg[j];
-        }
+        for (int j = 0; j < K; ++j) L.slot[K * tp + j] = slot_reg[j];
     }
-    if (tid <= nent) L.seg[tid] = seg_reg - (int)s0;
-    if (tid <= nr) L.ip[tid] = ip_reg - q0;
+    L.seg[min(tid, nent)] = seg_reg - (int)s0;
+    L.ip[min(tid, nr)] = ip_reg - q0;
     // remainders of large blocks (a single row with more pairs, entries or rows than threads)
     for (int u = K * (tid + kP1Threads); u < np * K; u += K * kP1Threads)
 #pragma unroll
