@@ -94,6 +94,7 @@ typedef struct {
     const int32_t *d_row_ptr;  /* device [n_dofs + 1], NULL if host-only     */
     const int32_t *d_col_idx;  /* device [nnz], NULL if host-only             */
     size_t device_bytes;       /* device memory owned by the pattern          */
+    int64_t n_slot;            /* length of the routing slot list             */
 } tg_pattern_info;
 
 /* Text of the last error on the calling thread; valid until its next tg_ call. */
@@ -154,12 +155,15 @@ tg_status tg_pattern_copy_element_nodes(const tg_pattern *p, int32_t *h_nodes);
  *       [h_blk_row[b], h_blk_row[b+1]).
  *   h_node_rp [N+1] : node-level CSR row pointers (node columns are the scalar
  *       CSR columns of component 0 divided by ncomp).
- *   h_seg_ptr [Z+1], h_slot [P*k] : S_mat as segments: node-level entry z sums
- *       the local-matrix slots h_slot[h_seg_ptr[z] .. h_seg_ptr[z+1]) in
+ *   h_seg_ptr [Z+1], h_slot [n_slot] : S_mat as segments: node-level entry z
+ *       sums the local-matrix slots h_slot[h_seg_ptr[z] .. h_seg_ptr[z+1]) in
  *       ascending element order; a slot is b * n + (pair - f), where f is the
  *       first pair and n the number of pairs of the entry's row block: local
  *       entry (a, b) of the pair's element.  For ncomp = 3 each slot is a 3x3
- *       block.
+ *       block.  For P1 the diagonal entry (i, i) has an empty segment: its
+ *       value is the sum of K_e[a][a] over the pairs (i, e, a) of node i, in
+ *       their S_vec (ascending element) order.  n_slot (tg_pattern_info) is
+ *       h_seg_ptr[Z] rounded up to a multiple of 4; the tail is unused.
  */
 /*
  * The coordinate staging of the fused kernels.  Row block b reads the

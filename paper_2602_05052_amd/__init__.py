@@ -49,7 +49,8 @@ class _Info(ctypes.Structure):
                 ("n_vertices", ctypes.c_int64), ("n_elements", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
                 ("n_dofs", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n_constrained", ctypes.c_int64),
                 ("n_blocks", ctypes.c_int64),
-                ("d_row_ptr", ctypes.c_void_p), ("d_col_idx", ctypes.c_void_p), ("device_bytes", ctypes.c_size_t)]
+                ("d_row_ptr", ctypes.c_void_p), ("d_col_idx", ctypes.c_void_p), ("device_bytes", ctypes.c_size_t),
+                ("n_slot", ctypes.c_int64)]
 
 
 class ServerResult(ctypes.Structure):
@@ -215,6 +216,7 @@ class Pattern:
         self.n_nodes, self.n_dofs, self.nnz = info.n_nodes, info.n_dofs, info.nnz
         self.n_constrained, self.n_blocks = info.n_constrained, info.n_blocks
         self.device_bytes = info.device_bytes
+        self.n_slot = info.n_slot
         self.host_only = host_only
 
     def __del__(self, _destroy=_lib.tg_pattern_destroy, _finalizing=sys.is_finalizing):
@@ -250,7 +252,7 @@ class Pattern:
         Z = self.nnz // (self.ncomp * self.ncomp)
         out = dict(inc_ptr=np.zeros(N + 1, np.int32), inc=np.zeros(P, np.int32),
                    blk_row=np.zeros(self.n_blocks + 1, np.int32), node_rp=np.zeros(N + 1, np.int32),
-                   seg_ptr=np.zeros(Z + 1, np.int32), slot=np.zeros(P * self.k, np.uint16))
+                   seg_ptr=np.zeros(Z + 1, np.int32), slot=np.zeros(max(1, self.n_slot), np.uint16))
         _check(_lib.tg_pattern_copy_routing(
             self._h, *(out[k].ctypes.data_as(_i32p) for k in ("inc_ptr", "inc", "blk_row", "node_rp", "seg_ptr")),
             out["slot"].ctypes.data_as(ctypes.POINTER(ctypes.c_uint16))))

@@ -182,6 +182,7 @@ tg_status tg_pattern_query(const tg_pattern *p, tg_pattern_info *info) {
     info->d_row_ptr = p->dev.row_ptr;
     info->d_col_idx = p->dev.col_idx;
     info->device_bytes = p->dev.bytes;
+    info->n_slot = (int64_t)h.slot.size();
     return ok();
 }
 
@@ -227,7 +228,7 @@ tg_status tg_pattern_copy_block_vertices(const tg_pattern *p, int64_t *n_vert, i
     if (n_vert) *n_vert = (int64_t)h.blk_vert.size();
     if (h_blk_vptr) {
         const int64_t nb = h.n_blocks();
-        for (int64_t b = 0; b < nb; ++b) h_blk_vptr[b] = h.blk_desc[b * 8 + 6];
+        for (int64_t b = 0; b < nb; ++b) h_blk_vptr[b] = h.blk_desc[b * tg::kBlkDesc + 6];
         h_blk_vptr[nb] = (int32_t)h.blk_vert.size();
     }
     if (h_blk_vert) std::memcpy(h_blk_vert, h.blk_vert.data(), sizeof(int32_t) * h.blk_vert.size());

@@ -110,28 +110,24 @@ __device__ __forceinline__ T segment_sum(const T *__restrict__ src, const uint16
     return acc;
 }
 
-// Dynamic LDS of one row block: local matrices, loads, and the block's share
-// of the routing (segment pointers and slot list, copied in with coalesced
-// loads, so the Reduce touches only LDS), plus, for the P1 kernel, the
-// block-relative first pair of every row (mr rows, mr + 1 offsets).
+// Dynamic LDS of one P2 row block: local matrices, loads, and the block's
+// share of the routing (segment pointers and slot list, copied in with
+// coalesced loads, so the Reduce touches only LDS).
 template <typename T>
 struct BlockLds {
-    T *K;            // [mp * kk]  local matrix entries (kk = k, or 9 k for 3x3 blocks)
+    T *K;            // [mp * kk]  local matrix entries (kk = 9 k: 3x3 blocks)
     T *F;            // [mp * nc]  local load entries
     int32_t *seg;    // [me + 1]   segment starts, relative to the block's first slot
     uint16_t *slot;  // [mp * k]   slots of the block, in CSR entry order
-    int32_t *ip;     // [mr + 1]   pair offsets of the block's rows (mr = 0: none)
-    __device__ BlockLds(unsigned char *base, int mp, int me, int kk, int nc, int k, int mr = 0) {
+    __device__ BlockLds(unsigned char *base, int mp, int me, int kk, int nc) {
         K = reinterpret_cast<T *>(base);
         F = K + (size_t)mp * kk;
         seg = reinterpret_cast<int32_t *>(F + (size_t)mp * nc);
         slot = reinterpret_cast<uint16_t *>(seg + ((me + 2) & ~1));
-        ip = reinterpret_cast<int32_t *>(slot + (((size_t)mp * k + 1) & ~(size_t)1));
-        (void)mr;
     }
-    __host__ __device__ static size_t bytes(int mp, int me, int kk, int nc, int k, int mr = 0) {
+    __host__ __device__ static size_t bytes(int mp, int me, int kk, int nc, int k) {
         return sizeof(T) * (size_t)mp * (kk + nc) + sizeof(int32_t) * (size_t)((me + 2) & ~1) +
-               sizeof(uint16_t) * (((size_t)mp * k + 1) & ~(size_t)1) + (mr > 0 ? sizeof(int32_t) * (mr + 1) : 0);
+               sizeof(uint16_t) * (size_t)mp * k;
     }
 };
 
@@ -139,13 +135,13 @@ struct BlockLds {
 // by 1 and sums with zeros), branch-free, and with no run-time index into the
 // table (a select of two table entries can be folded into a load through a
 // selected address, which sends the table to scratch memory).
-template <int D>
-__device__ __forceinline__ void select_row(const double (&C)[D + 1][D], int a, double (&out)[D]) {
+template <int D, typename T>
+__device__ __forceinline__ void select_row(const T (&C)[D + 1][D], int a, T (&out)[D]) {
 #pragma unroll
-    for (int c = 0; c < D; ++c) out[c] = 0.0;
+    for (int c = 0; c < D; ++c) out[c] = (T)0;
 #pragma unroll
     for (int k = 0; k <= D; ++k) {
-        const double m = (a == k) ? 1.0 : 0.0;
+        const T m = (a == k) ? (T)1 : (T)0;
 #pragma unroll
         for (int c = 0; c < D; ++c) out[c] += m * C[k][c];
     }
@@ -184,16 +180,20 @@ __device__ __forceinline__ void p1_row(const P1Geom<D> &g, int a, double c, doub
     for (int b = 0; b < K; ++b) kr[b] = (T)0;
     if constexpr (FORM != kMass) {
         const T sc = (T)(c / (g.adet * (1.0 / RefSimplex<D>::vol)));
-        double cad[D];
-        select_row<D>(g.C, a, cad);
-        T ca[D];
+        // the cofactors rounded to T first (selecting a row is exact, so this
+        // equals rounding the selected row)
+        T Ct[K][D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) ca[k] = (T)cad[k];
+        for (int b = 0; b < K; ++b)
+#pragma unroll
+            for (int k = 0; k < D; ++k) Ct[b][k] = (T)g.C[b][k];
+        T ca[D];
+        select_row<D, T>(Ct, a, ca);
 #pragma unroll
         for (int b = 0; b < K; ++b) {
             T sum = 0;
 #pragma unroll
-            for (int k = 0; k < D; ++k) sum += ca[k] * (T)g.C[b][k];
+            for (int k = 0; k < D; ++k) sum += ca[k] * Ct[b][k];
             kr[b] = sc * sum;
         }
     }
@@ -217,13 +217,8 @@ __device__ __forceinline__ void p1_row(const P1Geom<D> &g, int a, double c, doub
     fa = (T)(f * g.adet * (RefSimplex<D>::vol / K));  // phi_a(centroid) = 1/(d+1)
 }
 
-// Fused Map + Reduce over a batch of coefficient sets (nbatch >= 1; a plain
-// call is nbatch = 1).  Member m reads coef[m E + e] and load[m E + e] and
-// writes values[m nnz + p] and rhs[m N + i]; the geometry and the routing are
-// read once for the whole batch.  Every member runs exactly the arithmetic
-// of a single call, so it is bitwise equal to assembling it alone.
 // Per-block LDS copy of the vertex coordinates: VS doubles per vertex (16-byte
-// records), placed after the BlockLds arrays.
+// records), placed after the other per-block arrays.
 template <int D>
 struct VertLds {
     static constexpr int VS = D == 3 ? 4 : 2;
@@ -257,38 +252,87 @@ __device__ __forceinline__ void lds_vertices(const double *lx, uint32_t lv, doub
     }
 }
 
+template <typename T> struct Pair2;
+template <> struct Pair2<double> { using type = double2; };
+template <> struct Pair2<float> { using type = float2; };
+
+// Dynamic LDS of one P1 row block (mp pairs, me node entries, mr rows at most):
+//   K    [mp * k]  row a of every pair's local matrix, column-major (b * np + t)
+//   DF   [mp]      every pair's diagonal entry K_e[a][a] and load entry F_e[a]
+//   seg  [me + 1]  segment starts of the block's entries, relative to sb
+//   slot [mp (k-1) + 8]  the block's routing slots from sb = s0 rounded down to 4
+//   ip   [mr + 1]  first pair of every row of the block
+template <typename T>
+struct P1Lds {
+    using T2 = typename Pair2<T>::type;
+    T *K;
+    T2 *DF;
+    int32_t *seg;
+    uint16_t *slot;
+    int32_t *ip;
+    __host__ __device__ static size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
+    __host__ __device__ static size_t off_df(int mp, int k) { return a16(sizeof(T) * (size_t)mp * k); }
+    __host__ __device__ static size_t off_seg(int mp, int k) { return a16(off_df(mp, k) + sizeof(T2) * (size_t)mp); }
+    __host__ __device__ static size_t off_slot(int mp, int me, int k) {
+        return a16(off_seg(mp, k) + sizeof(int32_t) * (size_t)(me + 1));
+    }
+    __host__ __device__ static size_t off_ip(int mp, int me, int k) {
+        return a16(off_slot(mp, me, k) + sizeof(uint16_t) * ((size_t)mp * (k - 1) + 8));
+    }
+    __host__ __device__ static size_t bytes(int mp, int me, int mr, int k) {
+        return a16(off_ip(mp, me, k) + sizeof(int32_t) * (size_t)(mr + 1));
+    }
+    __device__ P1Lds(unsigned char *base, int mp, int me, int k) {
+        K = reinterpret_cast<T *>(base);
+        DF = reinterpret_cast<T2 *>(base + off_df(mp, k));
+        seg = reinterpret_cast<int32_t *>(base + off_seg(mp, k));
+        slot = reinterpret_cast<uint16_t *>(base + off_slot(mp, me, k));
+        ip = reinterpret_cast<int32_t *>(base + off_ip(mp, me, k));
+    }
+};
+
 // Minimum waves per SIMD the register allocation must allow: 8 for the
 // single-set Laplace kernels (they fit in 64 VGPRs without spilling), 7 for the
-// mass forms, 5 for the batched kernels (they keep the pair's geometry live
-// across the member loop).
+// mass forms, 5 (Laplace) or 4 (mass forms) for the batched kernels (they keep
+// the pair's geometry live across the member loop).
 template <typename T, int FORM, bool BATCHED>
 constexpr int p1_waves_per_eu() {
-    return BATCHED ? 5 : (FORM == 0 ? 8 : 7);
+    return BATCHED ? (FORM == 0 ? 5 : 4) : (FORM == 0 ? 8 : 7);
 }
 
+// Fused Map + Reduce over a batch of coefficient sets (nbatch >= 1; a plain
+// call is nbatch = 1).  Member m reads coef[m E + e] and load[m E + e] and
+// writes values[m nnz + p] and rhs[m N + i]; the geometry and the routing are
+// read once for the whole batch.  Every member runs exactly the arithmetic
+// of a single call, so it is bitwise equal to assembling it alone.
 template <int D, typename T, int FORM, bool LOAD, bool BATCHED>
 __global__ __launch_bounds__(kP1Threads) __attribute__((amdgpu_waves_per_eu(p1_waves_per_eu<T, FORM, BATCHED>())))
 void p1_assemble_kernel(
     const int32_t *__restrict__ blk_desc, const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc,
     const int32_t *__restrict__ seg_ptr, const uint16_t *__restrict__ slot, const int32_t *__restrict__ blk_vert,
-    const uint32_t *__restrict__ pair_lv, const double *__restrict__ coords, const T *__restrict__ coef,
-    const T *__restrict__ load, T *__restrict__ values, T *__restrict__ rhs, int32_t *__restrict__ status, int nblk,
-    int mp, int me, int mr, int nbatch, unsigned n_elem, unsigned nnz, unsigned n_rows) {
+    const uint32_t *__restrict__ pair_lv, const int32_t *__restrict__ diag_pos, const double *__restrict__ coords,
+    const T *__restrict__ coef, const T *__restrict__ load, T *__restrict__ values, T *__restrict__ rhs,
+    int32_t *__restrict__ status, int nblk, int mp, int me, int nbatch, unsigned n_elem, unsigned nnz,
+    unsigned n_rows, unsigned lds_verts) {
     constexpr int K = D + 1;
     constexpr int VS = VertLds<D>::VS;
     constexpr bool COEF = FORM != kMass;
+    using T2 = typename P1Lds<T>::T2;
     static_assert(kP1BlockVerts <= kP1Threads, "one staged vertex per thread");
     extern __shared__ __align__(16) unsigned char smem[];
-    BlockLds<T> L(smem, mp, me, K, 1, K, mr);
-    double *Lx = reinterpret_cast<double *>(smem + VertLds<D>::offset(BlockLds<T>::bytes(mp, me, K, 1, K, mr)));
+    P1Lds<T> L(smem, mp, me, K);
+    double *Lx = reinterpret_cast<double *>(smem + lds_verts);
 
     const int blk = xcd_swizzle(blockIdx.x, nblk);
-    const int4 dsc = ldg(reinterpret_cast<const int4 *>(blk_desc), 2u * blk);
-    const int4 dsv = ldg(reinterpret_cast<const int4 *>(blk_desc), 2u * blk + 1u);
+    const int4 dsc = ldg(reinterpret_cast<const int4 *>(blk_desc), 3u * blk);
+    const int4 dsv = ldg(reinterpret_cast<const int4 *>(blk_desc), 3u * blk + 1u);
+    const int2 dss = ldg(reinterpret_cast<const int2 *>(blk_desc), 6u * blk + 4u);
     const int r0 = dsc.x, r1 = dsc.y, q0 = dsc.z, q1 = dsc.w, v0 = dsv.x, v1 = dsv.y, w0 = dsv.z, w1 = dsv.w;
     const int np = q1 - q0, nent = v1 - v0, nvb = w1 - w0, nr = r1 - r0;
-    const unsigned s0 = (unsigned)q0 * K;  // the block's slots are slot[s0 .. s0 + np K)
+    const int sb = dss.x & ~3;               // the block's slots are slot[dss.x .. dss.y); copied from sb
+    const int nu = (dss.y - sb + 3) >> 2;    // 4-slot units to copy
     const int tid = threadIdx.x;
+    const int rr = kP1Threads - 1 - tid;     // the row this thread sums (the Reduce's last threads)
     const int nmem = BATCHED ? nbatch : 1;
 
     if (np == 0) {  // rows of nodes that belong to no element: no values, zero loads
@@ -301,23 +345,18 @@ void p1_assemble_kernel(
     // ---- Every load that needs only the block descriptor, issued back to back
     // with clamped (always valid) indices and no branches, so that their
     // latencies overlap: the vertex this thread stages, its pair's code and
-    // local vertex ids, the pair's K routing slots, one segment pointer and one
-    // row offset.  Then the loads that need one of them: the staged vertex's
-    // coordinates and the pair's coefficients.  Two memory latencies in all.
+    // local vertex ids, a 4-slot unit of the routing, one segment pointer, one
+    // row offset and one row's diagonal position.  Then the loads that need one
+    // of them: the staged vertex's coordinates and the pair's coefficients.
+    // Two memory latencies in all.
     const int tp = min(tid, np - 1);
     const unsigned vid = (unsigned)ldg(blk_vert, (unsigned)(w0 + min(tid, nvb - 1)));
     const unsigned code = (unsigned)ldg(inc, (unsigned)(q0 + tp));
     const uint32_t lv = ldg(pair_lv, (unsigned)(q0 + tp));
     const int seg_reg = ldg(seg_ptr, (unsigned)(v0 + min(tid, nent)));
     const int ip_reg = ldg(inc_ptr, (unsigned)(r0 + min(tid, nr)));
-    uint2 slot_w = make_uint2(0u, 0u);
-    uint16_t slot_reg[K];
-    if constexpr (K == 4) {  // s0 is a multiple of 4 slots: one 8-byte load
-        slot_w = ldg(reinterpret_cast<const uint2 *>(slot), s0 / 4u + (unsigned)tp);
-    } else {
-#pragma unroll
-        for (int j = 0; j < K; ++j) slot_reg[j] = ldg(slot, s0 + (unsigned)(K * tp + j));
-    }
+    const int dp_reg = ldg(diag_pos, (unsigned)(r0 + min(rr, nr - 1)));
+    const uint2 slot_w = ldg(reinterpret_cast<const uint2 *>(slot), (unsigned)(sb >> 2) + (unsigned)min(tid, nu - 1));
     double vxyz[D];
     if constexpr (D == 3) {
         vxyz[0] = ldg(coords, 3u * vid);
@@ -343,19 +382,13 @@ void p1_assemble_kernel(
         *reinterpret_cast<double2 *>(lx) = make_double2(vxyz[0], vxyz[1]);
         if constexpr (D == 3) lx[2] = vxyz[2];
     }
-    if constexpr (K == 4) {
-        *reinterpret_cast<uint2 *>(L.slot + 4 * tp) = slot_w;
-    } else {
-#pragma unroll
-        for (int j = 0; j < K; ++j) L.slot[K * tp + j] = slot_reg[j];
-    }
-    L.seg[min(tid, nent)] = seg_reg - (int)s0;
+    *reinterpret_cast<uint2 *>(L.slot + 4 * min(tid, nu - 1)) = slot_w;
+    L.seg[min(tid, nent)] = seg_reg - sb;
     L.ip[min(tid, nr)] = ip_reg - q0;
     // remainders of large blocks (a single row with more pairs, entries or rows than threads)
-    for (int u = K * (tid + kP1Threads); u < np * K; u += K * kP1Threads)
-#pragma unroll
-        for (int j = 0; j < K; ++j) L.slot[u + j] = ldg(slot, s0 + (unsigned)(u + j));
-    for (int u = tid + kP1Threads; u <= nent; u += kP1Threads) L.seg[u] = ldg(seg_ptr, (unsigned)(v0 + u)) - (int)s0;
+    for (int u = tid + kP1Threads; u < nu; u += kP1Threads)
+        *reinterpret_cast<uint2 *>(L.slot + 4 * u) = ldg(reinterpret_cast<const uint2 *>(slot), (unsigned)((sb >> 2) + u));
+    for (int u = tid + kP1Threads; u <= nent; u += kP1Threads) L.seg[u] = ldg(seg_ptr, (unsigned)(v0 + u)) - sb;
     for (int u = tid + kP1Threads; u <= nr; u += kP1Threads) L.ip[u] = ldg(inc_ptr, (unsigned)(r0 + u)) - q0;
     __syncthreads();  // vertices and routing are in LDS
 
@@ -380,15 +413,19 @@ void p1_assemble_kernel(
         if (own) {
             T row[K], fa;
             p1_row<D, T, FORM>(g, a, c, f, row, fa);
+            T kd = row[0];
+#pragma unroll
+            for (int b = 1; b < K; ++b) kd = (a == b) ? row[b] : kd;
 #pragma unroll
             for (int b = 0; b < K; ++b) L.K[b * np + tid] = row[b];
-            L.F[tid] = fa;
+            L.DF[tid] = T2{kd, fa};
             const bool bad = (bool)((int)g.bad | (int)!finite(c) | (int)!finite(f));
             if (bad && status) atomicMin(status, (int)e);
         }
         for (int t = tid + kP1Threads; t < np; t += kP1Threads) {  // a single row with more pairs than threads
             const unsigned code_t = (unsigned)ldg(inc, (unsigned)(q0 + t));
             const unsigned ee = code_t / K;
+            const int at = (int)(code_t - ee * K);
             double x[K][D];
             lds_vertices<D>(Lx, ldg(pair_lv, (unsigned)(q0 + t)), x);
             P1Geom<D> gg;
@@ -396,27 +433,51 @@ void p1_assemble_kernel(
             const double ct = COEF ? (double)ldg(coef, eo + ee) : 1.0;
             const double ft = LOAD ? (double)ldg(load, eo + ee) : 0.0;
             T row[K], fa;
-            p1_row<D, T, FORM>(gg, (int)(code_t - ee * K), ct, ft, row, fa);
+            p1_row<D, T, FORM>(gg, at, ct, ft, row, fa);
+            T kd = row[0];
+#pragma unroll
+            for (int b = 1; b < K; ++b) kd = (at == b) ? row[b] : kd;
 #pragma unroll
             for (int b = 0; b < K; ++b) L.K[b * np + t] = row[b];
-            L.F[t] = fa;
+            L.DF[t] = T2{kd, fa};
             if (((int)gg.bad | (int)!finite(ct) | (int)!finite(ft)) && status) atomicMin(status, (int)ee);
         }
         __syncthreads();
 
-        // ---- Reduce: CSR values of the block rows (S_mat projection), LDS only
+        // ---- Reduce: off-diagonal CSR values of the block rows (S_mat
+        // projection), LDS only; a row's diagonal entry has no slots.
         const unsigned vo = (unsigned)m * nnz;
-        for (int p = tid; p < nent; p += kP1Threads)
-            stg(values, vo + (unsigned)(v0 + p), segment_sum<T>(L.K, L.slot, L.seg[p], L.seg[p + 1]));
-        // ---- Reduce: right-hand side (S_vec projection)
-        if (LOAD) {
-            const unsigned ro = (unsigned)m * n_rows;
-            for (int r = tid; r < nr; r += kP1Threads) {
-                const int u0 = L.ip[r], u1 = L.ip[r + 1];
-                T acc = 0;
-                for (int u = u0; u < u1; ++u) acc += L.F[u];
-                stg(rhs, ro + (unsigned)(r0 + r), acc);
+        for (int p = tid; p < nent; p += kP1Threads) {
+            const int sa = L.seg[p], se = L.seg[p + 1];
+            if (sa != se) stg(values, vo + (unsigned)(v0 + p), segment_sum<T>(L.K, L.slot, sa, se));
+        }
+        // ---- Reduce per row, on the threads from the last one down: the diagonal
+        // entry (every pair of the row contributes K_e[a][a]) and the right-hand
+        // side (S_vec projection), both in the row's pair order.
+        const unsigned ro = (unsigned)m * n_rows;
+        for (int r = rr; r < nr; r += kP1Threads) {
+            const int u0 = L.ip[r], u1 = L.ip[r + 1];
+            T accd = 0, accf = 0;
+            int u = u0;
+            for (; u + 4 <= u1; u += 4) {
+                const T2 d0 = L.DF[u], d1 = L.DF[u + 1], d2 = L.DF[u + 2], d3 = L.DF[u + 3];
+                accd += d0.x;
+                accf += d0.y;
+                accd += d1.x;
+                accf += d1.y;
+                accd += d2.x;
+                accf += d2.y;
+                accd += d3.x;
+                accf += d3.y;
             }
+            for (; u < u1; ++u) {
+                const T2 d0 = L.DF[u];
+                accd += d0.x;
+                accf += d0.y;
+            }
+            const int dp = r == rr ? dp_reg : ldg(diag_pos, (unsigned)(r0 + r));
+            stg(values, vo + (unsigned)dp, accd);
+            if (LOAD) stg(rhs, ro + (unsigned)(r0 + r), accf);
         }
         if (m + 1 < nmem) __syncthreads();  // LDS is rewritten by the next member
     }
@@ -491,13 +552,13 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     constexpr int K = 10;
     constexpr int VS = VertLds<3>::VS;
     extern __shared__ __align__(16) unsigned char smem[];
-    BlockLds<T> L(smem, mp, me, 9 * K, 3, K);
+    BlockLds<T> L(smem, mp, me, 9 * K, 3);
     double *Lx = reinterpret_cast<double *>(smem + VertLds<3>::offset(BlockLds<T>::bytes(mp, me, 9 * K, 3, K)));
     __shared__ int sRp[kP2BlockCap + 1];
 
     const int blk = xcd_swizzle(blockIdx.x, nblk);
-    const int4 dsc = ldg(reinterpret_cast<const int4 *>(blk_desc), 2u * blk);
-    const int4 dsv = ldg(reinterpret_cast<const int4 *>(blk_desc), 2u * blk + 1u);
+    const int4 dsc = ldg(reinterpret_cast<const int4 *>(blk_desc), 3u * blk);
+    const int4 dsv = ldg(reinterpret_cast<const int4 *>(blk_desc), 3u * blk + 1u);
     const int r0 = dsc.x, r1 = dsc.y, q0 = dsc.z, q1 = dsc.w, rp0 = dsv.x, rp1 = dsv.y, w0 = dsv.z, w1 = dsv.w;
     const int np = q1 - q0, nent = rp1 - rp0, nvb = w1 - w0;
     const int nrows = r1 - r0;
@@ -614,18 +675,18 @@ static hipError_t launch_p1_t(const tg_pattern &p, int nbatch, const double *coo
     const HostPattern &h = p.host;
     const int nblk = (int)h.n_blocks();
     const int mp = h.max_block_pairs, me = h.max_block_entries, mr = h.max_block_rows;
-    const size_t lds = VertLds<D>::offset(BlockLds<T>::bytes(mp, me, D + 1, 1, D + 1, mr)) +
-                       VertLds<D>::bytes(h.max_block_verts);
+    const size_t lds_verts = VertLds<D>::offset(P1Lds<T>::bytes(mp, me, mr, D + 1));
+    const size_t lds = lds_verts + VertLds<D>::bytes(h.max_block_verts);
     if (nbatch == 1)
         hipLaunchKernelGGL((p1_assemble_kernel<D, T, FORM, LOAD, false>), dim3(nblk), dim3(kP1Threads), lds, s,
-                           d.blk_desc, d.inc_ptr, d.inc, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, coords,
-                           (const T *)coef, (const T *)load, (T *)values, (T *)rhs, status, nblk, mp, me, mr, 1,
-                           (unsigned)h.E, (unsigned)h.nnz, (unsigned)h.n_dofs);
+                           d.blk_desc, d.inc_ptr, d.inc, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, d.diag_pos,
+                           coords, (const T *)coef, (const T *)load, (T *)values, (T *)rhs, status, nblk, mp, me, 1,
+                           (unsigned)h.E, (unsigned)h.nnz, (unsigned)h.n_dofs, (unsigned)lds_verts);
     else
         hipLaunchKernelGGL((p1_assemble_kernel<D, T, FORM, LOAD, true>), dim3(nblk), dim3(kP1Threads), lds, s,
-                           d.blk_desc, d.inc_ptr, d.inc, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, coords,
-                           (const T *)coef, (const T *)load, (T *)values, (T *)rhs, status, nblk, mp, me, mr, nbatch,
-                           (unsigned)h.E, (unsigned)h.nnz, (unsigned)h.n_dofs);
+                           d.blk_desc, d.inc_ptr, d.inc, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, d.diag_pos,
+                           coords, (const T *)coef, (const T *)load, (T *)values, (T *)rhs, status, nblk, mp, me,
+                           nbatch, (unsigned)h.E, (unsigned)h.nnz, (unsigned)h.n_dofs, (unsigned)lds_verts);
     return hipGetLastError();
 }
 

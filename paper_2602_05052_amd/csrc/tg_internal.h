@@ -22,6 +22,7 @@ constexpr int kP1BlockVerts = 256;  // distinct vertices of a block (8-bit local
 constexpr int kP2Threads = 256;
 constexpr int kP2BlockTarget = 32;
 constexpr int kP2BlockCap = 64;
+constexpr int kBlkDesc = 12;  // ints per row-block descriptor
 
 // Host-side topology of one mesh: numbering, node-level CSR and the routing
 // of element slots to CSR entries.
@@ -41,7 +42,9 @@ struct HostPattern {
     std::vector<int32_t> inc;      // [n_pairs]
     // Row blocks for the fused kernels.
     std::vector<int32_t> blk_row;   // [n_blocks+1]
-    std::vector<int32_t> blk_desc;  // [n_blocks][8]: r0, r1, q0, q1, v0, v1, w0, w1 (rows, pairs, node entries, vertices)
+    // [n_blocks][kBlkDesc]: r0, r1, q0, q1, v0, v1, w0, w1, s0, s1, 0, 0 (rows, pairs,
+    // node entries, vertices, routing slots)
+    std::vector<int32_t> blk_desc;
     // The distinct vertices of each block's elements (ascending), and per pair
     // the block-local ids of its element's vertices, one byte each in local
     // vertex order (the Map reads coordinates from a per-block LDS copy).
@@ -49,8 +52,10 @@ struct HostPattern {
     std::vector<uint32_t> pair_lv;  // [n_pairs]
     // S_mat routing: node-level entry p sums slots slot[seg_ptr[p] .. seg_ptr[p+1]),
     // ascending element order; slot = b * (pairs of the block) + (pair - first pair of the block).
+    // P1: the diagonal entry of a row has an empty segment; its value is the sum over
+    // the row's pairs (S_vec order) of the element's diagonal entry K_e[a][a].
     std::vector<int32_t> seg_ptr;  // [nnz_nodes+1]
-    std::vector<uint16_t> slot;    // [n_pairs * k]
+    std::vector<uint16_t> slot;    // [seg_ptr[nnz_nodes]] rounded up to a multiple of 4
     // Scalar CSR (DoF = ncomp * node + c).
     std::vector<int32_t> row_ptr;   // [n_dofs+1]
     std::vector<int32_t> col_idx;   // [nnz]

@@ -244,7 +244,10 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
     // ---- S_mat routing, row by row
     hp.seg_ptr.clear();
     hp.seg_ptr.reserve((size_t)hp.node_ci.size() + 1);
-    hp.slot.resize((size_t)E * k * k);
+    // P1 diagonal entries take no slots: the kernel sums the pairs' own diagonal
+    // entries row by row (the same terms in the same order).
+    const bool skip_diag = p1;
+    hp.slot.resize((size_t)E * k * (skip_diag ? k - 1 : k) + 3);
     int64_t slot_fill = 0;
     int64_t blk = 0;
     for (int64_t i = 0; i < N; ++i) {
@@ -255,9 +258,13 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
         for (int32_t c = 0; c < m; ++c) pos[hp.node_ci[c0 + c]] = c;
         // counts per entry, then slots in (pair ascending, b) order -> ascending element per entry
         cnt.assign(m + 1, 0);
+        const int diag = skip_diag ? pos[i] : -1;
         for (int32_t t = hp.inc_ptr[i]; t < hp.inc_ptr[i + 1]; ++t) {
             const int64_t e = hp.inc[t] / k;
-            for (int b = 0; b < k; ++b) cnt[pos[hp.elem_nodes[e * k + b]] + 1]++;
+            for (int b = 0; b < k; ++b) {
+                const int c = pos[hp.elem_nodes[e * k + b]];
+                if (c != diag) cnt[c + 1]++;
+            }
         }
         for (int32_t c = 0; c < m; ++c) cnt[c + 1] += cnt[c];
         for (int32_t c = 0; c < m; ++c) hp.seg_ptr.push_back((int32_t)(slot_fill + cnt[c]));
@@ -265,24 +272,28 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
             const int64_t e = hp.inc[t] / k;
             for (int b = 0; b < k; ++b) {
                 const int c = pos[hp.elem_nodes[e * k + b]];
-                hp.slot[slot_fill + cnt[c]++] = (uint16_t)(b * blk_pairs + (t - blk_first_pair));
+                if (c != diag) hp.slot[slot_fill + cnt[c]++] = (uint16_t)(b * blk_pairs + (t - blk_first_pair));
             }
         }
-        slot_fill += (int64_t)(hp.inc_ptr[i + 1] - hp.inc_ptr[i]) * k;
+        slot_fill += cnt[m];
     }
     hp.seg_ptr.push_back((int32_t)slot_fill);
+    // the kernels copy whole 4-slot units: pad to a multiple of 4 (never referenced)
+    hp.slot.resize(((size_t)slot_fill + 3) & ~(size_t)3, 0);
     hp.nnz_nodes = (int64_t)hp.node_ci.size();
     hp.max_block_pairs = hp.max_block_entries = hp.max_block_rows = 0;
-    hp.blk_desc.assign((hp.blk_row.size() - 1) * 8, 0);
+    hp.blk_desc.assign((hp.blk_row.size() - 1) * kBlkDesc, 0);
     for (int64_t b = 0; b + 1 < (int64_t)hp.blk_row.size(); ++b) {
         const int32_t r0 = hp.blk_row[b], r1 = hp.blk_row[b + 1];
-        int32_t *dsc = &hp.blk_desc[b * 8];
+        int32_t *dsc = &hp.blk_desc[b * kBlkDesc];
         dsc[0] = r0;
         dsc[1] = r1;
         dsc[2] = hp.inc_ptr[r0];
         dsc[3] = hp.inc_ptr[r1];
         dsc[4] = hp.node_rp[r0];
         dsc[5] = hp.node_rp[r1];
+        dsc[8] = hp.seg_ptr[hp.node_rp[r0]];
+        dsc[9] = hp.seg_ptr[hp.node_rp[r1]];
         hp.max_block_pairs = std::max(hp.max_block_pairs, hp.inc_ptr[r1] - hp.inc_ptr[r0]);
         hp.max_block_entries = std::max(hp.max_block_entries, hp.node_rp[r1] - hp.node_rp[r0]);
         hp.max_block_rows = std::max(hp.max_block_rows, r1 - r0);
@@ -298,7 +309,7 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
         hp.pair_lv.assign((size_t)E * k, 0u);
         std::vector<int32_t> local(hp.nv, -1), verts;
         for (int64_t b = 0; b + 1 < (int64_t)hp.blk_row.size(); ++b) {
-            int32_t *dsc = &hp.blk_desc[b * 8];
+            int32_t *dsc = &hp.blk_desc[b * kBlkDesc];
             const int32_t q0 = dsc[2], q1 = dsc[3];
             verts.clear();
             for (int32_t t = q0; t < q1; ++t) {

@@ -47,7 +47,8 @@ def _pair_of_slot(r, k):
     node_of_entry = np.repeat(np.arange(nodes), np.diff(r["node_rp"]))
     seg_len = np.diff(r["seg_ptr"])
     slot_entry = np.repeat(np.arange(len(seg_len)), seg_len)
-    slot = r["slot"].astype(np.int64)
+    assert len(r["slot"]) % 4 == 0 and len(r["slot"]) - r["seg_ptr"][-1] < 4  # padded to 4-slot units
+    slot = r["slot"][:r["seg_ptr"][-1]].astype(np.int64)
     blk = row_blk[node_of_entry[slot_entry]]
     blk_pairs = (r["inc_ptr"][r["blk_row"][1:]] - r["inc_ptr"][r["blk_row"][:-1]])[blk]
     pair = blk_first_pair[blk] + slot % blk_pairs
@@ -76,6 +77,12 @@ def test_p1_pattern_routing_equals_oracle(dim, n):
     pair, b = _pair_of_slot(r, k)
     code = r["inc"][pair]
     vals = _sequential_segment_sum(Kl[code // k, code % k, b], r["seg_ptr"])
+    # diagonal entries carry no slots: each sums its row's pairs' K_e[a][a] in S_vec order
+    node_of_entry = np.repeat(np.arange(pat.n_nodes), np.diff(r["node_rp"]))
+    diag = np.flatnonzero(ci == node_of_entry)
+    assert len(diag) == pat.n_nodes and np.all(np.diff(r["seg_ptr"])[diag] == 0)
+    assert np.all(np.diff(r["seg_ptr"])[np.setdiff1d(np.arange(len(ci)), diag)] > 0)
+    vals[diag] = _sequential_segment_sum(Kl[r["inc"] // k, r["inc"] % k, r["inc"] % k], r["inc_ptr"])
     assert np.array_equal(vals, A.vals)  # bitwise
     rhs = _sequential_segment_sum(Fl[r["inc"] // k, r["inc"] % k], r["inc_ptr"])
     assert np.array_equal(rhs, A.rhs)
@@ -221,6 +228,15 @@ def test_block_vertex_staging_in_bounds(dim, n, shuffle):
     for b in range(pat.n_blocks):  # ascending and distinct within a block
         seg = vert[vptr[b]:vptr[b + 1]]
         assert np.all(np.diff(seg) > 0)
+    # the kernel copies each block's slots in whole 4-slot units from s0 rounded down to 4:
+    # the units stay inside the padded slot list and inside the LDS slot array (mp (k-1) + 8)
+    mp = int(np.diff(r["inc_ptr"][r["blk_row"]]).max())
+    s0 = r["seg_ptr"][r["node_rp"][r["blk_row"][:-1]]]
+    s1 = r["seg_ptr"][r["node_rp"][r["blk_row"][1:]]]
+    sb = s0 & ~3
+    nu = (s1 - sb + 3) // 4
+    assert np.all(nu >= 1) and np.all(sb + 4 * nu <= len(r["slot"]))
+    assert np.all(4 * nu <= mp * (k - 1) + 8)
 
 
 @pytest.mark.parametrize("n", [1, 3])
