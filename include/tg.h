@@ -166,6 +166,20 @@ tg_status tg_pattern_copy_element_nodes(const tg_pattern *p, int32_t *h_nodes);
  *       h_seg_ptr[Z] rounded up to a multiple of 4; the tail is unused.
  */
 /*
+ * The compact form of the P1 routing that the assembly kernel reads when every
+ * node has at most 256 / k pairs and every row block at most 255 rows (*compact
+ * receives 1; otherwise 0 and the kernel reads the form above).  It names the
+ * same slots in the same order: the slots of node i start at inc_ptr[i] (k-1)
+ * in h_slot8 [ceil4(P (k-1))], one byte each, coded (t - inc_ptr[i]) k + b for
+ * pair t and local column b; node-level entry z of node i, the r-th row of its
+ * block, is h_ent16[z] = r << 8 | (h_seg_ptr[z] - inc_ptr[i] (k-1)) (array
+ * [Z]).  Either array may be NULL; nothing is copied when *compact is 0.
+ * TG_E_ARG for a P2 pattern.
+ */
+tg_status tg_pattern_copy_compact_routing(const tg_pattern *p, int32_t *compact, uint16_t *h_ent16,
+                                          uint8_t *h_slot8);
+
+/*
  * The coordinate staging of the fused kernels.  Row block b reads the
  * coordinates of its elements' distinct vertices
  * h_blk_vert[h_blk_vptr[b] .. h_blk_vptr[b+1]) (ascending, at most 256) into

@@ -79,6 +79,8 @@ _SIGS = {
                                                ctypes.POINTER(ctypes.c_uint16)]),
     "tg_pattern_copy_block_vertices": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), _i32p, _i32p,
                                                       ctypes.POINTER(ctypes.c_uint32)]),
+    "tg_pattern_copy_compact_routing": (ctypes.c_int, [_vp, _i32p, ctypes.POINTER(ctypes.c_uint16),
+                                                       ctypes.POINTER(ctypes.c_uint8)]),
     "tg_pattern_destroy": (None, [_vp]),
     "tg_assemble": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tg_assemble_batched": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -257,6 +259,21 @@ class Pattern:
             self._h, *(out[k].ctypes.data_as(_i32p) for k in ("inc_ptr", "inc", "blk_row", "node_rp", "seg_ptr")),
             out["slot"].ctypes.data_as(ctypes.POINTER(ctypes.c_uint16))))
         return out
+
+    def compact_routing(self):
+        """(ent16 [Z], slot8) of the P1 kernel's one-byte routing, or None when the pattern uses the wide form
+        (see tg_pattern_copy_compact_routing)."""
+        flag = ctypes.c_int32(0)
+        _check(_lib.tg_pattern_copy_compact_routing(self._h, ctypes.byref(flag), None, None))
+        if not flag.value:
+            return None
+        Z = self.nnz // (self.ncomp * self.ncomp)
+        ent = np.zeros(max(1, Z), np.uint16)
+        s8 = np.zeros(max(4, (self.n_elements * self.k * (self.k - 1) + 3) // 4 * 4), np.uint8)
+        _check(_lib.tg_pattern_copy_compact_routing(self._h, ctypes.byref(flag),
+                                                    ent.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
+                                                    s8.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+        return ent[:Z], s8
 
     def block_vertices(self):
         """(blk_vptr [B+1], blk_vert, pair_lv [P]) of the kernels' per-block coordinate staging."""

@@ -35,7 +35,7 @@ hipError_t upload(const std::vector<V> &h, V **d, size_t &bytes) {
 void free_device(tg::DevicePattern &d) {
     void *ptrs[] = {d.conn,    d.inc_ptr, d.inc,      d.blk_row,     d.blk_desc, d.node_rp, d.node_ci, d.seg_ptr,
                     d.blk_vert, d.pair_lv,
-                    d.slot,    d.row_ptr, d.col_idx,  d.diag_pos,    d.constrained,
+                    d.slot,    d.ent16,   d.slot8,    d.row_ptr,     d.col_idx, d.diag_pos, d.constrained,
                     d.work,    d.partials, d.state, d.dir_rows,  d.pcg_slot, d.pcg_list};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -64,6 +64,8 @@ tg_status create_device(tg_pattern &pt) {
     TG_UP(node_ci, node_ci);
     TG_UP(seg_ptr, seg_ptr);
     TG_UP(slot, slot);
+    TG_UP(ent16, ent16);
+    TG_UP(slot8, slot8);
     TG_UP(row_ptr, row_ptr);
     TG_UP(col_idx, col_idx);
     TG_UP(diag_pos, diag_pos);
@@ -218,6 +220,19 @@ tg_status tg_pattern_copy_routing(const tg_pattern *p, int32_t *h_inc_ptr, int32
     cp(h_node_rp, h.node_rp);
     cp(h_seg_ptr, h.seg_ptr);
     cp(h_slot, h.slot);
+    return ok();
+}
+
+tg_status tg_pattern_copy_compact_routing(const tg_pattern *p, int32_t *compact, uint16_t *h_ent16,
+                                          uint8_t *h_slot8) {
+    if (!p) return fail(TG_E_ARG, "pattern is NULL");
+    const tg::HostPattern &h = p->host;
+    if (h.order != 1) return fail(TG_E_ARG, "the compact routing exists for P1 patterns only");
+    if (compact) *compact = h.compact ? 1 : 0;
+    if (h.compact) {
+        if (h_ent16) std::memcpy(h_ent16, h.ent16.data(), h.ent16.size() * sizeof(uint16_t));
+        if (h_slot8) std::memcpy(h_slot8, h.slot8.data(), h.slot8.size());
+    }
     return ok();
 }
 

@@ -19,6 +19,8 @@
 // K_local therefore never leaves the chip, every output is written exactly
 // once, and no atomics touch values: the result is bitwise reproducible and
 // independent of the launch geometry.
+#include <type_traits>
+
 #include "tg_device.h"
 
 namespace tg {
@@ -92,8 +94,8 @@ __device__ __forceinline__ double p1_gradients(const double (&x)[D + 1][D], doub
 // Sum of src[slot[u]] for u in [u0, u1), added strictly left to right.  The
 // slot indices and values are read four at a time so that the dependent LDS
 // round trips overlap; the order of the additions is unchanged.
-template <typename T, int STRIDE = 1>
-__device__ __forceinline__ T segment_sum(const T *__restrict__ src, const uint16_t *__restrict__ slot, int u0, int u1,
+template <typename T, int STRIDE = 1, typename S>
+__device__ __forceinline__ T segment_sum(const T *__restrict__ src, const S *__restrict__ slot, int u0, int u1,
                                          int off = 0) {
     T acc = 0;
     int u = u0;
@@ -257,27 +259,32 @@ template <> struct Pair2<double> { using type = double2; };
 template <> struct Pair2<float> { using type = float2; };
 
 // Dynamic LDS of one P1 row block (mp pairs, me node entries, mr rows at most):
-//   K    [mp * k]  row a of every pair's local matrix, column-major (b * np + t)
+//   K    [mp * k]  row a of every pair's local matrix: column-major (b * np + t)
+//                  for the wide routing, row-major (t * k + b) for the compact one
 //   DF   [mp]      every pair's diagonal entry K_e[a][a] and load entry F_e[a]
-//   seg  [me + 1]  segment starts of the block's entries, relative to sb
-//   slot [mp (k-1) + 8]  the block's routing slots from sb = s0 rounded down to 4
+//   seg  [me + 1]  wide: segment starts relative to sb (int32); compact: the
+//                  entries' ent16 codes (uint16) and a sentinel
+//   slot [mp (k-1) + 8]  the block's routing slots (uint16 wide, uint8 compact)
+//                  from the 4-aligned base sb
 //   ip   [mr + 1]  first pair of every row of the block
-template <typename T>
+template <typename T, bool COMPACT>
 struct P1Lds {
     using T2 = typename Pair2<T>::type;
+    using Seg = typename std::conditional<COMPACT, uint16_t, int32_t>::type;
+    using Slot = typename std::conditional<COMPACT, uint8_t, uint16_t>::type;
     T *K;
     T2 *DF;
-    int32_t *seg;
-    uint16_t *slot;
+    Seg *seg;
+    Slot *slot;
     int32_t *ip;
     __host__ __device__ static size_t a16(size_t x) { return (x + 15) & ~(size_t)15; }
     __host__ __device__ static size_t off_df(int mp, int k) { return a16(sizeof(T) * (size_t)mp * k); }
     __host__ __device__ static size_t off_seg(int mp, int k) { return a16(off_df(mp, k) + sizeof(T2) * (size_t)mp); }
     __host__ __device__ static size_t off_slot(int mp, int me, int k) {
-        return a16(off_seg(mp, k) + sizeof(int32_t) * (size_t)(me + 1));
+        return a16(off_seg(mp, k) + sizeof(Seg) * (size_t)(me + 1));
     }
     __host__ __device__ static size_t off_ip(int mp, int me, int k) {
-        return a16(off_slot(mp, me, k) + sizeof(uint16_t) * ((size_t)mp * (k - 1) + 8));
+        return a16(off_slot(mp, me, k) + sizeof(Slot) * ((size_t)mp * (k - 1) + 8));
     }
     __host__ __device__ static size_t bytes(int mp, int me, int mr, int k) {
         return a16(off_ip(mp, me, k) + sizeof(int32_t) * (size_t)(mr + 1));
@@ -285,8 +292,8 @@ struct P1Lds {
     __device__ P1Lds(unsigned char *base, int mp, int me, int k) {
         K = reinterpret_cast<T *>(base);
         DF = reinterpret_cast<T2 *>(base + off_df(mp, k));
-        seg = reinterpret_cast<int32_t *>(base + off_seg(mp, k));
-        slot = reinterpret_cast<uint16_t *>(base + off_slot(mp, me, k));
+        seg = reinterpret_cast<Seg *>(base + off_seg(mp, k));
+        slot = reinterpret_cast<Slot *>(base + off_slot(mp, me, k));
         ip = reinterpret_cast<int32_t *>(base + off_ip(mp, me, k));
     }
 };
@@ -304,12 +311,14 @@ constexpr int p1_waves_per_eu() {
 // call is nbatch = 1).  Member m reads coef[m E + e] and load[m E + e] and
 // writes values[m nnz + p] and rhs[m N + i]; the geometry and the routing are
 // read once for the whole batch.  Every member runs exactly the arithmetic
-// of a single call, so it is bitwise equal to assembling it alone.
-template <int D, typename T, int FORM, bool LOAD, bool BATCHED>
+// of a single call, so it is bitwise equal to assembling it alone.  COMPACT
+// selects the one-byte routing (ent16 / slot8) over the wide one (seg_ptr /
+// slot); both name the same slots in the same order.
+template <int D, typename T, int FORM, bool LOAD, bool BATCHED, bool COMPACT>
 __global__ __launch_bounds__(kP1Threads) __attribute__((amdgpu_waves_per_eu(p1_waves_per_eu<T, FORM, BATCHED>())))
 void p1_assemble_kernel(
     const int32_t *__restrict__ blk_desc, const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc,
-    const int32_t *__restrict__ seg_ptr, const uint16_t *__restrict__ slot, const int32_t *__restrict__ blk_vert,
+    const void *__restrict__ seg_v, const void *__restrict__ slot_v, const int32_t *__restrict__ blk_vert,
     const uint32_t *__restrict__ pair_lv, const int32_t *__restrict__ diag_pos, const double *__restrict__ coords,
     const T *__restrict__ coef, const T *__restrict__ load, T *__restrict__ values, T *__restrict__ rhs,
     int32_t *__restrict__ status, int nblk, int mp, int me, int nbatch, unsigned n_elem, unsigned nnz,
@@ -317,22 +326,38 @@ void p1_assemble_kernel(
     constexpr int K = D + 1;
     constexpr int VS = VertLds<D>::VS;
     constexpr bool COEF = FORM != kMass;
-    using T2 = typename P1Lds<T>::T2;
+    using LdsT = P1Lds<T, COMPACT>;
+    using T2 = typename LdsT::T2;
+    using Seg = typename LdsT::Seg;
     static_assert(kP1BlockVerts <= kP1Threads, "one staged vertex per thread");
     extern __shared__ __align__(16) unsigned char smem[];
-    P1Lds<T> L(smem, mp, me, K);
+    LdsT L(smem, mp, me, K);
     double *Lx = reinterpret_cast<double *>(smem + lds_verts);
+    const Seg *__restrict__ seg_g = static_cast<const Seg *>(seg_v);  // seg_ptr (wide) or ent16 (compact)
+    // the slot list as 8-byte units (4 wide slots) or 4-byte units (4 compact slots)
+    using Unit = typename std::conditional<COMPACT, uint32_t, uint2>::type;
+    const Unit *__restrict__ slot_u = static_cast<const Unit *>(slot_v);
 
     const int blk = xcd_swizzle(blockIdx.x, nblk);
     const int4 dsc = ldg(reinterpret_cast<const int4 *>(blk_desc), 3u * blk);
     const int4 dsv = ldg(reinterpret_cast<const int4 *>(blk_desc), 3u * blk + 1u);
-    const int2 dss = ldg(reinterpret_cast<const int2 *>(blk_desc), 6u * blk + 4u);
     const int r0 = dsc.x, r1 = dsc.y, q0 = dsc.z, q1 = dsc.w, v0 = dsv.x, v1 = dsv.y, w0 = dsv.z, w1 = dsv.w;
     const int np = q1 - q0, nent = v1 - v0, nvb = w1 - w0, nr = r1 - r0;
-    const int sb = dss.x & ~3;               // the block's slots are slot[dss.x .. dss.y); copied from sb
-    const int nu = (dss.y - sb + 3) >> 2;    // 4-slot units to copy
+    // the block's slots: wide slot[s0 .. s1) from the descriptor; compact slot8[q0 (k-1) .. q1 (k-1));
+    // copied in 4-slot units from sb = s0 rounded down to 4
+    int s0, s1;
+    if constexpr (COMPACT) {
+        s0 = q0 * (K - 1);
+        s1 = q1 * (K - 1);
+    } else {
+        const int2 dss = ldg(reinterpret_cast<const int2 *>(blk_desc), 6u * blk + 4u);
+        s0 = dss.x;
+        s1 = dss.y;
+    }
+    const int sb = s0 & ~3;
+    const int nu = (s1 - sb + 3) >> 2;
     const int tid = threadIdx.x;
-    const int rr = kP1Threads - 1 - tid;     // the row this thread sums (the Reduce's last threads)
+    const int rr = kP1Threads - 1 - tid;  // the row this thread sums (the Reduce's last threads)
     const int nmem = BATCHED ? nbatch : 1;
 
     if (np == 0) {  // rows of nodes that belong to no element: no values, zero loads
@@ -345,18 +370,19 @@ void p1_assemble_kernel(
     // ---- Every load that needs only the block descriptor, issued back to back
     // with clamped (always valid) indices and no branches, so that their
     // latencies overlap: the vertex this thread stages, its pair's code and
-    // local vertex ids, a 4-slot unit of the routing, one segment pointer, one
-    // row offset and one row's diagonal position.  Then the loads that need one
-    // of them: the staged vertex's coordinates and the pair's coefficients.
-    // Two memory latencies in all.
+    // local vertex ids, a 4-slot unit of the routing, one entry's segment
+    // pointer (or code), one row offset and one row's diagonal position.  Then
+    // the loads that need one of them: the staged vertex's coordinates and the
+    // pair's coefficients.  Two memory latencies in all.
     const int tp = min(tid, np - 1);
     const unsigned vid = (unsigned)ldg(blk_vert, (unsigned)(w0 + min(tid, nvb - 1)));
     const unsigned code = (unsigned)ldg(inc, (unsigned)(q0 + tp));
     const uint32_t lv = ldg(pair_lv, (unsigned)(q0 + tp));
-    const int seg_reg = ldg(seg_ptr, (unsigned)(v0 + min(tid, nent)));
+    const int te = COMPACT ? min(tid, nent - 1) : min(tid, nent);  // compact: the sentinel is written below
+    const Seg seg_reg = ldg(seg_g, (unsigned)(v0 + te));
     const int ip_reg = ldg(inc_ptr, (unsigned)(r0 + min(tid, nr)));
     const int dp_reg = ldg(diag_pos, (unsigned)(r0 + min(rr, nr - 1)));
-    const uint2 slot_w = ldg(reinterpret_cast<const uint2 *>(slot), (unsigned)(sb >> 2) + (unsigned)min(tid, nu - 1));
+    const Unit slot_w = ldg(slot_u, (unsigned)(sb >> 2) + (unsigned)min(tid, nu - 1));
     double vxyz[D];
     if constexpr (D == 3) {
         vxyz[0] = ldg(coords, 3u * vid);
@@ -382,13 +408,19 @@ void p1_assemble_kernel(
         *reinterpret_cast<double2 *>(lx) = make_double2(vxyz[0], vxyz[1]);
         if constexpr (D == 3) lx[2] = vxyz[2];
     }
-    *reinterpret_cast<uint2 *>(L.slot + 4 * min(tid, nu - 1)) = slot_w;
-    L.seg[min(tid, nent)] = seg_reg - sb;
+    reinterpret_cast<Unit *>(L.slot)[min(tid, nu - 1)] = slot_w;
+    if constexpr (COMPACT) {
+        L.seg[te] = seg_reg;
+        if (tid == 0) L.seg[nent] = (uint16_t)(nr << 8);  // sentinel: row nr, offset 0 = the block's end
+    } else {
+        L.seg[te] = seg_reg - sb;
+    }
     L.ip[min(tid, nr)] = ip_reg - q0;
     // remainders of large blocks (a single row with more pairs, entries or rows than threads)
     for (int u = tid + kP1Threads; u < nu; u += kP1Threads)
-        *reinterpret_cast<uint2 *>(L.slot + 4 * u) = ldg(reinterpret_cast<const uint2 *>(slot), (unsigned)((sb >> 2) + u));
-    for (int u = tid + kP1Threads; u <= nent; u += kP1Threads) L.seg[u] = ldg(seg_ptr, (unsigned)(v0 + u)) - sb;
+        reinterpret_cast<Unit *>(L.slot)[u] = ldg(slot_u, (unsigned)((sb >> 2) + u));
+    for (int u = tid + kP1Threads; u < nent + (COMPACT ? 0 : 1); u += kP1Threads)
+        L.seg[u] = COMPACT ? ldg(seg_g, (unsigned)(v0 + u)) : (Seg)(ldg(seg_g, (unsigned)(v0 + u)) - sb);
     for (int u = tid + kP1Threads; u <= nr; u += kP1Threads) L.ip[u] = ldg(inc_ptr, (unsigned)(r0 + u)) - q0;
     __syncthreads();  // vertices and routing are in LDS
 
@@ -417,7 +449,7 @@ void p1_assemble_kernel(
 #pragma unroll
             for (int b = 1; b < K; ++b) kd = (a == b) ? row[b] : kd;
 #pragma unroll
-            for (int b = 0; b < K; ++b) L.K[b * np + tid] = row[b];
+            for (int b = 0; b < K; ++b) L.K[COMPACT ? tid * K + b : b * np + tid] = row[b];
             L.DF[tid] = T2{kd, fa};
             const bool bad = (bool)((int)g.bad | (int)!finite(c) | (int)!finite(f));
             if (bad && status) atomicMin(status, (int)e);
@@ -438,7 +470,7 @@ void p1_assemble_kernel(
 #pragma unroll
             for (int b = 1; b < K; ++b) kd = (at == b) ? row[b] : kd;
 #pragma unroll
-            for (int b = 0; b < K; ++b) L.K[b * np + t] = row[b];
+            for (int b = 0; b < K; ++b) L.K[COMPACT ? t * K + b : b * np + t] = row[b];
             L.DF[t] = T2{kd, fa};
             if (((int)gg.bad | (int)!finite(ct) | (int)!finite(ft)) && status) atomicMin(status, (int)ee);
         }
@@ -448,8 +480,16 @@ void p1_assemble_kernel(
         // projection), LDS only; a row's diagonal entry has no slots.
         const unsigned vo = (unsigned)m * nnz;
         for (int p = tid; p < nent; p += kP1Threads) {
-            const int sa = L.seg[p], se = L.seg[p + 1];
-            if (sa != se) stg(values, vo + (unsigned)(v0 + p), segment_sum<T>(L.K, L.slot, sa, se));
+            if constexpr (COMPACT) {
+                const unsigned e0 = L.seg[p], e1 = L.seg[p + 1];
+                const int u0 = L.ip[e0 >> 8];
+                const int sa = s0 - sb + u0 * (K - 1) + (int)(e0 & 255u);
+                const int se = s0 - sb + L.ip[e1 >> 8] * (K - 1) + (int)(e1 & 255u);
+                if (sa != se) stg(values, vo + (unsigned)(v0 + p), segment_sum<T>(L.K + u0 * K, L.slot, sa, se));
+            } else {
+                const int sa = L.seg[p], se = L.seg[p + 1];
+                if (sa != se) stg(values, vo + (unsigned)(v0 + p), segment_sum<T>(L.K, L.slot, sa, se));
+            }
         }
         // ---- Reduce per row, on the threads from the last one down: the diagonal
         // entry (every pair of the row contributes K_e[a][a]) and the right-hand
@@ -675,18 +715,23 @@ static hipError_t launch_p1_t(const tg_pattern &p, int nbatch, const double *coo
     const HostPattern &h = p.host;
     const int nblk = (int)h.n_blocks();
     const int mp = h.max_block_pairs, me = h.max_block_entries, mr = h.max_block_rows;
-    const size_t lds_verts = VertLds<D>::offset(P1Lds<T>::bytes(mp, me, mr, D + 1));
-    const size_t lds = lds_verts + VertLds<D>::bytes(h.max_block_verts);
-    if (nbatch == 1)
-        hipLaunchKernelGGL((p1_assemble_kernel<D, T, FORM, LOAD, false>), dim3(nblk), dim3(kP1Threads), lds, s,
-                           d.blk_desc, d.inc_ptr, d.inc, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, d.diag_pos,
-                           coords, (const T *)coef, (const T *)load, (T *)values, (T *)rhs, status, nblk, mp, me, 1,
+    auto go = [&](auto batched, auto compact) {
+        constexpr bool B = decltype(batched)::value, C = decltype(compact)::value;
+        const size_t lds_verts = VertLds<D>::offset(P1Lds<T, C>::bytes(mp, me, mr, D + 1));
+        const size_t lds = lds_verts + VertLds<D>::bytes(h.max_block_verts);
+        const void *seg = C ? (const void *)d.ent16 : (const void *)d.seg_ptr;
+        const void *slot = C ? (const void *)d.slot8 : (const void *)d.slot;
+        hipLaunchKernelGGL((p1_assemble_kernel<D, T, FORM, LOAD, B, C>), dim3(nblk), dim3(kP1Threads), lds, s,
+                           d.blk_desc, d.inc_ptr, d.inc, seg, slot, d.blk_vert, d.pair_lv, d.diag_pos, coords,
+                           (const T *)coef, (const T *)load, (T *)values, (T *)rhs, status, nblk, mp, me, nbatch,
                            (unsigned)h.E, (unsigned)h.nnz, (unsigned)h.n_dofs, (unsigned)lds_verts);
+    };
+    using F_ = std::false_type;
+    using T_ = std::true_type;
+    if (nbatch == 1)
+        h.compact ? go(F_{}, T_{}) : go(F_{}, F_{});
     else
-        hipLaunchKernelGGL((p1_assemble_kernel<D, T, FORM, LOAD, true>), dim3(nblk), dim3(kP1Threads), lds, s,
-                           d.blk_desc, d.inc_ptr, d.inc, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, d.diag_pos,
-                           coords, (const T *)coef, (const T *)load, (T *)values, (T *)rhs, status, nblk, mp, me,
-                           nbatch, (unsigned)h.E, (unsigned)h.nnz, (unsigned)h.n_dofs, (unsigned)lds_verts);
+        h.compact ? go(T_{}, T_{}) : go(T_{}, F_{});
     return hipGetLastError();
 }
 

@@ -23,6 +23,9 @@ constexpr int kP2Threads = 256;
 constexpr int kP2BlockTarget = 32;
 constexpr int kP2BlockCap = 64;
 constexpr int kBlkDesc = 12;  // ints per row-block descriptor
+// Largest pair count of a row for the compact P1 routing: its one-byte
+// row-relative slot codes (pair offset * k + b) stay below 256.
+constexpr int compact_row_pairs(int k) { return 256 / k; }
 
 // Host-side topology of one mesh: numbering, node-level CSR and the routing
 // of element slots to CSR entries.
@@ -56,6 +59,13 @@ struct HostPattern {
     // the row's pairs (S_vec order) of the element's diagonal entry K_e[a][a].
     std::vector<int32_t> seg_ptr;  // [nnz_nodes+1]
     std::vector<uint16_t> slot;    // [seg_ptr[nnz_nodes]] rounded up to a multiple of 4
+    // Compact form of the same P1 routing (used by the kernel when every row has at
+    // most compact_row_pairs(k) pairs and every block at most 255 rows): the slots of
+    // row i are slot8[inc_ptr[i] (k-1) ...], one byte each, coded (pair - inc_ptr[i]) k + b;
+    // entry z of row i (block-local row r) is ent16[z] = r << 8 | (seg_ptr[z] - inc_ptr[i] (k-1)).
+    bool compact = false;
+    std::vector<uint16_t> ent16;  // [nnz_nodes]
+    std::vector<uint8_t> slot8;   // [n_pairs (k-1)] rounded up to a multiple of 4
     // Scalar CSR (DoF = ncomp * node + c).
     std::vector<int32_t> row_ptr;   // [n_dofs+1]
     std::vector<int32_t> col_idx;   // [nnz]
@@ -125,6 +135,8 @@ struct DevicePattern {
     int32_t *node_ci = nullptr;   // [nnz_nodes]
     int32_t *seg_ptr = nullptr;   // [nnz_nodes+1]
     uint16_t *slot = nullptr;     // [n_pairs*k]
+    uint16_t *ent16 = nullptr;    // compact P1 routing (HostPattern::compact)
+    uint8_t *slot8 = nullptr;
     int32_t *row_ptr = nullptr;   // [n_dofs+1]
     int32_t *col_idx = nullptr;   // [nnz]
     int32_t *diag_pos = nullptr;  // [n_dofs]

@@ -298,6 +298,33 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
         hp.max_block_entries = std::max(hp.max_block_entries, hp.node_rp[r1] - hp.node_rp[r0]);
         hp.max_block_rows = std::max(hp.max_block_rows, r1 - r0);
     }
+    // ---- compact P1 routing (same slots and order, one byte per slot, two per entry)
+    hp.compact = false;
+    hp.ent16.clear();
+    hp.slot8.clear();
+    if (p1) {
+        int32_t max_row_pairs = 0;
+        for (int64_t i = 0; i < N; ++i) max_row_pairs = std::max(max_row_pairs, hp.inc_ptr[i + 1] - hp.inc_ptr[i]);
+        hp.compact = max_row_pairs <= compact_row_pairs(k) && hp.max_block_rows <= 255;
+    }
+    if (hp.compact) {
+        hp.ent16.resize((size_t)hp.nnz_nodes);
+        hp.slot8.assign(((size_t)hp.n_pairs() * (k - 1) + 3) & ~(size_t)3, 0);
+        for (int64_t b = 0; b + 1 < (int64_t)hp.blk_row.size(); ++b) {
+            const int32_t r0 = hp.blk_row[b], r1 = hp.blk_row[b + 1];
+            const int32_t bf = hp.inc_ptr[r0], bp = hp.inc_ptr[r1] - bf;  // first pair, pairs of the block
+            for (int32_t i = r0; i < r1; ++i) {
+                const int32_t rs = hp.inc_ptr[i] * (k - 1);  // the row's first slot (wide and compact alike)
+                for (int32_t z = hp.node_rp[i]; z < hp.node_rp[i + 1]; ++z) {
+                    hp.ent16[z] = (uint16_t)(((i - r0) << 8) | (hp.seg_ptr[z] - rs));
+                    for (int32_t g = hp.seg_ptr[z]; g < hp.seg_ptr[z + 1]; ++g) {
+                        const int32_t t = bf + hp.slot[g] % bp, bb = hp.slot[g] / bp;
+                        hp.slot8[g] = (uint8_t)((t - hp.inc_ptr[i]) * k + bb);
+                    }
+                }
+            }
+        }
+    }
     // ---- block vertex lists and the per-pair block-local ids of the element's
     // vertices (its first dim + 1 nodes; P2 blocks hold at most 64 pairs, so
     // at most 256 vertices)

@@ -80,6 +80,42 @@ def test_p1_mass_parity(dim, n, dtype):
     _check_p1(meshgen.poisson_inputs(dim, n, seed=3), dtype, form=tg.MASS)
 
 
+def _fan_inputs(dim, m, seed):
+    """A node shared by m elements (more than the one-byte routing holds for m > 256 / (dim + 1)):
+    2D a fan of m triangles around the origin; 3D m tets joining a bottom apex, a ring edge and a top apex."""
+    rng = np.random.default_rng(seed)
+    ang = np.linspace(0, 2 * np.pi, m, endpoint=False)
+    if dim == 2:
+        coords = np.concatenate([[[0.0, 0.0]], np.stack([np.cos(ang), np.sin(ang)], 1)])
+        conn = np.array([[0, 1 + i, 1 + (i + 1) % m] for i in range(m)], dtype=np.int32)
+    else:
+        ring = np.stack([np.cos(ang), np.sin(ang), 0.1 * np.sin(3 * ang)], 1)
+        coords = np.concatenate([[[0.0, 0.0, -1.0], [0.0, 0.0, 1.0]], ring])
+        conn = np.array([[0, 2 + i, 2 + (i + 1) % m, 1] for i in range(m)], dtype=np.int32)
+    return {"coords": np.ascontiguousarray(coords), "conn": conn, "a": np.exp(rng.standard_normal(m)),
+            "f": rng.uniform(-1, 1, m)}
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dim,m", [(2, 100), (3, 80)])
+def test_p1_wide_routing_parity(dim, m, dtype):
+    """High-valence nodes: the pattern keeps the wide routing (its own kernel instance)."""
+    d = _fan_inputs(dim, m, seed=dim)
+    assert tg.Pattern(d["conn"], len(d["coords"]), host_only=True).compact_routing() is None
+    _check_p1(d, dtype)
+    _check_p1(d, dtype, form=tg.MASS)
+    # batched members on the wide routing equal single calls bitwise
+    pat = tg.Pattern(d["conn"], len(d["coords"]))
+    coords = torch.from_numpy(d["coords"]).cuda()
+    rng = np.random.default_rng(9)
+    a = torch.from_numpy(np.exp(rng.standard_normal((3, m)))).to(dtype).cuda()
+    f = torch.from_numpy(rng.uniform(-1, 1, (3, m))).to(dtype).cuda()
+    vb, rb = tg.assemble_batched(pat, tg.LAPLACE, coords, a, f)
+    for b in range(3):
+        v, r = tg.assemble(pat, tg.LAPLACE, coords, a[b].contiguous(), f[b].contiguous())
+        assert torch.equal(vb[b], v) and torch.equal(rb[b], r)
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_single_element(dim):
     rng = np.random.default_rng(dim)

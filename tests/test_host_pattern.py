@@ -84,12 +84,39 @@ def test_p1_pattern_routing_equals_oracle(dim, n):
     assert np.all(np.diff(r["seg_ptr"])[np.setdiff1d(np.arange(len(ci)), diag)] > 0)
     vals[diag] = _sequential_segment_sum(Kl[r["inc"] // k, r["inc"] % k, r["inc"] % k], r["inc_ptr"])
     assert np.array_equal(vals, A.vals)  # bitwise
+    # the compact routing the kernel reads names the same slots in the same order
+    assert pat.compact_routing() is not None
+    cvals = _compact_replay(pat, r, Kl, k)
+    cvals[diag] = vals[diag]
+    assert np.array_equal(cvals, A.vals)
     rhs = _sequential_segment_sum(Fl[r["inc"] // k, r["inc"] % k], r["inc_ptr"])
     assert np.array_equal(rhs, A.rhs)
     # pairs ascending by element inside every node
     for i in range(pat.n_nodes):
         seg = r["inc"][r["inc_ptr"][i]:r["inc_ptr"][i + 1]] // k
         assert np.all(np.diff(seg) > 0)
+
+
+def _compact_replay(pat, r, Kl, k):
+    """Decode the one-byte P1 routing (tg_pattern_copy_compact_routing) on its own terms and sum the
+    local matrices through it: entry z of node i sums slot8[start(z) .. start(z+1)), start(z) =
+    inc_ptr[i] (k-1) + (ent16[z] & 255), code c -> pair inc_ptr[i] + c // k, column c % k."""
+    ent, s8 = pat.compact_routing()
+    inc_ptr, inc, node_rp, blk_row = r["inc_ptr"], r["inc"], r["node_rp"], r["blk_row"]
+    vals = np.zeros(len(ent))
+    for b in range(len(blk_row) - 1):
+        for i in range(blk_row[b], blk_row[b + 1]):
+            for z in range(node_rp[i], node_rp[i + 1]):
+                assert ent[z] >> 8 == i - blk_row[b]
+                start = inc_ptr[i] * (k - 1) + (ent[z] & 255)
+                end = inc_ptr[i + 1] * (k - 1) if z + 1 == node_rp[i + 1] else inc_ptr[i] * (k - 1) + (ent[z + 1] & 255)
+                acc = 0.0
+                for g in range(start, end):
+                    t, col = inc_ptr[i] + s8[g] // k, s8[g] % k
+                    assert inc_ptr[i] <= t < inc_ptr[i + 1]
+                    acc += Kl[inc[t] // k, inc[t] % k, col]
+                vals[z] = acc
+    return vals
 
 
 def tg_block_cap(order):
@@ -255,3 +282,27 @@ def test_block_vertex_staging_p2(n):
         assert np.all(loc < np.diff(vptr)[pair_block])
         np.testing.assert_array_equal(vert[vptr[pair_block] + loc], nodes[e, a])
         np.testing.assert_array_equal(nodes[e, a], d["conn"][e, a])
+
+
+def test_p1_wide_routing_for_a_high_valence_node():
+    """A node with more than 256 / k elements keeps the wide (uint16) routing; the routing still
+    replays the oracle bitwise."""
+    m = 100  # fan of m triangles around vertex 0
+    ang = np.linspace(0, 2 * np.pi, m, endpoint=False)
+    coords = np.concatenate([[[0.0, 0.0]], np.stack([np.cos(ang), np.sin(ang)], 1)])
+    conn = np.array([[0, 1 + i, 1 + (i + 1) % m] for i in range(m)], dtype=np.int32)
+    a = np.exp(np.random.default_rng(0).standard_normal(m))
+    f = np.random.default_rng(1).uniform(-1, 1, m)
+    pat = tg.Pattern(conn, m + 1, host_only=True)
+    assert pat.compact_routing() is None
+    r = pat.routing()
+    A = oracle.assemble_p1(coords, conn, a, f)
+    Kl = np.stack([oracle.p1_laplace_element(coords[g], a[e], f[e])[0] for e, g in enumerate(conn)])
+    pair, b = _pair_of_slot(r, 3)
+    code = r["inc"][pair]
+    vals = _sequential_segment_sum(Kl[code // 3, code % 3, b], r["seg_ptr"])
+    rp, ci = pat.csr()
+    node_of_entry = np.repeat(np.arange(pat.n_nodes), np.diff(rp))
+    diag = np.flatnonzero(ci == node_of_entry)
+    vals[diag] = _sequential_segment_sum(Kl[r["inc"] // 3, r["inc"] % 3, r["inc"] % 3], r["inc_ptr"])
+    assert np.array_equal(vals, A.vals)
