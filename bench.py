@@ -251,7 +251,8 @@ def main():
     bmin32, balg32 = p1_bytes(nv, 3, E, pat.nnz, pat.n_dofs, 4, 2)
     mean_asm = float(t_asm.mean())
     gbs = balg64 / mean_asm / 1e9
-    traffic = stored_traffic("p1_assemble_kernel<3,double,0,true,false>")
+    routing = "true" if pat.compact_routing() is not None else "false"  # the kernel instance the pattern selects
+    traffic = stored_traffic(f"p1_assemble_kernel<3,double,0,true,false,{routing}>")
 
     out = {
         "metric": METRIC,
