@@ -4,7 +4,7 @@
 // One workgroup owns a block of consecutive CSR node rows.  Work inside it:
 //   Stage  : the distinct vertices of the block's elements (a list built with
 //            the pattern) are copied into LDS once.
-//   Map    : one lane (P1; 8 lanes for P2) per (row node i, element e, local
+//   Map    : one lane (P1; 5 lanes for P2) per (row node i, element e, local
 //            node a) pair of the block.  It reads e's vertices from LDS, forms
 //            J, |det J| and the cofactors of J in FP64 (Alg. 1 Geometry),
 //            pushes the reference gradients forward (Push-forward), evaluates
@@ -525,7 +525,9 @@ void p1_assemble_kernel(
 
 // ---------------------------------------------------------------- P2 elasticity
 
-constexpr int kP2LanesPerPair = 8;
+// Lanes per P2 pair: 5 lanes with two of the 10 column nodes each (every lane
+// repeats the pair's geometry, so fewer lanes with balanced work beat 8 or 10).
+constexpr int kP2LanesPerPair = 5;
 
 // Vertices (i, j) of P2 local node n (vertices 0..3, then edges (0,1),(0,2),(0,3),
 // (1,2),(1,3),(2,3)); a vertex node has i = j = n.
@@ -637,6 +639,10 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
         const T lam = (T)lam_d, mu = (T)mu_d;
         T ga[4][3];
         p2_node_grads<T>(a, g, ga);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ga[q][c] = w * ga[q][c];  // the weight, once (same products as before)
         for (int b = sub; b < K; b += kP2LanesPerPair) {
             // D_ab = sum_q w_q |det J| grad(phi_a) grad(phi_b)^T
             T gb[4][3];
@@ -647,7 +653,7 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
-                    for (int cc = 0; cc < 3; ++cc) Dm[c][cc] += w * ga[q][c] * gb[q][cc];
+                    for (int cc = 0; cc < 3; ++cc) Dm[c][cc] += ga[q][c] * gb[q][cc];
             // Hooke: block[c][c'] = lam D[c][c'] + mu (D[c'][c] + delta_cc' tr D)
             const T tr = Dm[0][0] + Dm[1][1] + Dm[2][2];
             T *dst = L.K + (b * np + t) * 9;

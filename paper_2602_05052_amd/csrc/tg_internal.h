@@ -19,8 +19,8 @@ constexpr int kP1Threads = 256;
 constexpr int kP1BlockTarget = 256;
 constexpr int kP1BlockCap = 512;
 constexpr int kP1BlockVerts = 256;  // distinct vertices of a block (8-bit local ids)
-constexpr int kP2Threads = 256;
-constexpr int kP2BlockTarget = 32;
+constexpr int kP2Threads = 192;
+constexpr int kP2BlockTarget = 38;
 constexpr int kP2BlockCap = 64;
 constexpr int kBlkDesc = 12;  // ints per row-block descriptor
 // Largest pair count of a row for the compact P1 routing: its one-byte
