@@ -16,6 +16,11 @@
 //
 // Admission: a request enters when its group has a free slot, or when one more
 // slot fits in the server's HBM budget and under the per-group slot limit.
+//
+// Each group runs on a stream of its own (default priority), forked from the
+// caller's stream at the start of a scheduling round and joined back before
+// the round's synchronisation, so the launches of groups on different patterns
+// (often small, latency-bound systems) overlap on the GPU.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -63,6 +68,12 @@ struct Group {
     int32_t *d_lists = nullptr, *h_lists = nullptr;  // [active | fresh | finished], max_slots each
     int step = 0;
     size_t slot_bytes = 0;
+    hipStream_t stream = nullptr;  // the group's own stream
+    hipEvent_t joined = nullptr;   // recorded on it at the end of a round
+    // retirement in flight between the launch and the finish phase of a round
+    std::vector<int> fin, keep;
+    std::vector<double> parts;
+    int n_parts = 0;
 };
 
 double now_s() {
@@ -74,6 +85,7 @@ double now_s() {
 
 struct tg_server {
     hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr;  // recorded on `stream` at the start of a round
     size_t budget = 0, used = 0;
     int max_slots = 1;
     int check_every = 1;
@@ -103,6 +115,8 @@ void free_group(Group &g) {
     (void)hipHostFree(g.h_states);
     (void)hipHostFree(g.h_status);
     (void)hipHostFree(g.h_lists);
+    if (g.joined) (void)hipEventDestroy(g.joined);
+    if (g.stream) (void)hipStreamDestroy(g.stream);
 }
 
 tg_status hip_fail(hipError_t e, const char *what) {
@@ -132,6 +146,8 @@ tg_status make_group(tg_server *srv, const tg_pattern *p, tg_dtype dtype, Group 
     if (e == hipSuccess) e = hipHostMalloc((void **)&g->h_states, S * sizeof(PcgState), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&g->h_status, S * sizeof(int32_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&g->h_lists, 3 * S * sizeof(int32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&g->joined, hipEventDisableTiming);
     if (e != hipSuccess) {
         free_group(*g);
         return hip_fail(e, "server group allocation failed");
@@ -210,7 +226,7 @@ tg_status admit(tg_server *srv, Group &g, std::vector<int> &fresh) {
         it = srv->queue.erase(it);
     }
     if (fresh.empty()) return TG_OK;
-    const hipStream_t str = srv->stream;
+    const hipStream_t str = g.stream;
     const int S = g.max_slots;
     for (int s : fresh) g.active.push_back(s);
     for (size_t i = 0; i < g.active.size(); ++i) g.h_lists[i] = g.active[i];
@@ -238,40 +254,51 @@ tg_status admit(tg_server *srv, Group &g, std::vector<int> &fresh) {
     return TG_OK;
 }
 
-// Retire the finished systems of g (states already copied to the host and synchronised).
-tg_status retire(tg_server *srv, Group &g) {
+// Retirement, phase 1 (states already copied to the host and synchronised):
+// pick the finished systems of g and enqueue their true-residual partials and
+// the new active list on the group's stream.
+tg_status retire_launch(Group &g) {
     const int S = g.max_slots;
-    std::vector<int> fin, keep;
+    g.fin.clear();
+    g.keep.clear();
+    g.n_parts = 0;
     for (int s : g.active) {
         const PcgState &st = g.h_states[s];
         const int it = g.step - g.h_slots[s].start;
-        if (st.done || it > g.h_slots[s].max_iter) fin.push_back(s);
-        else keep.push_back(s);
+        if (st.done || it > g.h_slots[s].max_iter) g.fin.push_back(s);
+        else g.keep.push_back(s);
     }
-    if (fin.empty()) return TG_OK;
-    const hipStream_t str = srv->stream;
+    if (g.fin.empty()) return TG_OK;
+    const hipStream_t str = g.stream;
     // The pinned lists are rewritten here only after a synchronisation, and the
-    // copies below complete before this function returns.
-    for (size_t i = 0; i < keep.size(); ++i) g.h_lists[i] = keep[i];
-    for (size_t i = 0; i < fin.size(); ++i) g.h_lists[2 * S + i] = fin[i];
+    // copies below complete before the round's finish phase.
+    for (size_t i = 0; i < g.keep.size(); ++i) g.h_lists[i] = g.keep[i];
+    for (size_t i = 0; i < g.fin.size(); ++i) g.h_lists[2 * S + i] = g.fin[i];
     int ns = 0;
-    hipError_t e = hipMemcpyAsync(g.d_lists + 2 * S, g.h_lists + 2 * S, fin.size() * sizeof(int32_t),
+    hipError_t e = hipMemcpyAsync(g.d_lists + 2 * S, g.h_lists + 2 * S, g.fin.size() * sizeof(int32_t),
                                   hipMemcpyHostToDevice, str);
     if (e == hipSuccess)
-        e = tg::launch_pcg_residual(*g.p, g.dtype, g.d_slots, g.d_lists + 2 * S, (int)fin.size(), &ns, str);
-    std::vector<double> parts(fin.size() * (size_t)std::max(ns, 1));
-    for (size_t i = 0; i < fin.size() && e == hipSuccess; ++i)
-        e = hipMemcpyAsync(parts.data() + i * ns, g.mem[fin[i]].partials + (size_t)tg::kResid * tg::kMaxGrid,
+        e = tg::launch_pcg_residual(*g.p, g.dtype, g.d_slots, g.d_lists + 2 * S, (int)g.fin.size(), &ns, str);
+    g.n_parts = ns;
+    g.parts.assign(g.fin.size() * (size_t)std::max(ns, 1), 0.0);
+    for (size_t i = 0; i < g.fin.size() && e == hipSuccess; ++i)
+        e = hipMemcpyAsync(g.parts.data() + i * ns, g.mem[g.fin[i]].partials + (size_t)tg::kResid * tg::kMaxGrid,
                            ns * sizeof(double), hipMemcpyDeviceToHost, str);
-    if (e == hipSuccess && !keep.empty())
-        e = hipMemcpyAsync(g.d_lists, g.h_lists, keep.size() * sizeof(int32_t), hipMemcpyHostToDevice, str);
-    if (e == hipSuccess) e = hipStreamSynchronize(str);
+    if (e == hipSuccess && !g.keep.empty())
+        e = hipMemcpyAsync(g.d_lists, g.h_lists, g.keep.size() * sizeof(int32_t), hipMemcpyHostToDevice, str);
     if (e != hipSuccess) return hip_fail(e, "server retirement failed");
-    for (size_t i = 0; i < fin.size(); ++i) {
-        const int s = fin[i];
+    return TG_OK;
+}
+
+// Retirement, phase 2 (the group's stream synchronised): results of the finished systems.
+void retire_finish(tg_server *srv, Group &g) {
+    if (g.fin.empty()) return;
+    const int ns = g.n_parts;
+    for (size_t i = 0; i < g.fin.size(); ++i) {
+        const int s = g.fin[i];
         const PcgState &st = g.h_states[s];
         double rr = 0.0;
-        for (int k = 0; k < ns; ++k) rr += parts[i * ns + k];
+        for (int k = 0; k < ns; ++k) rr += g.parts[i * ns + k];
         const double relres = st.bb > 0.0 ? std::sqrt(rr / st.bb) : std::sqrt(rr);
         tg_status status = st.done ? TG_OK : TG_E_NOCONV;
         int32_t bad = -1;
@@ -282,8 +309,8 @@ tg_status retire(tg_server *srv, Group &g) {
         finish(srv, g.req[s], status, st.done ? st.iters : g.h_slots[s].max_iter, relres, bad);
         g.busy[s] = 0;
     }
-    g.active = keep;
-    return TG_OK;
+    g.active = g.keep;
+    g.fin.clear();
 }
 
 }  // namespace
@@ -299,6 +326,10 @@ tg_status tg_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t c
     tg_server *srv = new (std::nothrow) tg_server;
     if (!srv) return tg::api_fail(TG_E_NOMEM, "out of host memory");
     srv->stream = (hipStream_t)stream;
+    if (hipEventCreateWithFlags(&srv->fork, hipEventDisableTiming) != hipSuccess) {
+        delete srv;
+        return tg::api_fail(TG_E_HIP, "server event creation failed");
+    }
     srv->budget = hbm_budget_bytes;
     srv->max_slots = max_slots;
     srv->check_every = check_every;
@@ -337,37 +368,55 @@ tg_status tg_server_step(tg_server *srv, int32_t *n_active, int32_t *n_queued) {
             if (st != TG_OK) return st;
         }
     }
+    // fork: every group's stream starts after the work already on the caller's stream
+    hipError_t e = hipEventRecord(srv->fork, str);
+    if (e != hipSuccess) return hip_fail(e, "server fork failed");
     bool any = false;
     for (auto &gp : srv->groups) {
         Group &g = *gp;
+        bool waits = false;
+        for (const Request &r : srv->queue) waits = waits || (r.p == g.p && r.dtype == g.dtype);
+        if (g.active.empty() && !waits) continue;
+        e = hipStreamWaitEvent(g.stream, srv->fork, 0);
+        if (e != hipSuccess) return hip_fail(e, "server fork failed");
         std::vector<int> fresh;
         tg_status st = admit(srv, g, fresh);
         if (st != TG_OK) return st;
         if (g.active.empty()) continue;
         any = true;
         for (int k = 0; k < srv->check_every; ++k) {
-            const hipError_t e =
-                tg::launch_pcg_step(*g.p, g.dtype, g.d_slots, g.d_lists, (int)g.active.size(), g.step, str);
+            e = tg::launch_pcg_step(*g.p, g.dtype, g.d_slots, g.d_lists, (int)g.active.size(), g.step, g.stream);
             if (e != hipSuccess) return hip_fail(e, "server iteration launch failed");
             ++g.step;
         }
+        e = hipMemcpyAsync(g.h_states, g.d_states, g.mem.size() * sizeof(PcgState), hipMemcpyDeviceToHost,
+                           g.stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(g.h_status, g.d_status, g.mem.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                               g.stream);
+        if (e == hipSuccess) e = hipEventRecord(g.joined, g.stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(str, g.joined, 0);  // join
+        if (e != hipSuccess) return hip_fail(e, "server state copy failed");
     }
     if (any) {
-        for (auto &gp : srv->groups) {
-            Group &g = *gp;
-            if (g.active.empty()) continue;
-            hipError_t e = hipMemcpyAsync(g.h_states, g.d_states, g.mem.size() * sizeof(PcgState),
-                                          hipMemcpyDeviceToHost, str);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(g.h_status, g.d_status, g.mem.size() * sizeof(int32_t), hipMemcpyDeviceToHost, str);
-            if (e != hipSuccess) return hip_fail(e, "server state copy failed");
-        }
-        const hipError_t e = hipStreamSynchronize(str);
+        e = hipStreamSynchronize(str);
         if (e != hipSuccess) return hip_fail(e, "server synchronisation failed");
+        bool retiring = false;
         for (auto &gp : srv->groups) {
             if (gp->active.empty()) continue;
-            const tg_status st = retire(srv, *gp);
+            const tg_status st = retire_launch(*gp);
             if (st != TG_OK) return st;
+            if (!gp->fin.empty()) {
+                retiring = true;
+                e = hipEventRecord(gp->joined, gp->stream);
+                if (e == hipSuccess) e = hipStreamWaitEvent(str, gp->joined, 0);
+                if (e != hipSuccess) return hip_fail(e, "server retirement failed");
+            }
+        }
+        if (retiring) {
+            e = hipStreamSynchronize(str);
+            if (e != hipSuccess) return hip_fail(e, "server retirement failed");
+            for (auto &gp : srv->groups) retire_finish(srv, *gp);
         }
     }
     int32_t act = 0;
@@ -407,7 +456,10 @@ tg_status tg_server_query(const tg_server *srv, tg_server_info *info) {
 void tg_server_destroy(tg_server *srv) {
     if (!srv) return;
     (void)hipStreamSynchronize(srv->stream);
+    for (auto &gp : srv->groups)
+        if (gp->stream) (void)hipStreamSynchronize(gp->stream);
     for (auto &gp : srv->groups) free_group(*gp);
+    if (srv->fork) (void)hipEventDestroy(srv->fork);
     delete srv;
 }
 
