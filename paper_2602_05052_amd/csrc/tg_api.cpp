@@ -41,6 +41,8 @@ void free_device(tg::DevicePattern &d) {
         if (p) (void)hipFree(p);
     if (d.ws) (void)hipFree(d.ws);
     if (d.host_state) (void)hipHostFree(d.host_state);
+    for (hipEvent_t ev : d.poll_ev)
+        if (ev) (void)hipEventDestroy(ev);
     if (d.host_pcg_slot) (void)hipHostFree(d.host_pcg_slot);
     d = tg::DevicePattern{};
 }
@@ -87,7 +89,8 @@ tg_status create_device(tg_pattern &pt) {
         e = hipMalloc((void **)&d.state, sizeof(PcgState));
         bytes += sizeof(PcgState);
     }
-    if (e == hipSuccess) e = hipHostMalloc((void **)&d.host_state, sizeof(PcgState), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&d.host_state, 2 * sizeof(PcgState), hipHostMallocDefault);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&d.poll_ev[k], hipEventDisableTiming);
     if (e == hipSuccess) e = hipHostMalloc((void **)&d.host_pcg_slot, sizeof(PcgSlot), hipHostMallocDefault);
     if (e == hipSuccess) {
         e = hipMalloc((void **)&d.pcg_slot, sizeof(PcgSlot));

@@ -147,7 +147,8 @@ struct DevicePattern {
     int32_t *dir_rows = nullptr; // rows that are constrained or have a constrained column
     int64_t n_dir_rows = 0;
     PcgState *state = nullptr;
-    PcgState *host_state = nullptr;  // pinned mirror
+    PcgState *host_state = nullptr;  // pinned mirrors [2] (the solver polls one while the other fills)
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
     PcgSlot *pcg_slot = nullptr;       // the solo solver's slot (device) ...
     PcgSlot *host_pcg_slot = nullptr;  // ... and its pinned staging copy
     int32_t *pcg_list = nullptr;       // device {0}

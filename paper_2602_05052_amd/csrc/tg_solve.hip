@@ -576,16 +576,26 @@ tg_status run_pcg(const tg_pattern &pt, tg_dtype dtype, const void *values, cons
     TG_CHECK(hipMemcpyAsync(d.state, d.host_state, sizeof(PcgState), hipMemcpyHostToDevice, s));
     TG_CHECK(hipMemcpyAsync(d.pcg_slot, d.host_pcg_slot, sizeof(PcgSlot), hipMemcpyHostToDevice, s));
     TG_CHECK(launch_pcg_init(pt, dtype, d.pcg_slot, d.pcg_list, 1, s));
+    // Iterations go out in chunks of check_every, each followed by a copy of the
+    // state into one of two pinned mirrors and an event.  The host polls a chunk's
+    // state while the next chunk already runs, so the GPU never idles on the
+    // round trip; launches after convergence return at once (the stop test is
+    // taken on the device), so the result is the same as stopping exactly.
     int it = 0;
-    bool done = false;
-    while (it < max_iter && !done) {
-        TG_CHECK(launch_pcg_step(pt, dtype, d.pcg_slot, d.pcg_list, 1, it, s));
-        ++it;
-        if (it % check_every == 0) {
-            TG_CHECK(hipMemcpyAsync(d.host_state, d.state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-            TG_CHECK(hipStreamSynchronize(s));
-            done = d.host_state->done != 0;
+    auto chunk = [&](int buf) -> hipError_t {
+        for (int k = 0; k < check_every && it < max_iter; ++k, ++it) {
+            const hipError_t e = launch_pcg_step(pt, dtype, d.pcg_slot, d.pcg_list, 1, it, s);
+            if (e != hipSuccess) return e;
         }
+        const hipError_t e = hipMemcpyAsync(d.host_state + buf, d.state, sizeof(PcgState), hipMemcpyDeviceToHost, s);
+        return e != hipSuccess ? e : hipEventRecord(d.poll_ev[buf], s);
+    };
+    TG_CHECK(chunk(0));
+    for (int cur = 0;; cur ^= 1) {
+        const bool more = it < max_iter;
+        if (more) TG_CHECK(chunk(cur ^ 1));
+        TG_CHECK(hipEventSynchronize(d.poll_ev[cur]));
+        if (d.host_state[cur].done || !more) break;
     }
     // stop test on the last update (sets done/iters if it converged)
     dispatch(pt, dtype, [&]<typename T, int G>() { launch_check_t<T, G>(pt, d.pcg_slot, d.pcg_list, 1, it, s); });
@@ -597,7 +607,7 @@ tg_status run_pcg(const tg_pattern &pt, tg_dtype dtype, const void *values, cons
                             hipMemcpyDeviceToHost, s));
     TG_CHECK(hipStreamSynchronize(s));
 #undef TG_CHECK
-    done = d.host_state->done != 0;
+    const bool done = d.host_state->done != 0;
     double rr = 0.0;
     for (double v : host_parts) rr += v;
     const double bb = d.host_state->bb;
