@@ -97,7 +97,17 @@ def _fan_inputs(dim, m, seed):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("dim,m", [(2, 100), (3, 80)])
+@pytest.mark.parametrize("dim,m", [(2, 85), (3, 64)])
+def test_p1_compact_routing_at_its_limit(dim, m, dtype):
+    """The largest valence the one-byte routing holds (256 / (dim + 1) elements at a node)."""
+    d = _fan_inputs(dim, m, seed=dim + 10)
+    assert tg.Pattern(d["conn"], len(d["coords"]), host_only=True).compact_routing() is not None
+    _check_p1(d, dtype)
+    _check_p1(d, dtype, form=tg.MASS)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dim,m", [(2, 86), (2, 100), (3, 65), (3, 80)])
 def test_p1_wide_routing_parity(dim, m, dtype):
     """High-valence nodes: the pattern keeps the wide routing (its own kernel instance)."""
     d = _fan_inputs(dim, m, seed=dim)

@@ -306,3 +306,31 @@ def test_p1_wide_routing_for_a_high_valence_node():
     diag = np.flatnonzero(ci == node_of_entry)
     vals[diag] = _sequential_segment_sum(Kl[r["inc"] // 3, r["inc"] % 3, r["inc"] % 3], r["inc_ptr"])
     assert np.array_equal(vals, A.vals)
+
+
+@pytest.mark.parametrize("m,compact", [(64, True), (65, False)])
+def test_p1_compact_routing_limit(m, compact):
+    """3D: two apexes shared by m tets each.  m = 64 = 256 / 4 is the largest valence whose one-byte
+    slot codes ((pair offset) * 4 + b <= 255) fit; one more element switches the pattern to the wide
+    form.  At the limit the compact codes still replay the oracle bitwise."""
+    ang = np.linspace(0, 2 * np.pi, m, endpoint=False)
+    ring = np.stack([np.cos(ang), np.sin(ang), 0.1 * np.sin(3 * ang)], 1)
+    coords = np.ascontiguousarray(np.concatenate([[[0.0, 0.0, -1.0], [0.0, 0.0, 1.0]], ring]))
+    conn = np.array([[0, 2 + i, 2 + (i + 1) % m, 1] for i in range(m)], dtype=np.int32)
+    rng = np.random.default_rng(m)
+    a, f = np.exp(rng.standard_normal(m)), rng.uniform(-1, 1, m)
+    pat = tg.Pattern(conn, m + 2, host_only=True)
+    assert (pat.compact_routing() is not None) == compact
+    if not compact:
+        return
+    ent, s8 = pat.compact_routing()
+    assert s8[:m * 4 * 3].max() == 255  # the apex rows use the full byte range
+    r = pat.routing()
+    A = oracle.assemble_p1(coords, conn, a, f)
+    Kl = np.stack([oracle.p1_laplace_element(coords[g], a[e], f[e])[0] for e, g in enumerate(conn)])
+    vals = _compact_replay(pat, r, Kl, 4)
+    rp, ci = pat.csr()
+    node_of_entry = np.repeat(np.arange(pat.n_nodes), np.diff(rp))
+    diag = np.flatnonzero(ci == node_of_entry)
+    vals[diag] = _sequential_segment_sum(Kl[r["inc"] // 4, r["inc"] % 4, r["inc"] % 4], r["inc_ptr"])
+    assert np.array_equal(vals, A.vals)
