@@ -15,7 +15,8 @@
 //            element slots that the routing table maps to it (the S_mat
 //            projection of Alg. 2), in ascending element order, and writes it
 //            once; one lane per row sums its load contributions (the S_vec
-//            projection).
+//            projection) and, for P1, the row's diagonal entry, whose terms
+//            are exactly the row's pairs in order, so it needs no slots.
 // K_local therefore never leaves the chip, every output is written exactly
 // once, and no atomics touch values: the result is bitwise reproducible and
 // independent of the launch geometry.
