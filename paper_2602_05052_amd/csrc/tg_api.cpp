@@ -440,14 +440,21 @@ hipError_t heat_matrices(const tg_pattern *p, tg_dtype dtype, const double *coor
 }
 
 // One implicit solve A x = rhs on the free DoFs (rhs is zeroed on the constrained ones first).
-tg_status heat_solve(const tg_pattern *p, tg_dtype dtype, const void *vals_a, void *rhs, void *x, double rtol,
-                     int32_t max_iter, int32_t check_every, int64_t &iters, double &worst, hipStream_t s) {
+// x0: the initial guess (the neighbouring step's solution), or NULL for x0 = 0.
+tg_status heat_solve(const tg_pattern *p, tg_dtype dtype, const void *vals_a, void *rhs, void *x, const void *x0,
+                     double rtol, int32_t max_iter, int32_t check_every, int64_t &iters, double &worst,
+                     hipStream_t s) {
+    const size_t bytes = (size_t)p->host.n_dofs * (dtype == TG_F64 ? 8 : 4);
     hipError_t e = tg::launch_dirichlet(*p, dtype, nullptr, rhs, nullptr, s);
-    if (e != hipSuccess) return fail(TG_E_HIP, std::string("dirichlet launch failed: ") + hipGetErrorString(e));
+    if (e == hipSuccess && x0) e = hipMemcpyAsync(x, x0, bytes, hipMemcpyDeviceToDevice, s);
+    // constrained entries of the guess set to their value 0, so that they stay exactly 0
+    if (e == hipSuccess && x0) e = tg::launch_dirichlet(*p, dtype, nullptr, x, nullptr, s);
+    if (e != hipSuccess) return fail(TG_E_HIP, std::string("heat solve setup failed: ") + hipGetErrorString(e));
     int32_t it = 0;
     double rr = 0.0;
     std::string msg;
-    const tg_status st = tg::run_pcg(*p, dtype, vals_a, rhs, x, rtol, max_iter, check_every, &it, &rr, s, msg);
+    const tg_status st =
+        tg::run_pcg(*p, dtype, vals_a, rhs, x, rtol, max_iter, check_every, &it, &rr, s, msg, x0 != nullptr);
     iters += it;
     if (rr > worst) worst = rr;
     if (st != TG_OK) return fail(st, msg);
@@ -510,8 +517,9 @@ tg_status tg_heat_rollout(const tg_pattern *p, tg_dtype dtype, const double *d_c
     for (int32_t k = 0; k < nsteps; ++k) {
         e = tg::launch_spmv(*p, dtype, ws + o_m, states + (size_t)k * n * elt, ws + o_rhs, s);
         if (e != hipSuccess) return fail(TG_E_HIP, std::string("spmv launch failed: ") + hipGetErrorString(e));
-        st = heat_solve(p, dtype, ws + o_a, ws + o_rhs, states + (size_t)(k + 1) * n * elt, rtol, max_iter,
-                        check_every, it, worst, s);
+        // u^k starts the solve for u^{k+1}
+        st = heat_solve(p, dtype, ws + o_a, ws + o_rhs, states + (size_t)(k + 1) * n * elt,
+                        states + (size_t)k * n * elt, rtol, max_iter, check_every, it, worst, s);
         if (st != TG_OK) break;
     }
     if (iters) *iters = it;
@@ -554,7 +562,7 @@ tg_status tg_heat_adjoint(const tg_pattern *p, tg_dtype dtype, const double *d_c
     int64_t it = 0;
     double worst = 0.0;
     // A lambda^N = g;  A lambda^k = M lambda^{k+1}  (A and M symmetric)
-    st = heat_solve(p, dtype, ws + o_a, ws + o_rhs, lam + (size_t)(nsteps - 1) * n * elt, rtol, max_iter,
+    st = heat_solve(p, dtype, ws + o_a, ws + o_rhs, lam + (size_t)(nsteps - 1) * n * elt, nullptr, rtol, max_iter,
                     check_every, it, worst, s);
     for (int32_t k = nsteps - 1; st == TG_OK && k >= 1; --k) {
         e = tg::launch_spmv(*p, dtype, ws + o_m, lam + (size_t)k * n * elt, ws + o_rhs, s);
@@ -562,8 +570,9 @@ tg_status tg_heat_adjoint(const tg_pattern *p, tg_dtype dtype, const double *d_c
             st = fail(TG_E_HIP, std::string("spmv launch failed: ") + hipGetErrorString(e));
             break;
         }
-        st = heat_solve(p, dtype, ws + o_a, ws + o_rhs, lam + (size_t)(k - 1) * n * elt, rtol, max_iter,
-                        check_every, it, worst, s);
+        // lambda^{k+1} starts the solve for lambda^k
+        st = heat_solve(p, dtype, ws + o_a, ws + o_rhs, lam + (size_t)(k - 1) * n * elt, lam + (size_t)k * n * elt,
+                        rtol, max_iter, check_every, it, worst, s);
     }
     if (iters) *iters = it;
     if (relres) *relres = worst;

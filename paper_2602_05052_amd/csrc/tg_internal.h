@@ -113,6 +113,7 @@ struct PcgSlot {
     double rtol2;
     int32_t start;       // launch step of this system's iteration 0 (iteration = step - start)
     int32_t max_iter;    // no update past this iteration (the stop test still runs there)
+    int32_t warm = 0;    // 1: x holds the initial guess and the stop test is relative to ||b||
 };
 
 constexpr int kVecThreads = 1024;  // threads per block of the PCG kernels
@@ -208,7 +209,8 @@ hipError_t launch_assemble(const tg_pattern *p, tg_form form, tg_dtype dtype, in
                            const void *d_coef, const void *d_load, void *d_values, void *d_rhs, int32_t *d_status,
                            hipStream_t s);
 // Runs the whole PCG; returns TG_OK / TG_E_NOCONV / TG_E_HIP with *msg on failure.
+// warm: x holds the initial guess (else x0 = 0); the stop test is ||r|| <= rtol ||b|| either way.
 tg_status run_pcg(const tg_pattern &p, tg_dtype dtype, const void *values, const void *rhs, void *x, double rtol,
                   int32_t max_iter, int32_t check_every, int32_t *iters, double *relres, hipStream_t s,
-                  std::string &msg);
+                  std::string &msg, bool warm = false);
 }  // namespace tg

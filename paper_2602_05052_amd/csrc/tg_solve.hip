@@ -250,6 +250,47 @@ __global__ __launch_bounds__(kVecThreads) void pcg_init_kernel(int n, const PcgS
     }
 }
 
+// Warm start: r = b - K x for the given x, p = 0, s = 0, dinv = 1 / diag
+// (record of parity 0; w follows), and per-block partials of b.b at kResid.
+template <typename T, int G>
+__global__ __launch_bounds__(kVecThreads, 8) void pcg_warm_init_kernel(int n, const int32_t *__restrict__ row_ptr,
+                                                                    const int32_t *__restrict__ col_idx,
+                                                                    const PcgSlot *__restrict__ slots,
+                                                                    const int32_t *__restrict__ diag_pos) {
+    __shared__ double sh[kWaves];
+    const PcgSlot S = *slots;
+    const SlotVecs<T> v(S, n);
+    const TG_GLOBAL T *__restrict__ b = gl((const T *)S.b);
+    const TG_GLOBAL T *__restrict__ values = gl((const T *)S.values);
+    const TG_GLOBAL T *__restrict__ x = gl((const T *)S.x);
+    const int lane = threadIdx.x % G;
+    const int rows_per_grid = gridDim.x * (kVecThreads / G);
+    double bb = 0.0;
+    for (int i = blockIdx.x * (kVecThreads / G) + threadIdx.x / G; i < n; i += rows_per_grid) {
+        const double kx = row_dot<G>(i, lane, row_ptr, col_idx, values, x);
+        if (lane == 0) {
+            const T bi = b[i];
+            v.p[i] = (T)0;
+            store_rec(v.rec0, i, (T)((double)bi - kx), (T)0, (T)0, (T)1 / values[diag_pos[i]]);
+            bb += (double)bi * (double)bi;
+        }
+    }
+    bb = block_sum(bb, sh);
+    if (threadIdx.x == 0) part(S.partials, kResid)[blockIdx.x] = bb;
+}
+
+// Warm start: b.b from the n_prev partials -> state bb and tol2 = rtol^2 b.b.
+__global__ __launch_bounds__(kVecThreads) void pcg_warm_tol_kernel(const PcgSlot *__restrict__ slots, int n_prev) {
+    __shared__ double sh[kWaves];
+    const PcgSlot S = *slots;
+    double bb = (int)threadIdx.x < n_prev ? part(S.partials, kResid)[threadIdx.x] : 0.0;
+    bb = block_sum(bb, sh);
+    if (threadIdx.x == 0) {
+        S.state->bb = bb;
+        S.state->tol2 = S.rtol2 * bb;
+    }
+}
+
 // w_0 = K u_0 with u_0 = dinv r_0, and partials of r.u, w.u, r.r (parity 0).
 // Reads the r and dinv fields of neighbouring records and writes only the w
 // field of its own rows.
@@ -312,7 +353,7 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_iter_kernel(int n, const i
     sum_partials3(part(S.partials, kRr + cur), part(S.partials, kGam + cur), part(S.partials, kDel + cur), n_prev,
                   sh, rr_cur, gam, del);
     double tol2;
-    if (it == 0) {
+    if (it == 0 && !S.warm) {
         tol2 = S.rtol2 * rr_cur;
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             st->bb = rr_cur;
@@ -476,6 +517,17 @@ void launch_init_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *li
 }
 
 template <typename T, int G>
+void launch_warm_init_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *list, hipStream_t s) {
+    const int n = (int)pt.host.n_dofs;
+    const int ns = spmv_blocks<G>(n);
+    hipLaunchKernelGGL((pcg_warm_init_kernel<T, G>), dim3(ns), dim3(kVecThreads), 0, s, n, pt.dev.row_ptr,
+                       pt.dev.col_idx, slots, pt.dev.diag_pos);
+    hipLaunchKernelGGL(pcg_warm_tol_kernel, dim3(1), dim3(kVecThreads), 0, s, slots, ns);
+    hipLaunchKernelGGL((pcg_init_spmv_kernel<T, G>), dim3(ns, 1), dim3(kVecThreads), 0, s, n, pt.dev.row_ptr,
+                       pt.dev.col_idx, slots, list);
+}
+
+template <typename T, int G>
 void launch_step_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *list, int count, int step,
                    hipStream_t s) {
     const int n = (int)pt.host.n_dofs;
@@ -556,7 +608,7 @@ hipError_t launch_pcg_residual(const tg_pattern &p, tg_dtype dtype, const PcgSlo
 
 tg_status run_pcg(const tg_pattern &pt, tg_dtype dtype, const void *values, const void *rhs, void *x, double rtol,
                   int32_t max_iter, int32_t check_every, int32_t *iters, double *relres, hipStream_t s,
-                  std::string &msg) {
+                  std::string &msg, bool warm) {
     const DevicePattern &d = pt.dev;
     hipError_t err;
 #define TG_CHECK(call)                    \
@@ -572,10 +624,15 @@ tg_status run_pcg(const tg_pattern &pt, tg_dtype dtype, const void *values, cons
     // caller may capture this stream.
     d.host_state->done = 0;
     d.host_state->iters = 0;
-    *d.host_pcg_slot = PcgSlot{values, rhs, x, d.work, d.partials, d.state, rtol * rtol, 0, max_iter};
+    *d.host_pcg_slot = PcgSlot{values, rhs, x, d.work, d.partials, d.state, rtol * rtol, 0, max_iter, warm ? 1 : 0};
     TG_CHECK(hipMemcpyAsync(d.state, d.host_state, sizeof(PcgState), hipMemcpyHostToDevice, s));
     TG_CHECK(hipMemcpyAsync(d.pcg_slot, d.host_pcg_slot, sizeof(PcgSlot), hipMemcpyHostToDevice, s));
-    TG_CHECK(launch_pcg_init(pt, dtype, d.pcg_slot, d.pcg_list, 1, s));
+    if (warm) {
+        dispatch(pt, dtype, [&]<typename T, int G>() { launch_warm_init_t<T, G>(pt, d.pcg_slot, d.pcg_list, s); });
+        TG_CHECK(hipGetLastError());
+    } else {
+        TG_CHECK(launch_pcg_init(pt, dtype, d.pcg_slot, d.pcg_list, 1, s));
+    }
     // Iterations go out in chunks of check_every, each followed by a copy of the
     // state into one of two pinned mirrors and an event.  The host polls a chunk's
     // state while the next chunk already runs, so the GPU never idles on the
