@@ -273,7 +273,9 @@ tg_status tg_spmv(const tg_pattern *p, tg_dtype dtype, const void *d_values, con
  * (bitwise reproducible).
  *   d_values, d_rhs : device arrays of dtype (e.g. after tg_apply_dirichlet).
  *   d_x             : device [n_dofs] of dtype, output.
- *   check_every     : iterations between host checks of the stop test (>= 1);
+ *   check_every     : iterations per chunk between host checks of the stop test
+ *                     (>= 1); the host reads one chunk's state while the next
+ *                     chunk runs, launches after convergence do nothing, and
  *                     the iteration count reported is exact regardless.
  *   iters, relres   : host outputs: iterations done, and the final TRUE
  *                     relative residual ||b - K x|| / ||b|| (eq. linres).
@@ -322,7 +324,9 @@ tg_status tg_adjoint_p1(const tg_pattern *p, tg_form form, tg_dtype dtype, int32
  * on the pattern's constrained DoFs:
  *     (M + dt K(a)) u^{k+1} = M u^k on the free DoFs,  k = 0 .. nsteps-1,
  * with a_e = exp(log_a_e).  Per step: one SpMV with M, then Jacobi-PCG on
- * A = M + dt K(a) (both assembled once per call by the Map-Reduce kernels).
+ * A = M + dt K(a) (both assembled once per call by the Map-Reduce kernels),
+ * started from u^k (its constrained entries set to 0); the stop test is
+ * ||r|| <= rtol ||M u^k|| as in tg_pcg.
  *   d_coords  : device FP64 [n_vertices][dim].   d_log_a : device FP64 [n_elements].
  *   d_u0      : device [n_dofs] of dtype (entries on constrained DoFs enter M u^0).
  *   d_states  : device [nsteps+1][n_dofs] of dtype, out: row k = u^k (row 0 = u^0).
@@ -344,7 +348,8 @@ tg_status tg_heat_rollout(const tg_pattern *p, tg_dtype dtype, const double *d_c
  *     A lam^N = g,   A lam^k = M lam^{k+1}  (k = N-1 .. 1)   on the free DoFs,
  *     dL/dtheta = -sum_k d/dtheta [lam^k^T (A u^k - M u^{k-1})],
  * evaluated by tg_adjoint_p1 over the N (lam^k, u^k, u^{k-1}) triples in one
- * launch, and dL/du^0 = M lam^1.
+ * launch, and dL/du^0 = M lam^1.  The solve for lam^k starts from lam^{k+1}
+ * (lam^N from 0).
  *   d_states    : the rollout's [nsteps+1][n_dofs] of dtype (read only).
  *   d_g         : device [n_dofs] of dtype.
  *   d_dlog_a    : device FP64 [n_elements] out, dL/d(log a_e), or NULL.
@@ -365,8 +370,9 @@ tg_status tg_heat_adjoint(const tg_pattern *p, tg_dtype dtype, const double *d_c
  * A request = assemble (tg_assemble's forms except TG_MASS), eliminate
  * Dirichlet data (tg_apply_dirichlet, with d_g or g = 0), and solve with
  * Jacobi-PCG (tg_pcg).  Requests are grouped by (pattern, dtype); a group keeps
- * up to max_slots systems in one batched CG (one launch pair per iteration for
- * the whole group).  Each tg_server_step admits queued requests into free
+ * up to max_slots systems in one batched CG (one launch per iteration for the
+ * whole group; each group on its own stream, forked from and joined back to
+ * `stream` in every tg_server_step).  Each tg_server_step admits queued requests into free
  * slots (a slot is allocated when the server's HBM budget allows), runs
  * check_every CG iterations, then retires the converged systems (or those at
  * max_iter).  A request's solution and iteration count are bitwise the same as
