@@ -45,6 +45,13 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def stats_us(t):
+    """mean / median / p90 of a sample of durations in seconds, in microseconds."""
+    import numpy as np
+    return {"mean": float(np.mean(t)) * 1e6, "p50": float(np.median(t)) * 1e6,
+            "p90": float(np.percentile(t, 90)) * 1e6, "samples": int(len(t))}
+
+
 def kernel_key(name: str) -> str:
     """'void tg::(anonymous namespace)::p1_assemble_kernel<3, double, 0, true, false>(...)' ->
     'p1_assemble_kernel<3,double,0,true,false>'."""
@@ -117,8 +124,8 @@ def p1_bytes(nv, dim, E, nnz, ndof, s, n_coef):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=64, help="grid cells per axis (64 = the benchmark mesh)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (profiling runs)")
@@ -132,7 +139,9 @@ def main():
     ap.add_argument("--batch", type=int, default=8, help="coefficient sets for --workload batched")
     ap.add_argument("--requests", type=int, default=64, help="requests for --workload serve")
     ap.add_argument("--slots", type=int, default=16, help="slots per group for --workload serve")
-    ap.add_argument("--rate", type=float, default=400.0, help="request arrivals per second for --workload serve")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="request arrivals per second for --workload serve (0: 0.5x and 0.8x of saturation)")
+    ap.add_argument("--budget-gib", type=float, default=8.0, help="server HBM budget for --workload serve")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc runs of this script and exit")
     args = ap.parse_args()
@@ -238,9 +247,12 @@ def main():
         torch.cuda.synchronize()
         return np.array([e0.elapsed_time(e1) for e0, e1 in evs]) * 1e-3
 
-    t64_warm = time_kernel(assemble64, 20, cold=False)
-    t32_cold = time_kernel(assemble32, 20, cold=True)
-    t32_warm = time_kernel(assemble32, 20, cold=False)
+    t64_warm = time_kernel(assemble64, 50, cold=False)
+    t32_cold = time_kernel(assemble32, 50, cold=True)
+    t32_warm = time_kernel(assemble32, 50, cold=False)
+    # attainable HBM bandwidth: the 1 GiB read-modify-write of the flush (2 GiB moved per launch)
+    t_copy = time_kernel(lambda: flush.add_(1.0), 10, cold=False)
+    attainable_gbs = 2.0 * flush.numel() * 4 / float(np.median(t_copy)) / 1e9
     # bitwise repeatability of the FP64 assembly
     ref_vals = vals.clone()
     assemble64()
@@ -279,12 +291,13 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": balg64, "bytes_per_element": balg64 / E,
             "b_min_bytes_per_launch": bmin64,
+            "attainable_gbs": attainable_gbs, "frac_of_attainable": gbs / attainable_gbs,
         },
         "assembly": {
-            "fp64_cold_us": {"mean": mean_asm * 1e6, "p50": float(np.median(t_asm)) * 1e6},
-            "fp64_warm_us": {"mean": float(t64_warm.mean()) * 1e6, "p50": float(np.median(t64_warm)) * 1e6},
-            "fp32_cold_us": {"mean": float(t32_cold.mean()) * 1e6, "p50": float(np.median(t32_cold)) * 1e6},
-            "fp32_warm_us": {"mean": float(t32_warm.mean()) * 1e6, "p50": float(np.median(t32_warm)) * 1e6},
+            "fp64_cold_us": stats_us(t_asm),
+            "fp64_warm_us": stats_us(t64_warm),
+            "fp32_cold_us": stats_us(t32_cold),
+            "fp32_warm_us": stats_us(t32_warm),
             "fp64_elements_per_s": E / mean_asm,
             "fp32_elements_per_s": E / float(t32_cold.mean()),
             "fp64_gbs_b_alg": gbs, "fp32_gbs_b_alg": balg32 / float(t32_cold.mean()) / 1e9,
@@ -565,12 +578,14 @@ def run_batched(args, dev):
 
 
 def run_serve(args, dev):
-    """Served assemble+solve stream: requests arrive as a Poisson process at --rate per second; each is a
-    Poisson problem on its own jittered 2D P1 (1k-500k triangles) or 3D P1 (6k-1.5M tets) mesh whose
-    element count is log-uniform, with lognormal a and f = U(-1,1), FP32 assembly + Dirichlet + Jacobi-PCG
-    to 1e-6.  Mesh topologies come from a catalogue of 6 sizes per dimension whose CSR patterns are built
-    before the run and stay resident; the vertex jitter and the coefficients differ per request.  The
-    continuous-batching server is timed against the same arrivals served one at a time."""
+    """Served assemble+solve stream: each request is a Poisson problem on its own jittered 2D P1 (1k-500k
+    triangles) or 3D P1 (6k-1.5M tets) mesh whose element count is log-uniform, with lognormal a and
+    f = U(-1,1), FP32 assembly + Dirichlet + Jacobi-PCG to 1e-6.  Mesh topologies come from a catalogue of 6
+    sizes per dimension whose CSR patterns are built before the stream and stay resident; the vertex jitter
+    and the coefficients differ per request.  First all requests arrive at once (saturation throughput),
+    then as a Poisson process at 0.5x and 0.8x of the served saturation rate (or at --rate); the
+    continuous-batching server (HBM budget --budget-gib, so admission binds) is timed against the same
+    arrivals served one at a time."""
     import numpy as np
     import torch
 
@@ -596,13 +611,13 @@ def run_serve(args, dev):
         m = meshgen.poisson_inputs(key[0], key[1], seed=1000 + i)
         reqs.append((key, torch.from_numpy(m["coords"]).to(dev), torch.from_numpy(m["a"]).float().to(dev),
                      torch.from_numpy(m["f"]).float().to(dev)))
-    arrive = np.cumsum(rng.exponential(1.0 / args.rate, R))
+    gaps = rng.exponential(1.0, R)  # unit-rate gaps, scaled per arrival rate
     xs = [torch.empty(pats[r[0]].n_dofs, dtype=torch.float32, device=dev) for r in reqs]
     s = torch.cuda.Stream(device=dev)
     rtol = 1e-6
     print(f"# serve: {R} requests on catalogue {cat}", file=sys.stderr, flush=True)
 
-    def sequential():
+    def sequential(arrive):
         lat, its = [], 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -618,9 +633,9 @@ def run_serve(args, dev):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, np.array(lat), its
 
-    srv = tg.Server(hbm_budget=32 << 30, max_slots=args.slots, check_every=10, stream=s)
+    srv = tg.Server(hbm_budget=int(args.budget_gib * (1 << 30)), max_slots=args.slots, check_every=10, stream=s)
 
-    def served():  # slots stay allocated across calls: the warm-up call pays for them
+    def served(arrive):  # slots stay allocated across calls: the warm-up call pays for them
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         nxt, lat, arr = 0, [], {}
@@ -639,24 +654,35 @@ def run_serve(args, dev):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, np.array(lat)
 
-    sequential()  # warm-up: code paths, slot allocation
-    served()
-    t_seq, lat_seq, its = sequential()
-    ref = [x.clone() for x in xs]
-    t_srv, lat_srv = served()
-    same = all(torch.equal(a, b) for a, b in zip(ref, xs))
-
     def pct(v):
         return {"p50": float(np.percentile(v, 50)) * 1e3, "p99": float(np.percentile(v, 99)) * 1e3}
 
-    out = {"workload": f"served stream: {R} requests, Poisson arrivals at {args.rate:g}/s, jittered 2D P1 "
-                       f"1k-500k triangles and 3D P1 6k-1.5M tets (log-uniform sizes on the (dim, n) catalogue "
-                       f"{cat}), lognormal a, f=U(-1,1), FP32 assembly + Dirichlet + Jacobi-PCG to {rtol:g}",
-           "requests": R, "rate_per_s": args.rate, "slots_per_group": args.slots,
-           "elements_total": int(sum(elems[r[0]] for r in reqs)),
-           "served_requests_per_s": R / t_srv, "sequential_requests_per_s": R / t_seq,
-           "speedup": t_seq / t_srv, "served_latency_ms": pct(lat_srv), "sequential_latency_ms": pct(lat_seq),
-           "pcg_iterations_total": int(its), "bitwise_equal_to_sequential": bool(same)}
+    burst = np.zeros(R)
+    sequential(burst)  # warm-up: code paths, slot allocation
+    served(burst)
+    t_seq, lat_seq, its = sequential(burst)
+    ref = [x.clone() for x in xs]
+    t_srv, lat_srv = served(burst)
+    same = all(torch.equal(a, b) for a, b in zip(ref, xs))
+    sat = R / t_srv
+    rates = [args.rate] if args.rate > 0 else [0.5 * sat, 0.8 * sat]
+    legs = []
+    for rate in rates:
+        arrive = np.cumsum(gaps / rate)
+        ts, ls, _ = sequential(arrive)
+        tv, lv = served(arrive)
+        same = same and all(torch.equal(a, b) for a, b in zip(ref, xs))
+        legs.append({"rate_per_s": rate, "served_requests_per_s": R / tv, "sequential_requests_per_s": R / ts,
+                     "served_latency_ms": pct(lv), "sequential_latency_ms": pct(ls)})
+    out = {"workload": f"served stream: {R} requests, jittered 2D P1 1k-500k triangles and 3D P1 6k-1.5M tets "
+                       f"(log-uniform sizes on the (dim, n) catalogue {cat}), lognormal a, f=U(-1,1), FP32 assembly "
+                       f"+ Dirichlet + Jacobi-PCG to {rtol:g}; all at once, then Poisson arrivals",
+           "requests": R, "slots_per_group": args.slots, "hbm_budget_gib": args.budget_gib,
+           "elements_total": int(sum(elems[r[0]] for r in reqs)), "pcg_iterations_total": int(its),
+           "saturation": {"served_requests_per_s": sat, "sequential_requests_per_s": R / t_seq,
+                          "speedup": t_seq / t_srv, "served_latency_ms": pct(lat_srv),
+                          "sequential_latency_ms": pct(lat_seq)},
+           "poisson_arrivals": legs, "bitwise_equal_to_sequential": bool(same)}
     print(json.dumps(out))
 
 
