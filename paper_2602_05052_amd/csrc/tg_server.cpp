@@ -220,7 +220,7 @@ tg_status admit(tg_server *srv, Group &g, std::vector<int> &fresh) {
         const SlotMem &m = g.mem[s];
         g.h_slots[s] = PcgSlot{m.values, m.b, it->x, m.work, m.partials, g.d_states + s, it->rtol * it->rtol,
                                g.step, it->max_iter};
-        g.h_states[s] = PcgState{0.0, 0.0, 0.0, 0, 0};
+        g.h_states[s] = PcgState{};  // all zero: not done, no iterations
         g.h_status[s] = TG_STATUS_CLEAN;
         fresh.push_back(s);
         it = srv->queue.erase(it);
