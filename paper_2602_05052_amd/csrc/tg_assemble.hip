@@ -299,6 +299,9 @@ struct P1Lds {
     }
 };
 
+// Descriptor prefetch distance, in blocks (see p1_assemble_kernel).
+constexpr int kP1DescAhead = 256;
+
 // Minimum waves per SIMD the register allocation must allow: 8 for the
 // single-set Laplace kernels (they fit in 64 VGPRs without spilling), 7 for the
 // mass forms, 5 (Laplace) or 4 (mass forms) for the batched kernels (they keep
@@ -398,6 +401,11 @@ void p1_assemble_kernel(
     const int a = (int)(code - e * K);
     T c_next = COEF ? ldg(coef, e) : (T)1;  // member 0's coefficients (then each next member's)
     T f_next = LOAD ? ldg(load, e) : (T)0;
+    // Bring into L2 the descriptor of the block that starts on this XCD about one
+    // round of workgroups later (32 CUs x 8 resident blocks), so that its first,
+    // dependent load hits: a vector load issued after this block's own loads and
+    // consumed only at the end.
+    const int pf_desc = ldg(blk_desc, (unsigned)(min(blk + kP1DescAhead, nblk - 1) * kBlkDesc + (tid & 7)));
 
     // ---- staged vertex and routing -> LDS, also without branches: a thread past
     // the end of a list writes the last element's value to the last element's
@@ -522,6 +530,7 @@ void p1_assemble_kernel(
         }
         if (m + 1 < nmem) __syncthreads();  // LDS is rewritten by the next member
     }
+    asm volatile("" ::"v"(pf_desc));  // keeps the prefetch (its value is not needed)
 }
 
 // ---------------------------------------------------------------- P2 elasticity
