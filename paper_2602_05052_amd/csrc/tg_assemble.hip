@@ -301,6 +301,7 @@ struct P1Lds {
 
 // Descriptor prefetch distance, in blocks (see p1_assemble_kernel).
 constexpr int kP1DescAhead = 256;
+constexpr int kP2DescAhead = 128;  // about one round of P2 workgroups on an XCD
 
 // Minimum waves per SIMD the register allocation must allow: 8 for the
 // single-set Laplace kernels (they fit in 64 VGPRs without spilling), 7 for the
@@ -537,8 +538,6 @@ void p1_assemble_kernel(
 
 // Lanes per P2 pair: 5 lanes with two of the 10 column nodes each (every lane
 // repeats the pair's geometry, so fewer lanes with balanced work beat 8 or 10).
-constexpr int kP2LanesPerPair = 5;
-
 // Vertices (i, j) of P2 local node n (vertices 0..3, then edges (0,1),(0,2),(0,3),
 // (1,2),(1,3),(2,3)); a vertex node has i = j = n.
 __device__ __forceinline__ void p2_node(int n, int &i, int &j) {
@@ -576,6 +575,82 @@ __device__ __forceinline__ void p2_node_grads(int n, const T (&g)[4][3], T (&out
     }
 }
 
+// The 3x3 blocks (a, b) of one pair's element row, Hooke's law (Sec. B.1.1):
+//   block[c][c'] = lam D[c][c'] + mu (D[c'][c] + delta_cc' tr D),
+//   D = sum_q w_q |det J| grad(phi_a)(x_q) grad(phi_b)(x_q)^T  (Keast 4-point rule).
+// grad(phi_b) is written through the barycentric gradients g_v: vertex b:
+// (4 lambda_b - 1) g_b; edge (i, j): 4 lambda_j g_i + 4 lambda_i g_j.  With
+// ga_q = w_q |det J| grad(phi_a)(x_q) and lambda_v(x_q) = lo + (hi - lo) [q == v],
+// sum_q lambda_v(x_q) ga_q = lo S + (hi - lo) ga_v with S = sum_q ga_q, so
+//   vertex b:   D = ((4 lo - 1) S + 4 (hi - lo) ga_b) g_b^T
+//   edge (i,j): D = (4 lo S + 4 (hi - lo) ga_j) g_i^T + (4 lo S + 4 (hi - lo) ga_i) g_j^T
+// (the same sums as sum_q ga_q gb_q^T, grouped by barycentric gradient).
+template <typename T>
+struct P2Row {
+    T g[4][3];        // grad(lambda_v), v = 0..3
+    T lam, mu;        // Lame coefficients of the element
+    T P[4][3];        // 4 (hi - lo) ga_v
+    T S0[3], S1[3];   // 4 lo S and (4 lo - 1) S
+
+    __device__ __forceinline__ void init(int a, T w) {
+        using R = Deg2Rule<3>;
+        T ga[4][3];
+        p2_node_grads<T>(a, g, ga);
+        T S[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            S[c] = (T)0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                ga[q][c] = w * ga[q][c];
+                S[c] += ga[q][c];
+            }
+        }
+        const T k4 = (T)(4.0 * (R::hi - R::lo)), l4 = (T)(4.0 * R::lo), l41 = (T)(4.0 * R::lo - 1.0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) P[q][c] = k4 * ga[q][c];
+            S0[c] = l4 * S[c];
+            S1[c] = l41 * S[c];
+        }
+    }
+
+    // Writes block (a, B) to dst[B * cs .. + 9) (row-major 3x3).
+    template <int B>
+    __device__ __forceinline__ void block(T *dst, int cs) const {
+        T D[3][3];
+        if constexpr (B < 4) {
+            T h[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) h[c] = S1[c] + P[B][c];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) D[c][cc] = h[c] * g[B][cc];
+        } else {
+            constexpr int i = B < 7 ? 0 : (B < 9 ? 1 : 2);
+            constexpr int j = B == 4 ? 1 : ((B == 5 || B == 7) ? 2 : 3);
+            T hi[3], hj[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                hi[c] = S0[c] + P[j][c];
+                hj[c] = S0[c] + P[i][c];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) D[c][cc] = hi[c] * g[i][cc] + hj[c] * g[j][cc];
+        }
+        const T tr = D[0][0] + D[1][1] + D[2][2];
+        T *o = dst + B * cs;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) o[c * 3 + cc] = lam * D[c][cc] + mu * (D[cc][c] + (c == cc ? tr : (T)0));
+    }
+};
+
 // int over the reference tetrahedron of phi_n (degree-2 rule; exact).
 __device__ __forceinline__ double p2_ref_integral(int n) {
     using R = Deg2Rule<3>;
@@ -606,8 +681,11 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     extern __shared__ __align__(16) unsigned char smem[];
     BlockLds<T> L(smem, mp, me, 9 * K, 3);
     double *Lx = reinterpret_cast<double *>(smem + VertLds<3>::offset(BlockLds<T>::bytes(mp, me, 9 * K, 3, K)));
-    __shared__ int sRp[kP2BlockCap + 1];
+    __shared__ int sRp[kP2BlockCap + 1];  // row starts in the block's node-level entries
+    __shared__ int sIp[kP2BlockCap + 1];  // row starts in the block's pairs
 
+    static_assert(kP2Threads == 3 * 64, "one wave per set of column nodes");
+    static_assert(kP2BlockCap <= 64, "one lane per pair in each wave");
     const int blk = xcd_swizzle(blockIdx.x, nblk);
     const int4 dsc = ldg(reinterpret_cast<const int4 *>(blk_desc), 3u * blk);
     const int4 dsv = ldg(reinterpret_cast<const int4 *>(blk_desc), 3u * blk + 1u);
@@ -615,74 +693,115 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     const int np = q1 - q0, nent = rp1 - rp0, nvb = w1 - w0;
     const int nrows = r1 - r0;
     const int s0 = q0 * K;
-    for (int r = threadIdx.x; r <= nrows; r += kP2Threads) sRp[r] = node_rp[r0 + r] - rp0;
-    for (int t = threadIdx.x; t <= nent; t += kP2Threads) L.seg[t] = seg_ptr[rp0 + t] - s0;
-    for (int t = threadIdx.x; t < np * K / 2; t += kP2Threads)  // s0 and np K are even: 4-byte copies
-        reinterpret_cast<uint32_t *>(L.slot)[t] = reinterpret_cast<const uint32_t *>(slot + s0)[t];
-    for (int t = threadIdx.x; t < nvb * 3; t += kP2Threads) {  // one coordinate per lane
-        const int l = t / 3, c = t - 3 * l;
-        Lx[l * VS + c] = ldg(coords, 3u * (unsigned)ldg(blk_vert, (unsigned)(w0 + l)) + (unsigned)c);
+    const int tid = threadIdx.x, lane = tid & 63;
+
+    if (np == 0) {  // rows of nodes that belong to no element: no values, zero loads
+        if (rhs && load)
+            for (int u = tid; u < 3 * nrows; u += kP2Threads) rhs[3 * (size_t)r0 + u] = (T)0;
+        return;
+    }
+
+    // ---- Every load that needs only the block descriptor, issued back to back
+    // with clamped (always valid) indices and no branches, so that their
+    // latencies overlap: the pair of this lane (code, local vertex ids), a row's
+    // two offsets (entries, pairs), two segment starts, two 2-slot units of the routing and the vertex
+    // this thread stages; then the loads that need one of them (coordinates,
+    // coefficients, body force).  Two memory latencies in all for blocks of at
+    // most 2 kP2Threads - 1 entries and kP2Threads vertices.
+    const int nsu = np * K / 2;  // s0 and np K are even: 4-byte units of two slots
+    const uint32_t *__restrict__ slot_u = reinterpret_cast<const uint32_t *>(slot + s0);
+    const int tp = min(lane, np - 1);
+    const int code = ldg(inc, (unsigned)(q0 + tp));
+    const uint32_t lv = ldg(pair_lv, (unsigned)(q0 + tp));
+    const int rp_reg = ldg(node_rp, (unsigned)(r0 + min(tid, nrows)));
+    const int ip_reg = ldg(inc_ptr, (unsigned)(r0 + min(tid, nrows)));
+    const int sg_a = ldg(seg_ptr, (unsigned)(rp0 + min(tid, nent)));
+    const int sg_b = ldg(seg_ptr, (unsigned)(rp0 + min(tid + kP2Threads, nent)));
+    const uint32_t su_a = ldg(slot_u, (unsigned)min(tid, nsu - 1));
+    const uint32_t su_b = ldg(slot_u, (unsigned)min(tid + kP2Threads, nsu - 1));
+    const unsigned vid = (unsigned)ldg(blk_vert, (unsigned)(w0 + min(tid, nvb - 1)));
+    const int e = code / K, a = code - e * K;
+    const T lam_t = ldg(coef, (unsigned)e), mu_t = ldg(coef, (unsigned)(E + e));
+    // the body force of the pair's element (or, with no load, a valid dummy read)
+    const T *__restrict__ bsrc = load ? load : coef;
+    const unsigned bidx = load ? 3u * (unsigned)e : (unsigned)e, bstep = load ? 1u : 0u;
+    T bf[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) bf[c] = ldg(bsrc, bidx + (unsigned)c * bstep);
+    double vx[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vx[c] = ldg(coords, 3u * vid + (unsigned)c);
+    // Bring into L2 the descriptor of a block that starts on this XCD a round or
+    // two of workgroups later, so that its first, dependent load hits (a vector
+    // load consumed only at the end).
+    const int pf_desc = ldg(blk_desc, (unsigned)(min(blk + kP2DescAhead, nblk - 1) * kBlkDesc + (tid & 7)));
+
+    // ---- LDS staging, also without branches: a thread past the end of a list
+    // writes the last element's value to the last element's place, the same
+    // value its owner writes there.
+    sRp[min(tid, nrows)] = rp_reg - rp0;
+    sIp[min(tid, nrows)] = ip_reg - q0;
+    L.seg[min(tid, nent)] = sg_a - s0;
+    L.seg[min(tid + kP2Threads, nent)] = sg_b - s0;
+    reinterpret_cast<uint32_t *>(L.slot)[min(tid, nsu - 1)] = su_a;
+    reinterpret_cast<uint32_t *>(L.slot)[min(tid + kP2Threads, nsu - 1)] = su_b;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Lx[min(tid, nvb - 1) * VS + c] = vx[c];
+    // remainders of large blocks (more entries or vertices than the above covers)
+    for (int u = tid + 2 * kP2Threads; u <= nent; u += kP2Threads) L.seg[u] = ldg(seg_ptr, (unsigned)(rp0 + u)) - s0;
+    for (int l = tid + kP2Threads; l < nvb; l += kP2Threads) {
+        const unsigned v = (unsigned)ldg(blk_vert, (unsigned)(w0 + l));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Lx[l * VS + c] = ldg(coords, 3u * v + (unsigned)c);
     }
     __syncthreads();
 
-    // ---- Map: block row a of K_e (10 blocks of 3x3), kP2LanesPerPair lanes per pair
-    // split by column node b; each lane forms the pair's geometry itself (no
-    // extra barrier).  grad(phi_n) at Keast point q is c_i(q) grad(lambda_i) +
-    // c_j(q) grad(lambda_j) for the node's vertices i, j (see p2_node).
-    using R = Deg2Rule<3>;
-    for (int u = threadIdx.x; u < np * kP2LanesPerPair; u += kP2Threads) {
-        const int t = u / kP2LanesPerPair, sub = u - t * kP2LanesPerPair;
-        const int code = inc[q0 + t];
-        const int e = code / K, a = code - e * K;
+    // ---- Map: block row a of K_e (10 blocks of 3x3).  One lane per pair; wave w
+    // of the block forms the column nodes of the w-th set (vertices 0..3, edges
+    // 4..6, edges 7..9), so the column nodes are compile-time constants, and
+    // each wave forms the pair's geometry itself (no extra barrier).
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (lane < np) {
+        const int t = lane;
         double x[4][3], Gd[4][3];
-        lds_vertices<3>(Lx, ldg(pair_lv, (unsigned)(q0 + t)), x);
-        const double lam_d = (double)coef[e], mu_d = (double)coef[(size_t)E + e];
+        lds_vertices<3>(Lx, lv, x);
+        const double lam_d = (double)lam_t, mu_d = (double)mu_t;
         const double det = p1_gradients<3>(x, Gd);
         const double adet = fabs(det);
-        bool bad = numerically_singular<3>(x, det) || !finite(lam_d) || !finite(mu_d);
-        T g[4][3];
+        P2Row<T> pr;
 #pragma unroll
         for (int p = 0; p < 4; ++p)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) g[p][c] = (T)Gd[p][c];
-        const T w = (T)(adet * R::w);
-        const T lam = (T)lam_d, mu = (T)mu_d;
-        T ga[4][3];
-        p2_node_grads<T>(a, g, ga);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) ga[q][c] = w * ga[q][c];  // the weight, once (same products as before)
-        for (int b = sub; b < K; b += kP2LanesPerPair) {
-            // D_ab = sum_q w_q |det J| grad(phi_a) grad(phi_b)^T
-            T gb[4][3];
-            p2_node_grads<T>(b, g, gb);
-            T Dm[3][3] = {};
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-#pragma unroll
-                    for (int cc = 0; cc < 3; ++cc) Dm[c][cc] += ga[q][c] * gb[q][cc];
-            // Hooke: block[c][c'] = lam D[c][c'] + mu (D[c'][c] + delta_cc' tr D)
-            const T tr = Dm[0][0] + Dm[1][1] + Dm[2][2];
-            T *dst = L.K + (b * np + t) * 9;
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc) dst[c * 3 + cc] = lam * Dm[c][cc] + mu * (Dm[cc][c] + (c == cc ? tr : (T)0));
-        }
-        if (sub == 0) {
+            for (int c = 0; c < 3; ++c) pr.g[p][c] = (T)Gd[p][c];
+        pr.lam = lam_t;
+        pr.mu = mu_t;
+        pr.init(a, (T)(adet * Deg2Rule<3>::w));
+        T *dst = L.K + (size_t)t * 9;
+        const int cs = np * 9;  // LDS stride between column nodes
+        if (wave == 0) {
+            pr.template block<0>(dst, cs);
+            pr.template block<1>(dst, cs);
+            pr.template block<2>(dst, cs);
+            pr.template block<3>(dst, cs);
+            bool bad = numerically_singular<3>(x, det) || !finite(lam_d) || !finite(mu_d);
             if (load) {
                 const double ia = adet * p2_ref_integral(a);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const double bc = (double)load[(size_t)e * 3 + c];
+                    const double bc = (double)bf[c];
                     bad = bad || !finite(bc);
                     L.F[t * 3 + c] = (T)(bc * ia);
                 }
             }
             if (bad && status) atomicMin(status, e);
+        } else if (wave == 1) {
+            pr.template block<4>(dst, cs);
+            pr.template block<5>(dst, cs);
+            pr.template block<6>(dst, cs);
+        } else {
+            pr.template block<7>(dst, cs);
+            pr.template block<8>(dst, cs);
+            pr.template block<9>(dst, cs);
         }
     }
     __syncthreads();
@@ -712,12 +831,12 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     if (rhs && load) {
         for (int u = threadIdx.x; u < 3 * nrows; u += kP2Threads) {
             const int r = u / 3, c = u - 3 * r;
-            const int u0 = inc_ptr[r0 + r] - q0, u1 = inc_ptr[r0 + r + 1] - q0;
             T acc = 0;
-            for (int s = u0; s < u1; ++s) acc += L.F[s * 3 + c];
+            for (int s = sIp[r]; s < sIp[r + 1]; ++s) acc += L.F[s * 3 + c];
             rhs[3 * (size_t)(r0 + r) + c] = acc;
         }
     }
+    asm volatile("" ::"v"(pf_desc));  // keeps the prefetch (its value is not needed)
 }
 
 }  // namespace

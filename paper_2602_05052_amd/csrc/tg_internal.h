@@ -19,8 +19,10 @@ constexpr int kP1Threads = 256;
 constexpr int kP1BlockTarget = 256;
 constexpr int kP1BlockCap = 512;
 constexpr int kP1BlockVerts = 256;  // distinct vertices of a block (8-bit local ids)
-constexpr int kP2Threads = 192;
-constexpr int kP2BlockTarget = 38;
+constexpr int kP2Threads = 192;  // three waves: one per set of column nodes
+// P2: one lane per pair in each wave, so at most 64 pairs; the target keeps an
+// FP64 block's LDS (about 0.75 KB per pair) within a third of the CU's 160 KB.
+constexpr int kP2BlockTarget = 60;
 constexpr int kP2BlockCap = 64;
 constexpr int kBlkDesc = 12;  // ints per row-block descriptor
 // Largest pair count of a row for the compact P1 routing: its one-byte

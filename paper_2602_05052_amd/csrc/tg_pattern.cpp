@@ -233,8 +233,9 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
                 nverts += extra;
                 ++j;
             }
-        } else {
-            while (j < N && hp.inc_ptr[j + 1] - first <= target && hp.node_rp[j + 1] - first_entry <= entry_target)
+        } else {  // P2 blocks also hold at most kP2BlockCap rows (nodes of no element add rows, not pairs)
+            while (j < N && j - i < kP2BlockCap && hp.inc_ptr[j + 1] - first <= target &&
+                   hp.node_rp[j + 1] - first_entry <= entry_target)
                 ++j;
         }
         hp.blk_row.push_back((int32_t)j);

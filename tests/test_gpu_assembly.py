@@ -213,11 +213,7 @@ def _gpu_elasticity(d, dtype):
     return pat, vals.double().cpu().numpy(), rhs.double().cpu().numpy()
 
 
-@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("n", [1, 2, 5])
-def test_p2_elasticity_parity(n, dtype):
-    d = meshgen.elasticity_inputs(n, seed=0)
-    print(f"p2 parity n={n} dtype={dtype}", flush=True)
+def _check_p2(d, dtype):
     pat, vals, rhs = _gpu_elasticity(d, dtype)
     A = oracle.assemble_p2_elasticity(d["coords"], d["conn"], d["lam"], d["mu"], d["b"])
     rp, ci = pat.csr()
@@ -227,6 +223,24 @@ def test_p2_elasticity_parity(n, dtype):
     err = _norm_rel(K, A.scipy())
     assert err <= TOL[dtype], err
     assert _vec_rel(rhs, A.rhs) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("n", [1, 2, 5])
+def test_p2_elasticity_parity(n, dtype):
+    print(f"p2 parity n={n} dtype={dtype}", flush=True)
+    _check_p2(meshgen.elasticity_inputs(n, seed=0), dtype)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("m", [7, 40, 64])
+def test_p2_high_valence_parity(m, dtype):
+    """Nodes shared by m tets (both apexes and their edge): 64 pairs in one row is the P2 block capacity."""
+    print(f"p2 fan m={m} dtype={dtype}", flush=True)
+    d = _fan_inputs(3, m, seed=m)
+    rng = np.random.default_rng(m)
+    d.update(lam=rng.uniform(0.5, 2.0, m), mu=rng.uniform(0.5, 2.0, m), b=rng.standard_normal((m, 3)))
+    _check_p2(d, dtype)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])

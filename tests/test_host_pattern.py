@@ -334,3 +334,15 @@ def test_p1_compact_routing_limit(m, compact):
     diag = np.flatnonzero(ci == node_of_entry)
     vals[diag] = _sequential_segment_sum(Kl[r["inc"] // 4, r["inc"] % 4, r["inc"] % 4], r["inc_ptr"])
     assert np.array_equal(vals, A.vals)
+
+
+@pytest.mark.parametrize("m,ok", [(64, True), (65, False)])
+def test_p2_block_capacity(m, ok):
+    """P2 kernels hold a node's pairs in one wave: a node may belong to at most 64 elements."""
+    conn = np.array([[0, 2 + i, 2 + (i + 1) % m, 1] for i in range(m)], dtype=np.int32)
+    if ok:
+        pat = tg.Pattern(conn, m + 2, order=2, ncomp=3, host_only=True)
+        assert pat.n_nodes == m + 2 + 2 * m + m + 1  # vertices, 2m apex-ring edges, m ring edges, the apex edge
+    else:
+        with pytest.raises(tg.TGError, match="block capacity"):
+            tg.Pattern(conn, m + 2, order=2, ncomp=3, host_only=True)
