@@ -302,6 +302,7 @@ struct P1Lds {
 // Descriptor prefetch distance, in blocks (see p1_assemble_kernel).
 constexpr int kP1DescAhead = 256;
 constexpr int kP2DescAhead = 128;  // about one round of P2 workgroups on an XCD
+constexpr int kP2PhaseCols = 6;     // column nodes of a P2 pair held in LDS at once (the edges)
 
 // Minimum waves per SIMD the register allocation must allow: 8 for the
 // single-set Laplace kernels (they fit in 64 VGPRs without spilling), 7 for the
@@ -616,9 +617,9 @@ struct P2Row {
         }
     }
 
-    // Writes block (a, B) to dst[B * cs .. + 9) (row-major 3x3).
+    // Writes block (a, B) to o[0 .. 9) (row-major 3x3).
     template <int B>
-    __device__ __forceinline__ void block(T *dst, int cs) const {
+    __device__ __forceinline__ void block(T *o) const {
         T D[3][3];
         if constexpr (B < 4) {
             T h[3];
@@ -643,7 +644,6 @@ struct P2Row {
                 for (int cc = 0; cc < 3; ++cc) D[c][cc] = hi[c] * g[i][cc] + hj[c] * g[j][cc];
         }
         const T tr = D[0][0] + D[1][1] + D[2][2];
-        T *o = dst + B * cs;
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -669,6 +669,39 @@ __device__ __forceinline__ double p2_ref_integral(int n) {
     return s;
 }
 
+// Reduce of one column class of a P2 block: one lane per node-level entry
+// whose column is an edge node (edge) or a vertex node (!edge) sums its routed
+// 3x3 blocks (ascending element order, components in parallel) and writes the
+// 9 scalars.  The class's blocks sit in LDS at (slot - first slot of the
+// class) * 9, slot = b np + pair.  Entry pe of row r, column position jpos,
+// lands at 9 sRp[r] + c (3 m) + 3 jpos + cc of the block's value range (the 3
+// DoF rows of a node share its columns).
+template <typename T>
+__device__ __forceinline__ void p2_reduce(const BlockLds<T> &L, const int *sRp, int np, int nent, bool edge,
+                                          T *__restrict__ out) {
+    const int first = edge ? 4 * np : 0;
+    for (int pe = threadIdx.x; pe < nent; pe += kP2Threads) {
+        const int u0 = L.seg[pe], u1 = L.seg[pe + 1];
+        if (u0 == u1 || ((int)L.slot[u0] >= 4 * np) != edge) continue;
+        int r = 0;
+        while (sRp[r + 1] <= pe) ++r;
+        const int m = sRp[r + 1] - sRp[r], jpos = pe - sRp[r];
+        T acc[9];
+#pragma unroll
+        for (int z = 0; z < 9; ++z) acc[z] = 0;
+        for (int u = u0; u < u1; ++u) {
+            const T *src = L.K + ((int)L.slot[u] - first) * 9;
+#pragma unroll
+            for (int z = 0; z < 9; ++z) acc[z] += src[z];
+        }
+        T *o = out + 9 * sRp[r] + 3 * jpos;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) o[c * 3 * m + cc] = acc[c * 3 + cc];
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     const int32_t *__restrict__ blk_desc, const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc,
@@ -679,8 +712,9 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     constexpr int K = 10;
     constexpr int VS = VertLds<3>::VS;
     extern __shared__ __align__(16) unsigned char smem[];
-    BlockLds<T> L(smem, mp, me, 9 * K, 3);
-    double *Lx = reinterpret_cast<double *>(smem + VertLds<3>::offset(BlockLds<T>::bytes(mp, me, 9 * K, 3, K)));
+    BlockLds<T> L(smem, mp, me, 9 * kP2PhaseCols, 3);
+    double *Lx =
+        reinterpret_cast<double *>(smem + VertLds<3>::offset(BlockLds<T>::bytes(mp, me, 9 * kP2PhaseCols, 3, K)));
     __shared__ int sRp[kP2BlockCap + 1];  // row starts in the block's node-level entries
     __shared__ int sIp[kP2BlockCap + 1];  // row starts in the block's pairs
 
@@ -756,19 +790,24 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     }
     __syncthreads();
 
-    // ---- Map: block row a of K_e (10 blocks of 3x3).  One lane per pair; wave w
-    // of the block forms the column nodes of the w-th set (vertices 0..3, edges
-    // 4..6, edges 7..9), so the column nodes are compile-time constants, and
-    // each wave forms the pair's geometry itself (no extra barrier).
+    // ---- Map and Reduce in two phases, one per class of column node: every
+    // entry's column is a vertex node (local b = 0..3 in each of its elements)
+    // or an edge node (b = 4..9), so the vertex-column blocks can be summed
+    // and written before the edge-column blocks take their place in LDS (LDS
+    // for 6 blocks per pair instead of 10: more resident blocks per CU).
+    // One lane per pair; in each phase wave w forms a fixed set of column nodes
+    // (compile-time constants), and each wave forms the pair's geometry once,
+    // kept in registers for both phases.
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    if (lane < np) {
-        const int t = lane;
+    const bool own = lane < np;
+    const int cs = np * 9;  // LDS stride between column nodes
+    T *dst = L.K + lane * 9;
+    P2Row<T> pr;
+    if (own) {
         double x[4][3], Gd[4][3];
         lds_vertices<3>(Lx, lv, x);
-        const double lam_d = (double)lam_t, mu_d = (double)mu_t;
         const double det = p1_gradients<3>(x, Gd);
         const double adet = fabs(det);
-        P2Row<T> pr;
 #pragma unroll
         for (int p = 0; p < 4; ++p)
 #pragma unroll
@@ -776,13 +815,14 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
         pr.lam = lam_t;
         pr.mu = mu_t;
         pr.init(a, (T)(adet * Deg2Rule<3>::w));
-        T *dst = L.K + (size_t)t * 9;
-        const int cs = np * 9;  // LDS stride between column nodes
         if (wave == 0) {
-            pr.template block<0>(dst, cs);
-            pr.template block<1>(dst, cs);
-            pr.template block<2>(dst, cs);
-            pr.template block<3>(dst, cs);
+            pr.template block<0>(dst);
+            pr.template block<1>(dst + cs);
+        } else if (wave == 1) {
+            pr.template block<2>(dst + 2 * cs);
+            pr.template block<3>(dst + 3 * cs);
+        } else {  // the local load and the checks
+            const double lam_d = (double)lam_t, mu_d = (double)mu_t;
             bool bad = numerically_singular<3>(x, det) || !finite(lam_d) || !finite(mu_d);
             if (load) {
                 const double ia = adet * p2_ref_integral(a);
@@ -790,44 +830,29 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
                 for (int c = 0; c < 3; ++c) {
                     const double bc = (double)bf[c];
                     bad = bad || !finite(bc);
-                    L.F[t * 3 + c] = (T)(bc * ia);
+                    L.F[lane * 3 + c] = (T)(bc * ia);
                 }
             }
             if (bad && status) atomicMin(status, e);
-        } else if (wave == 1) {
-            pr.template block<4>(dst, cs);
-            pr.template block<5>(dst, cs);
-            pr.template block<6>(dst, cs);
-        } else {
-            pr.template block<7>(dst, cs);
-            pr.template block<8>(dst, cs);
-            pr.template block<9>(dst, cs);
         }
     }
     __syncthreads();
-
-    // ---- Reduce: one lane per node-level entry sums its routed 3x3 blocks (ascending
-    // element order, components in parallel) and writes the 9 scalars.  Entry pe of
-    // row r, column position jpos, lands at 9 sRp[r] + c (3 m) + 3 jpos + cc of the
-    // block's contiguous value range (the 3 DoF rows of a node share its columns).
-    for (int pe = threadIdx.x; pe < nent; pe += kP2Threads) {
-        int r = 0;
-        while (sRp[r + 1] <= pe) ++r;
-        const int m = sRp[r + 1] - sRp[r], jpos = pe - sRp[r];
-        T acc[9];
-#pragma unroll
-        for (int z = 0; z < 9; ++z) acc[z] = 0;
-        for (int u = L.seg[pe]; u < L.seg[pe + 1]; ++u) {
-            const T *src = L.K + (int)L.slot[u] * 9;
-#pragma unroll
-            for (int z = 0; z < 9; ++z) acc[z] += src[z];
+    p2_reduce<T>(L, sRp, np, nent, false, values + 9 * (size_t)rp0);
+    __syncthreads();  // the edge-column blocks reuse the LDS of the vertex-column ones
+    if (own) {
+        if (wave == 0) {
+            pr.template block<4>(dst);
+            pr.template block<5>(dst + cs);
+        } else if (wave == 1) {
+            pr.template block<6>(dst + 2 * cs);
+            pr.template block<7>(dst + 3 * cs);
+        } else {
+            pr.template block<8>(dst + 4 * cs);
+            pr.template block<9>(dst + 5 * cs);
         }
-        T *o = values + 9 * (size_t)rp0 + 9 * sRp[r] + 3 * jpos;
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int cc = 0; cc < 3; ++cc) o[c * 3 * m + cc] = acc[c * 3 + cc];
     }
+    __syncthreads();
+    p2_reduce<T>(L, sRp, np, nent, true, values + 9 * (size_t)rp0);
     if (rhs && load) {
         for (int u = threadIdx.x; u < 3 * nrows; u += kP2Threads) {
             const int r = u / 3, c = u - 3 * r;
@@ -908,13 +933,13 @@ hipError_t launch_assemble_p2(const tg_pattern &p, tg_dtype dtype, const double 
     const size_t verts = VertLds<3>::bytes(p.host.max_block_verts);
     if (dtype == TG_F64)
         hipLaunchKernelGGL(p2_elasticity_kernel<double>, dim3(nblk), dim3(kP2Threads),
-                           VertLds<3>::offset(BlockLds<double>::bytes(mp, me, 90, 3, 10)) + verts, s, d.blk_desc,
+                           VertLds<3>::offset(BlockLds<double>::bytes(mp, me, 9 * kP2PhaseCols, 3, 10)) + verts, s, d.blk_desc,
                            d.inc_ptr, d.inc, d.node_rp, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, coords,
                            (const double *)coef, (const double *)load, (double *)values, (double *)rhs, status, nblk,
                            E, mp, me);
     else
         hipLaunchKernelGGL(p2_elasticity_kernel<float>, dim3(nblk), dim3(kP2Threads),
-                           VertLds<3>::offset(BlockLds<float>::bytes(mp, me, 90, 3, 10)) + verts, s, d.blk_desc,
+                           VertLds<3>::offset(BlockLds<float>::bytes(mp, me, 9 * kP2PhaseCols, 3, 10)) + verts, s, d.blk_desc,
                            d.inc_ptr, d.inc, d.node_rp, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, coords,
                            (const float *)coef, (const float *)load, (float *)values, (float *)rhs, status, nblk, E,
                            mp, me);

@@ -21,8 +21,9 @@ constexpr int kP1BlockCap = 512;
 constexpr int kP1BlockVerts = 256;  // distinct vertices of a block (8-bit local ids)
 constexpr int kP2Threads = 192;  // three waves: one per set of column nodes
 // P2: one lane per pair in each wave, so at most 64 pairs; the target keeps an
-// FP64 block's LDS (about 0.75 KB per pair) within a third of the CU's 160 KB.
-constexpr int kP2BlockTarget = 60;
+// FP64 block's LDS (about 0.55 KB per pair) within a fifth of the CU's 160 KB,
+// as many blocks as the FP64 kernel's registers allow.
+constexpr int kP2BlockTarget = 52;
 constexpr int kP2BlockCap = 64;
 constexpr int kBlkDesc = 12;  // ints per row-block descriptor
 // Largest pair count of a row for the compact P1 routing: its one-byte
