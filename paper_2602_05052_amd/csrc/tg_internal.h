@@ -105,7 +105,8 @@ struct PcgState {
 
 // One CG system in flight.  The solo solver (tg_pcg) uses one; the request
 // server one per slot.  Lives in device memory; the kernels of a batched
-// launch read slots[list[blockIdx.y]].
+// launch read slots[list[blockIdx.y]] (the solo iteration kernel takes it by
+// value).
 struct PcgSlot {
     const void *values;  // T[nnz], Dirichlet applied
     const void *b;       // T[n]
@@ -196,8 +197,10 @@ hipError_t launch_scaled_exp(tg_dtype dtype, int64_t n, double dt, const double 
 // holds a system on pattern p in dtype.  One launch per iteration (tg_solve.hip).
 hipError_t launch_pcg_init(const tg_pattern &p, tg_dtype dtype, const PcgSlot *slots, const int32_t *list, int count,
                            hipStream_t s);
+// With solo (a host copy of the one slot of a solo solve), the iteration kernel
+// takes the slot by value and slots/list are not read.
 hipError_t launch_pcg_step(const tg_pattern &p, tg_dtype dtype, const PcgSlot *slots, const int32_t *list, int count,
-                           int step, hipStream_t s);
+                           int step, hipStream_t s, const PcgSlot *solo = nullptr);
 // Per-block partials of ||b - K x||^2 into each listed slot's RR partials; returns the block count.
 hipError_t launch_pcg_residual(const tg_pattern &p, tg_dtype dtype, const PcgSlot *slots, const int32_t *list,
                                int count, int *n_partials, hipStream_t s);

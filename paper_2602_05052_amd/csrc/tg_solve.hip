@@ -64,15 +64,19 @@ __device__ __forceinline__ void block_sum3_first(double &a, double &b, double &c
 }
 
 // Sums of three partial arrays [0 .. n), n <= kVecThreads, identical in every
-// block and in the same order as sum_partials, with one pair of barriers.
+// block (the fixed order of block_sum), with one pair of barriers:
+// load_partials3 fetches this thread's entries, reduce_partials3 sums them.
 // sh: 3 kWaves doubles.
-__device__ __forceinline__ void sum_partials3(const double *__restrict__ p0, const double *__restrict__ p1,
-                                              const double *__restrict__ p2, int n, double *sh, double &a,
-                                              double &b, double &c) {
+__device__ __forceinline__ void load_partials3(const double *__restrict__ p0, const double *__restrict__ p1,
+                                               const double *__restrict__ p2, int n, double &a, double &b,
+                                               double &c) {
     const bool in = (int)threadIdx.x < n;
     a = in ? p0[threadIdx.x] : 0.0;
     b = in ? p1[threadIdx.x] : 0.0;
     c = in ? p2[threadIdx.x] : 0.0;
+}
+
+__device__ __forceinline__ void reduce_partials3(double *sh, double &a, double &b, double &c) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         a += __shfl_xor(a, off, 64);
@@ -337,21 +341,46 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_init_spmv_kernel(int n, co
 // the updates of every owned row and w = K u for them, with the partials of
 // the next iterate.  CHECK_ONLY launches stop after the test, and so does
 // iteration max_iter.  n_prev: number of partials written by the previous launch.
-template <typename T, int G, bool CHECK_ONLY>
+// The slot of this launch's system: by value for a solo system (no dependent
+// load before its state), else through the batch's table.
+template <bool SOLO>
+__device__ __forceinline__ PcgSlot pick_slot(const PcgSlot *__restrict__ slots, const int32_t *__restrict__ list,
+                                             const PcgSlot &solo) {
+    if constexpr (SOLO)
+        return solo;
+    else
+        return slots[list[blockIdx.y]];
+}
+
+template <typename T, int G, bool CHECK_ONLY, bool SOLO>
 __global__ __launch_bounds__(kVecThreads, 8) void pcg_iter_kernel(int n, const int32_t *__restrict__ row_ptr,
                                                                const int32_t *__restrict__ col_idx,
                                                                const PcgSlot *__restrict__ slots,
-                                                               const int32_t *__restrict__ list, int step,
-                                                               int n_prev) {
+                                                               const int32_t *__restrict__ list, PcgSlot solo,
+                                                               int step, int n_prev) {
     __shared__ double sh[3 * kWaves];
-    const PcgSlot S = slots[list[blockIdx.y]];
+    const PcgSlot S = pick_slot<SOLO>(slots, list, solo);
     PcgState *__restrict__ st = S.state;
     const int it = step - S.start;
-    if (st->done) return;  // written only by earlier launches: the same value for every wave
     const int cur = 3 * (it & 1), nxt = 3 * ((it + 1) & 1);
+    // The previous launch's partials (threads below n_prev <= kMaxGrid), and the
+    // stop flag and scalars written by earlier launches (the same values for
+    // every wave), loaded by the block's last thread: their latencies overlap,
+    // and the reduction's barriers publish the scalars through LDS.
+    static_assert(kMaxGrid < kVecThreads, "the last thread loads no partials");
+    __shared__ double sst[4];
     double rr_cur, gam, del;
-    sum_partials3(part(S.partials, kRr + cur), part(S.partials, kGam + cur), part(S.partials, kDel + cur), n_prev,
-                  sh, rr_cur, gam, del);
+    load_partials3(part(S.partials, kRr + cur), part(S.partials, kGam + cur), part(S.partials, kDel + cur), n_prev,
+                   rr_cur, gam, del);
+    if (threadIdx.x == kVecThreads - 1) {
+        sst[0] = (double)st->done;
+        sst[1] = st->tol2;
+        sst[2] = st->gamma[(it + 1) & 1];
+        sst[3] = st->alpha[(it + 1) & 1];
+    }
+    reduce_partials3(sh, rr_cur, gam, del);
+    if (sst[0] != 0.0) return;
+    const double tol2_prev = sst[1], gam_prev = sst[2], alpha_prev = sst[3];
     double tol2;
     if (it == 0 && !S.warm) {
         tol2 = S.rtol2 * rr_cur;
@@ -360,7 +389,7 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_iter_kernel(int n, const i
             st->tol2 = tol2;
         }
     } else {
-        tol2 = st->tol2;
+        tol2 = tol2_prev;
     }
     if (rr_cur <= tol2) {  // the same decision in every block
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -375,7 +404,6 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_iter_kernel(int n, const i
         beta_d = 0.0;
         alpha_d = gam / del;
     } else {
-        const double gam_prev = st->gamma[(it + 1) & 1], alpha_prev = st->alpha[(it + 1) & 1];
         beta_d = gam / gam_prev;
         alpha_d = gam / (del - beta_d * gam / alpha_prev);
     }
@@ -529,19 +557,23 @@ void launch_warm_init_t(const tg_pattern &pt, const PcgSlot *slots, const int32_
 
 template <typename T, int G>
 void launch_step_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *list, int count, int step,
-                   hipStream_t s) {
+                   hipStream_t s, const PcgSlot *solo) {
     const int n = (int)pt.host.n_dofs;
     const int ns = spmv_blocks<G>(n);
-    hipLaunchKernelGGL((pcg_iter_kernel<T, G, false>), dim3(ns, count), dim3(kVecThreads), 0, s, n, pt.dev.row_ptr,
-                       pt.dev.col_idx, slots, list, step, ns);
+    if (solo)
+        hipLaunchKernelGGL((pcg_iter_kernel<T, G, false, true>), dim3(ns, 1), dim3(kVecThreads), 0, s, n,
+                           pt.dev.row_ptr, pt.dev.col_idx, slots, list, *solo, step, ns);
+    else
+        hipLaunchKernelGGL((pcg_iter_kernel<T, G, false, false>), dim3(ns, count), dim3(kVecThreads), 0, s, n,
+                           pt.dev.row_ptr, pt.dev.col_idx, slots, list, PcgSlot{}, step, ns);
 }
 
 template <typename T, int G>
 void launch_check_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *list, int count, int step,
                     hipStream_t s) {
     const int n = (int)pt.host.n_dofs;
-    hipLaunchKernelGGL((pcg_iter_kernel<T, G, true>), dim3(1, count), dim3(kVecThreads), 0, s, n, pt.dev.row_ptr,
-                       pt.dev.col_idx, slots, list, step, spmv_blocks<G>(n));
+    hipLaunchKernelGGL((pcg_iter_kernel<T, G, true, false>), dim3(1, count), dim3(kVecThreads), 0, s, n, pt.dev.row_ptr,
+                       pt.dev.col_idx, slots, list, PcgSlot{}, step, spmv_blocks<G>(n));
 }
 
 template <typename T, int G>
@@ -590,9 +622,9 @@ hipError_t launch_pcg_init(const tg_pattern &p, tg_dtype dtype, const PcgSlot *s
 }
 
 hipError_t launch_pcg_step(const tg_pattern &p, tg_dtype dtype, const PcgSlot *slots, const int32_t *list, int count,
-                           int step, hipStream_t s) {
+                           int step, hipStream_t s, const PcgSlot *solo) {
     if (count <= 0) return hipSuccess;
-    dispatch(p, dtype, [&]<typename T, int G>() { launch_step_t<T, G>(p, slots, list, count, step, s); });
+    dispatch(p, dtype, [&]<typename T, int G>() { launch_step_t<T, G>(p, slots, list, count, step, s, solo); });
     return hipGetLastError();
 }
 
@@ -624,7 +656,8 @@ tg_status run_pcg(const tg_pattern &pt, tg_dtype dtype, const void *values, cons
     // caller may capture this stream.
     d.host_state->done = 0;
     d.host_state->iters = 0;
-    *d.host_pcg_slot = PcgSlot{values, rhs, x, d.work, d.partials, d.state, rtol * rtol, 0, max_iter, warm ? 1 : 0};
+    const PcgSlot slot{values, rhs, x, d.work, d.partials, d.state, rtol * rtol, 0, max_iter, warm ? 1 : 0};
+    *d.host_pcg_slot = slot;
     TG_CHECK(hipMemcpyAsync(d.state, d.host_state, sizeof(PcgState), hipMemcpyHostToDevice, s));
     TG_CHECK(hipMemcpyAsync(d.pcg_slot, d.host_pcg_slot, sizeof(PcgSlot), hipMemcpyHostToDevice, s));
     if (warm) {
@@ -641,7 +674,7 @@ tg_status run_pcg(const tg_pattern &pt, tg_dtype dtype, const void *values, cons
     int it = 0;
     auto chunk = [&](int buf) -> hipError_t {
         for (int k = 0; k < check_every && it < max_iter; ++k, ++it) {
-            const hipError_t e = launch_pcg_step(pt, dtype, d.pcg_slot, d.pcg_list, 1, it, s);
+            const hipError_t e = launch_pcg_step(pt, dtype, d.pcg_slot, d.pcg_list, 1, it, s, &slot);
             if (e != hipSuccess) return e;
         }
         const hipError_t e = hipMemcpyAsync(d.host_state + buf, d.state, sizeof(PcgState), hipMemcpyDeviceToHost, s);
