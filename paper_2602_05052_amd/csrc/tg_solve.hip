@@ -2,8 +2,9 @@
 // CSR system (TensorGalerkin Sec. B.1.2: Jacobi-preconditioned Krylov solve of
 // the condensed system, stopped on ||K u - f|| / ||f||).
 //
-// One CG iteration is one kernel of at most 512 blocks of 1024 threads (the
-// single-reduction form described with the PCG kernels below).  Every scalar
+// One CG iteration is one kernel of at most 512 blocks of 1024 threads (512
+// for small systems; the single-reduction form described with the PCG kernels
+// below).  Every scalar
 // (alpha, beta, the stop decision) is recomputed by every block from the
 // previous launch's per-block partials, summed in one fixed order, so all
 // blocks agree bitwise and the solver is reproducible with no atomics, no
@@ -34,7 +35,9 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 }
 
 // Block sums of three values in the same fixed order as block_sum, delivered to
-// thread 0 only (the writer of the block's partials).  sh: 3 kWaves doubles.
+// thread 0 only (the writer of the block's partials).  W: waves of the block;
+// sh: 3 W doubles.
+template <int W = kWaves>
 __device__ __forceinline__ void block_sum3_first(double &a, double &b, double &c, double *sh) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -45,17 +48,17 @@ __device__ __forceinline__ void block_sum3_first(double &a, double &b, double &c
     if ((threadIdx.x & 63) == 0) {
         const int w = threadIdx.x >> 6;
         sh[w] = a;
-        sh[kWaves + w] = b;
-        sh[2 * kWaves + w] = c;
+        sh[W + w] = b;
+        sh[2 * W + w] = c;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double ra = 0.0, rb = 0.0, rc = 0.0;
 #pragma unroll 2
-        for (int w = 0; w < kWaves; ++w) {
+        for (int w = 0; w < W; ++w) {
             ra += sh[w];
-            rb += sh[kWaves + w];
-            rc += sh[2 * kWaves + w];
+            rb += sh[W + w];
+            rc += sh[2 * W + w];
         }
         a = ra;
         b = rb;
@@ -76,6 +79,7 @@ __device__ __forceinline__ void load_partials3(const double *__restrict__ p0, co
     c = in ? p2[threadIdx.x] : 0.0;
 }
 
+template <int W = kWaves>
 __device__ __forceinline__ void reduce_partials3(double *sh, double &a, double &b, double &c) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -86,16 +90,16 @@ __device__ __forceinline__ void reduce_partials3(double *sh, double &a, double &
     if ((threadIdx.x & 63) == 0) {
         const int w = threadIdx.x >> 6;
         sh[w] = a;
-        sh[kWaves + w] = b;
-        sh[2 * kWaves + w] = c;
+        sh[W + w] = b;
+        sh[2 * W + w] = c;
     }
     __syncthreads();
     double ra = 0.0, rb = 0.0, rc = 0.0;
 #pragma unroll 2
-    for (int w = 0; w < kWaves; ++w) {
+    for (int w = 0; w < W; ++w) {
         ra += sh[w];
-        rb += sh[kWaves + w];
-        rc += sh[2 * kWaves + w];
+        rb += sh[W + w];
+        rc += sh[2 * W + w];
     }
     __syncthreads();
     a = ra;
@@ -352,13 +356,18 @@ __device__ __forceinline__ PcgSlot pick_slot(const PcgSlot *__restrict__ slots, 
         return slots[list[blockIdx.y]];
 }
 
-template <typename T, int G, bool CHECK_ONLY, bool SOLO>
-__global__ __launch_bounds__(kVecThreads, 8) void pcg_iter_kernel(int n, const int32_t *__restrict__ row_ptr,
-                                                               const int32_t *__restrict__ col_idx,
-                                                               const PcgSlot *__restrict__ slots,
-                                                               const int32_t *__restrict__ list, PcgSlot solo,
-                                                               int step, int n_prev) {
-    __shared__ double sh[3 * kWaves];
+// TPB: threads per block (kVecThreads, or half of it for small systems, whose
+// grid at kVecThreads stays below kMaxGrid).  n_prev_init: blocks of the kernel
+// that formed iteration 0's partials (pcg_init_spmv_kernel, kVecThreads wide);
+// n_prev: blocks of this kernel at TPB.
+template <typename T, int G, bool CHECK_ONLY, bool SOLO, int TPB>
+__global__ __launch_bounds__(TPB, 8) void pcg_iter_kernel(int n, const int32_t *__restrict__ row_ptr,
+                                                       const int32_t *__restrict__ col_idx,
+                                                       const PcgSlot *__restrict__ slots,
+                                                       const int32_t *__restrict__ list, PcgSlot solo, int step,
+                                                       int n_prev_init, int n_prev) {
+    constexpr int W = TPB / 64;
+    __shared__ double sh[3 * W];
     const PcgSlot S = pick_slot<SOLO>(slots, list, solo);
     PcgState *__restrict__ st = S.state;
     const int it = step - S.start;
@@ -367,18 +376,18 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_iter_kernel(int n, const i
     // stop flag and scalars written by earlier launches (the same values for
     // every wave), loaded by the block's last thread: their latencies overlap,
     // and the reduction's barriers publish the scalars through LDS.
-    static_assert(kMaxGrid < kVecThreads, "the last thread loads no partials");
+    static_assert(kMaxGrid <= TPB, "one partial per thread");
     __shared__ double sst[4];
     double rr_cur, gam, del;
-    load_partials3(part(S.partials, kRr + cur), part(S.partials, kGam + cur), part(S.partials, kDel + cur), n_prev,
-                   rr_cur, gam, del);
-    if (threadIdx.x == kVecThreads - 1) {
+    load_partials3(part(S.partials, kRr + cur), part(S.partials, kGam + cur), part(S.partials, kDel + cur),
+                   it == 0 ? n_prev_init : n_prev, rr_cur, gam, del);
+    if (threadIdx.x == TPB - 1) {
         sst[0] = (double)st->done;
         sst[1] = st->tol2;
         sst[2] = st->gamma[(it + 1) & 1];
         sst[3] = st->alpha[(it + 1) & 1];
     }
-    reduce_partials3(sh, rr_cur, gam, del);
+    reduce_partials3<W>(sh, rr_cur, gam, del);
     if (sst[0] != 0.0) return;
     const double tol2_prev = sst[1], gam_prev = sst[2], alpha_prev = sst[3];
     double tol2;
@@ -418,9 +427,9 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_iter_kernel(int n, const i
     const TG_GLOBAL T *__restrict__ values = gl((const T *)S.values);
     TG_GLOBAL T *__restrict__ x = gl((T *)S.x);
     const int lane = threadIdx.x % G;
-    const int rows_per_grid = gridDim.x * (kVecThreads / G);
+    const int rows_per_grid = gridDim.x * (TPB / G);
     double gn = 0.0, dn = 0.0, rn = 0.0;
-    for (int i = blockIdx.x * (kVecThreads / G) + threadIdx.x / G; i < n; i += rows_per_grid) {
+    for (int i = blockIdx.x * (TPB / G) + threadIdx.x / G; i < n; i += rows_per_grid) {
         const int p0 = row_ptr[i], p1 = row_ptr[i + 1];
         // the row's own record, p and x do not depend on the SpMV: fetch them first
         // (up to 16 lanes per row; wider groups need the registers for the SpMV)
@@ -459,7 +468,7 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_iter_kernel(int n, const i
             rn += (double)ri * (double)ri;
         }
     }
-    block_sum3_first(gn, dn, rn, sh);
+    block_sum3_first<W>(gn, dn, rn, sh);
     if (threadIdx.x == 0) {
         part(S.partials, kGam + nxt)[blockIdx.x] = gn;
         part(S.partials, kDel + nxt)[blockIdx.x] = dn;
@@ -555,25 +564,50 @@ void launch_warm_init_t(const tg_pattern &pt, const PcgSlot *slots, const int32_
                        pt.dev.col_idx, slots, list);
 }
 
+// Threads per block of the iteration kernel: half of kVecThreads when the grid
+// at kVecThreads would stay below kMaxGrid (a small system: twice the blocks,
+// half the waves per barrier; measured 16% faster per FP64 iteration at 66k
+// rows), else kVecThreads (a grid-stride kernel at kMaxGrid blocks).
+template <int G>
+int iter_tpb(int64_t n) {
+    return n * G < (int64_t)kMaxGrid * kVecThreads ? kVecThreads / 2 : kVecThreads;
+}
+
+template <int G>
+int iter_blocks(int64_t n) {
+    const int64_t rows_per_block = iter_tpb<G>(n) / G;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxGrid, (n + rows_per_block - 1) / rows_per_block));
+}
+
+template <typename T, int G, int TPB>
+void launch_step_tpb(const tg_pattern &pt, const PcgSlot *slots, const int32_t *list, int count, int step,
+                     hipStream_t s, const PcgSlot *solo) {
+    const int n = (int)pt.host.n_dofs;
+    const int ns0 = spmv_blocks<G>(n), ns = iter_blocks<G>(n);
+    if (solo)
+        hipLaunchKernelGGL((pcg_iter_kernel<T, G, false, true, TPB>), dim3(ns, 1), dim3(TPB), 0, s, n, pt.dev.row_ptr,
+                           pt.dev.col_idx, slots, list, *solo, step, ns0, ns);
+    else
+        hipLaunchKernelGGL((pcg_iter_kernel<T, G, false, false, TPB>), dim3(ns, count), dim3(TPB), 0, s, n,
+                           pt.dev.row_ptr, pt.dev.col_idx, slots, list, PcgSlot{}, step, ns0, ns);
+}
+
 template <typename T, int G>
 void launch_step_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *list, int count, int step,
                    hipStream_t s, const PcgSlot *solo) {
-    const int n = (int)pt.host.n_dofs;
-    const int ns = spmv_blocks<G>(n);
-    if (solo)
-        hipLaunchKernelGGL((pcg_iter_kernel<T, G, false, true>), dim3(ns, 1), dim3(kVecThreads), 0, s, n,
-                           pt.dev.row_ptr, pt.dev.col_idx, slots, list, *solo, step, ns);
+    if (iter_tpb<G>(pt.host.n_dofs) == kVecThreads)
+        launch_step_tpb<T, G, kVecThreads>(pt, slots, list, count, step, s, solo);
     else
-        hipLaunchKernelGGL((pcg_iter_kernel<T, G, false, false>), dim3(ns, count), dim3(kVecThreads), 0, s, n,
-                           pt.dev.row_ptr, pt.dev.col_idx, slots, list, PcgSlot{}, step, ns);
+        launch_step_tpb<T, G, kVecThreads / 2>(pt, slots, list, count, step, s, solo);
 }
 
 template <typename T, int G>
 void launch_check_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *list, int count, int step,
                     hipStream_t s) {
     const int n = (int)pt.host.n_dofs;
-    hipLaunchKernelGGL((pcg_iter_kernel<T, G, true, false>), dim3(1, count), dim3(kVecThreads), 0, s, n, pt.dev.row_ptr,
-                       pt.dev.col_idx, slots, list, PcgSlot{}, step, spmv_blocks<G>(n));
+    hipLaunchKernelGGL((pcg_iter_kernel<T, G, true, false, kVecThreads>), dim3(1, count), dim3(kVecThreads), 0, s, n,
+                       pt.dev.row_ptr, pt.dev.col_idx, slots, list, PcgSlot{}, step, spmv_blocks<G>(n),
+                       iter_blocks<G>(n));
 }
 
 template <typename T, int G>
