@@ -20,12 +20,54 @@ namespace {
 
 constexpr int kWaves = kVecThreads / 64;
 
-// Sum over the block in a fixed order: butterfly within each wave (every lane
-// ends with the same bits: a + b == b + a), then the wave sums in index order.
-__device__ __forceinline__ double block_sum(double v, double *sh) {
+// One DPP move of a double (both 32-bit halves); lanes whose source is outside
+// the row, and lanes of rows outside ROW_MASK, receive +0.0.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, ROW_MASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, ROW_MASK, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wave in a fixed order with DPP moves (VALU only,
+// no LDS round trips): an inclusive scan within each row of 16 lanes (shifts
+// by 1, 2, 4, 8), then lane 15 of rows 0 and 2 added into rows 1 and 3, then
+// lane 31 into rows 2 and 3.  Lane 63 ends with the total.
+__device__ __forceinline__ double wave_sum_last(double v) {
+    v += dpp_move<0x111>(v);       // row_shr:1
+    v += dpp_move<0x112>(v);       // row_shr:2
+    v += dpp_move<0x114>(v);       // row_shr:4
+    v += dpp_move<0x118>(v);       // row_shr:8
+    v += dpp_move<0x142, 0xA>(v);  // row_bcast:15
+    v += dpp_move<0x143, 0xC>(v);  // row_bcast:31
+    return v;
+}
+
+// Sum over the lanes of a row group of G lanes, in a fixed order, every lane of
+// the group ending with the same bits (a + b == b + a): DPP moves within a row
+// of 16 lanes for G <= 16 (swap neighbours, swap pairs, mirror 8, mirror 16),
+// lane shuffles for G = 32.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+    static_assert(G == 4 || G == 8 || G == 16 || G == 32, "row groups of 4 to 32 lanes");
+    if constexpr (G <= 16) {
+        v += dpp_move<0xB1>(v);  // quad_perm [1, 0, 3, 2]
+        v += dpp_move<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+        if constexpr (G >= 8) v += dpp_move<0x141>(v);  // row_half_mirror
+        if constexpr (G >= 16) v += dpp_move<0x140>(v);  // row_mirror
+    } else {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+        for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+    }
+    return v;
+}
+
+// Sum over the block in a fixed order: wave_sum_last, then the wave totals in
+// index order; every thread gets the result.
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    v = wave_sum_last(v);
+    if ((threadIdx.x & 63) == 63) sh[threadIdx.x >> 6] = v;
     __syncthreads();
     double r = 0.0;
 #pragma unroll
@@ -34,18 +76,15 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     return r;
 }
 
-// Block sums of three values in the same fixed order as block_sum, delivered to
-// thread 0 only (the writer of the block's partials).  W: waves of the block;
-// sh: 3 W doubles.
+// Block sums of three values, in a fixed order (wave_sum_last, then the wave
+// totals in index order), delivered to thread 0 only (the writer of the
+// block's partials).  W: waves of the block; sh: 3 W doubles.
 template <int W = kWaves>
 __device__ __forceinline__ void block_sum3_first(double &a, double &b, double &c, double *sh) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        a += __shfl_xor(a, off, 64);
-        b += __shfl_xor(b, off, 64);
-        c += __shfl_xor(c, off, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
+    a = wave_sum_last(a);
+    b = wave_sum_last(b);
+    c = wave_sum_last(c);
+    if ((threadIdx.x & 63) == 63) {
         const int w = threadIdx.x >> 6;
         sh[w] = a;
         sh[W + w] = b;
@@ -67,7 +106,7 @@ __device__ __forceinline__ void block_sum3_first(double &a, double &b, double &c
 }
 
 // Sums of three partial arrays [0 .. n), n <= kVecThreads, identical in every
-// block (the fixed order of block_sum), with one pair of barriers:
+// block (the fixed order of block_sum3_first), with one pair of barriers:
 // load_partials3 fetches this thread's entries, reduce_partials3 sums them.
 // sh: 3 kWaves doubles.
 __device__ __forceinline__ void load_partials3(const double *__restrict__ p0, const double *__restrict__ p1,
@@ -81,13 +120,10 @@ __device__ __forceinline__ void load_partials3(const double *__restrict__ p0, co
 
 template <int W = kWaves>
 __device__ __forceinline__ void reduce_partials3(double *sh, double &a, double &b, double &c) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        a += __shfl_xor(a, off, 64);
-        b += __shfl_xor(b, off, 64);
-        c += __shfl_xor(c, off, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
+    a = wave_sum_last(a);
+    b = wave_sum_last(b);
+    c = wave_sum_last(c);
+    if ((threadIdx.x & 63) == 63) {
         const int w = threadIdx.x >> 6;
         sh[w] = a;
         sh[W + w] = b;
@@ -145,8 +181,7 @@ __device__ __forceinline__ double row_dot(int i, int lane, const int32_t *__rest
     const int p0 = row_ptr[i], p1 = row_ptr[i + 1];
     double acc = 0.0;
     for (int q = p0 + lane; q < p1; q += G) acc += (double)values[q] * (double)x[col_idx[q]];
-#pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+    acc = group_sum<G>(acc);
     return acc;
 }
 
@@ -323,8 +358,7 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_init_spmv_kernel(int n, co
             const int j = col_idx[q];
             acc += (double)values[q] * (double)(rec[j].d * rec[j].r);
         }
-#pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+        acc = group_sum<G>(acc);
         if (lane == 0) {
             const T ri = rec[i].r, ui = rec[i].d * ri, wi = (T)acc;
             rec[i].w = wi;
@@ -447,8 +481,7 @@ __global__ __launch_bounds__(TPB, 8) void pcg_iter_kernel(int n, const int32_t *
             const int j = col_idx[q];
             acc += (double)values[q] * (double)next_u(load_rec(ra, j), beta, alpha);
         }
-#pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+        acc = group_sum<G>(acc);
         if (lane == 0) {
             if (!kEarly) {
                 o = load_rec(ra, i);
