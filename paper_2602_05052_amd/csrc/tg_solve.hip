@@ -106,9 +106,10 @@ __device__ __forceinline__ void block_sum3_first(double &a, double &b, double &c
 }
 
 // Sums of three partial arrays [0 .. n), n <= kVecThreads, identical in every
-// block (the fixed order of block_sum3_first), with one pair of barriers:
+// block (the fixed order of block_sum3_first), with one barrier:
 // load_partials3 fetches this thread's entries, reduce_partials3 sums them.
-// sh: 3 kWaves doubles.
+// sh: 3 W doubles, not written again by the caller's block in this launch (no
+// barrier protects its later reuse).
 __device__ __forceinline__ void load_partials3(const double *__restrict__ p0, const double *__restrict__ p1,
                                                const double *__restrict__ p2, int n, double &a, double &b,
                                                double &c) {
@@ -137,7 +138,6 @@ __device__ __forceinline__ void reduce_partials3(double *sh, double &a, double &
         rb += sh[W + w];
         rc += sh[2 * W + w];
     }
-    __syncthreads();
     a = ra;
     b = rb;
     c = rc;
@@ -401,7 +401,8 @@ __global__ __launch_bounds__(TPB, 8) void pcg_iter_kernel(int n, const int32_t *
                                                        const int32_t *__restrict__ list, PcgSlot solo, int step,
                                                        int n_prev_init, int n_prev) {
     constexpr int W = TPB / 64;
-    __shared__ double sh[3 * W];
+    __shared__ double sh[3 * W];   // the previous partials' reduction
+    __shared__ double sh2[3 * W];  // this launch's block sums
     const PcgSlot S = pick_slot<SOLO>(slots, list, solo);
     PcgState *__restrict__ st = S.state;
     const int it = step - S.start;
@@ -501,7 +502,7 @@ __global__ __launch_bounds__(TPB, 8) void pcg_iter_kernel(int n, const int32_t *
             rn += (double)ri * (double)ri;
         }
     }
-    block_sum3_first<W>(gn, dn, rn, sh);
+    block_sum3_first<W>(gn, dn, rn, sh2);
     if (threadIdx.x == 0) {
         part(S.partials, kGam + nxt)[blockIdx.x] = gn;
         part(S.partials, kDel + nxt)[blockIdx.x] = dn;
