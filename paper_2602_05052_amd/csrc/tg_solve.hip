@@ -407,10 +407,34 @@ __global__ __launch_bounds__(TPB, 8) void pcg_iter_kernel(int n, const int32_t *
     PcgState *__restrict__ st = S.state;
     const int it = step - S.start;
     const int cur = 3 * (it & 1), nxt = 3 * ((it + 1) & 1);
+    const SlotVecs<T> v(S, n);
+    const TG_GLOBAL Rec<T> *__restrict__ ra = v.rec(it & 1);
+    TG_GLOBAL Rec<T> *__restrict__ rb = v.rec((it + 1) & 1);
+    const TG_GLOBAL T *__restrict__ values = gl((const T *)S.values);
+    TG_GLOBAL T *__restrict__ x = gl((T *)S.x);
+    const int lane = threadIdx.x % G;
+    const int rows_per_grid = gridDim.x * (TPB / G);
+    const int i_first = blockIdx.x * (TPB / G) + threadIdx.x / G;
+    // Small systems (TPB below kVecThreads: at most a few blocks take a second
+    // row): this thread's first row's operands do not depend on alpha and beta,
+    // so they are fetched here, before the reduction, and their latencies
+    // overlap it: the row's bounds, its first kPre entries of this lane
+    // (column, value, the column's record) and the row's own record, p and x.
+    constexpr int kPre = (!CHECK_ONLY && TPB < kVecThreads) ? 2 : 0;
+    int f_p0 = 0, f_p1 = 0;
+    T f_val[kPre > 0 ? kPre : 1];
+    Rec<T> f_rec[kPre > 0 ? kPre : 1];
+    Rec<T> f_o{};
+    T f_pold = 0, f_xold = 0;
+    if constexpr (kPre > 0) {
+        const int i0 = min(i_first, n - 1);  // clamped: a thread past the end fetches row n-1, unused
+        f_p0 = row_ptr[i0];
+        f_p1 = row_ptr[i0 + 1];
+    }
     // The previous launch's partials (threads below n_prev <= kMaxGrid), and the
     // stop flag and scalars written by earlier launches (the same values for
     // every wave), loaded by the block's last thread: their latencies overlap,
-    // and the reduction's barriers publish the scalars through LDS.
+    // and the reduction's barrier publishes the scalars through LDS.
     static_assert(kMaxGrid <= TPB, "one partial per thread");
     __shared__ double sst[4];
     double rr_cur, gam, del;
@@ -421,6 +445,21 @@ __global__ __launch_bounds__(TPB, 8) void pcg_iter_kernel(int n, const int32_t *
         sst[1] = st->tol2;
         sst[2] = st->gamma[(it + 1) & 1];
         sst[3] = st->alpha[(it + 1) & 1];
+    }
+    if constexpr (kPre > 0) {
+        const int i0 = min(i_first, n - 1);
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            const int q = f_p0 + lane + u * G;
+            const int qc = q < f_p1 ? q : f_p0;  // every row holds its diagonal: f_p0 is an entry
+            f_val[u] = values[qc];
+            f_rec[u] = load_rec(ra, col_idx[qc]);
+        }
+        if (lane == 0) {
+            f_o = load_rec(ra, i0);
+            f_pold = v.p[i0];
+            f_xold = x[i0];
+        }
     }
     reduce_partials3<W>(sh, rr_cur, gam, del);
     if (sst[0] != 0.0) return;
@@ -456,15 +495,36 @@ __global__ __launch_bounds__(TPB, 8) void pcg_iter_kernel(int n, const int32_t *
         st->gamma[it & 1] = gam;
     }
     const T alpha = (T)alpha_d, beta = (T)beta_d;
-    const SlotVecs<T> v(S, n);
-    const TG_GLOBAL Rec<T> *__restrict__ ra = v.rec(it & 1);
-    TG_GLOBAL Rec<T> *__restrict__ rb = v.rec((it + 1) & 1);
-    const TG_GLOBAL T *__restrict__ values = gl((const T *)S.values);
-    TG_GLOBAL T *__restrict__ x = gl((T *)S.x);
-    const int lane = threadIdx.x % G;
-    const int rows_per_grid = gridDim.x * (TPB / G);
     double gn = 0.0, dn = 0.0, rn = 0.0;
-    for (int i = blockIdx.x * (TPB / G) + threadIdx.x / G; i < n; i += rows_per_grid) {
+    // the row's update by its group's lane 0, from its own record, p, x and w = (K u)_i
+    auto update_row = [&](int i, double acc, const Rec<T> &o, T p_old, T x_old) {
+        const T pi = o.d * o.r + beta * p_old;  // u_i + beta p
+        const T si = next_s(o, beta);
+        const T ri = next_r(o, si, alpha);
+        const T ui = o.d * ri;
+        const T wi = (T)acc;
+        x[i] = x_old + alpha * pi;
+        v.p[i] = pi;
+        store_rec(rb, i, ri, wi, si, o.d);
+        gn += (double)ri * (double)ui;
+        dn += (double)wi * (double)ui;
+        rn += (double)ri * (double)ri;
+    };
+    int i_start = i_first;
+    if constexpr (kPre > 0) {
+        if (i_first < n) {
+            double acc = 0.0;
+#pragma unroll
+            for (int u = 0; u < kPre; ++u)
+                if (f_p0 + lane + u * G < f_p1) acc += (double)f_val[u] * (double)next_u(f_rec[u], beta, alpha);
+            for (int q = f_p0 + lane + kPre * G; q < f_p1; q += G)  // rows longer than kPre G entries
+                acc += (double)values[q] * (double)next_u(load_rec(ra, col_idx[q]), beta, alpha);
+            acc = group_sum<G>(acc);
+            if (lane == 0) update_row(i_first, acc, f_o, f_pold, f_xold);
+        }
+        i_start += rows_per_grid;
+    }
+    for (int i = i_start; i < n; i += rows_per_grid) {
         const int p0 = row_ptr[i], p1 = row_ptr[i + 1];
         // the row's own record, p and x do not depend on the SpMV: fetch them first
         // (up to 16 lanes per row; wider groups need the registers for the SpMV)
@@ -489,17 +549,7 @@ __global__ __launch_bounds__(TPB, 8) void pcg_iter_kernel(int n, const int32_t *
                 p_old = v.p[i];
                 x_old = x[i];
             }
-            const T pi = o.d * o.r + beta * p_old;  // u_i + beta p
-            const T si = next_s(o, beta);
-            const T ri = next_r(o, si, alpha);
-            const T ui = o.d * ri;
-            const T wi = (T)acc;
-            x[i] = x_old + alpha * pi;
-            v.p[i] = pi;
-            store_rec(rb, i, ri, wi, si, o.d);
-            gn += (double)ri * (double)ui;
-            dn += (double)wi * (double)ui;
-            rn += (double)ri * (double)ri;
+            update_row(i, acc, o, p_old, x_old);
         }
     }
     block_sum3_first<W>(gn, dn, rn, sh2);
