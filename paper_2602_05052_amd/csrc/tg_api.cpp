@@ -111,10 +111,11 @@ tg_status create_device(tg_pattern &pt) {
         return fail(st, msg);
     }
     d.bytes = bytes;
-    // lanes per row in the SpMV: about half the mean row length, power of two in [4, 32]
+    // lanes per row in the SpMV: about a quarter of the mean row length (two
+    // entries per lane, more rows in flight per wave), power of two in [4, 32]
     const double mean_row = h.n_dofs ? (double)h.nnz / (double)h.n_dofs : 1.0;
     int g = 4;
-    while (g < 32 && g < mean_row / 2) g *= 2;
+    while (g < 32 && g < mean_row / 4) g *= 2;
     d.spmv_group = g;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, pt.device) == hipSuccess && prop.multiProcessorCount > 0)
