@@ -155,8 +155,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path; the path would shard by row blocks across GPUs",
-              file=sys.stderr)
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the path would shard by row blocks across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
