@@ -230,7 +230,7 @@ tg_status tg_assemble(const tg_pattern *p, tg_form form, tg_dtype dtype, const d
 /*
  * tg_assemble for nbatch coefficient sets on one pattern in one launch
  * (LAPLACE and MASS_LAPLACE; many right-hand sides / coefficient fields on a
- * fixed mesh, cf. the batched data generation of Sec. B.2).  The geometry and
+ * fixed mesh, cf. the batched data generation of SM B.1.4).  The geometry and
  * the routing are read once; member m reads d_coef + m*E and d_load + m*E
  * (both [nbatch][n_elements]) and writes d_values + m*nnz and d_rhs + m*n_dofs
  * ([nbatch][nnz] and [nbatch][n_dofs]).  Each member is bitwise equal to a
@@ -365,7 +365,7 @@ tg_status tg_heat_adjoint(const tg_pattern *p, tg_dtype dtype, const double *d_c
 /*
  * Request server: continuous batching of assemble + solve requests with
  * iteration-level scheduling (the batched generation of many PDE instances of
- * SM B.2, served the way LLM servers batch generation steps).
+ * SM B.1.4, served the way LLM servers batch generation steps).
  *
  * A request = assemble (tg_assemble's forms except TG_MASS), eliminate
  * Dirichlet data (tg_apply_dirichlet, with d_g or g = 0), and solve with

@@ -1,7 +1,7 @@
 // Request server: continuous batching of assemble + Dirichlet + PCG requests
 // with iteration-level scheduling.
 //
-// The paper generates data in batches (SM B.2, efficient batch data
+// The paper generates data in batches (SM B.1.4, efficient batch data
 // generation); a stream of independent solves is served here the way LLM
 // servers batch token generation.  Requests are grouped by (pattern, dtype).
 // Each group owns slots: per-slot device buffers (values, rhs, Krylov
