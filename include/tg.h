@@ -403,9 +403,9 @@ typedef struct {
     size_t hbm_used, hbm_budget;
 } tg_server_info;
 
-/* hbm_budget_bytes: cap on slot memory (per slot: nnz + 10 n_dofs values of the
- * dtype + 28 KB); max_slots: slots per group (1..65535); check_every: CG
- * iterations per tg_server_step (>= 1). */
+/* hbm_budget_bytes: cap on slot memory (tg_server_slot_bytes per slot);
+ * max_slots: slots per group (1..65535); check_every: CG iterations per
+ * tg_server_step (>= 1). */
 tg_status tg_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t check_every, void *stream,
                            tg_server **out);
 
@@ -423,6 +423,12 @@ tg_status tg_server_step(tg_server *srv, int32_t *n_active, int32_t *n_queued);
 tg_status tg_server_poll(tg_server *srv, int32_t max_results, tg_server_result *out, int32_t *n_out);
 
 tg_status tg_server_query(const tg_server *srv, tg_server_info *info);
+
+/* Device bytes of one server slot for systems on pattern p in dtype (values in
+ * CSR and sliced-ELL layouts, right-hand side, Krylov vectors and partial sums),
+ * the unit in which a server's HBM budget is spent.  Host-only; TG_E_ARG for a
+ * NULL pattern or output, TG_E_STATE for a host-only pattern. */
+tg_status tg_server_slot_bytes(const tg_pattern *p, tg_dtype dtype, size_t *bytes);
 
 /* Synchronises the server's stream and frees its slots (NULL is a no-op). */
 void tg_server_destroy(tg_server *srv);

@@ -103,6 +103,7 @@ _SIGS = {
     "tg_server_step": (ctypes.c_int, [_vp, _i32p, _i32p]),
     "tg_server_poll": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ServerResult), _i32p]),
     "tg_server_query": (ctypes.c_int, [_vp, ctypes.POINTER(_ServerInfo)]),
+    "tg_server_slot_bytes": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_size_t)]),
     "tg_server_destroy": (None, [_vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -505,6 +506,13 @@ def heat_adjoint(pattern: Pattern, coords, log_a, states, g, dt: float, rtol: fl
                                 du0.data_ptr() if du0 is not None else None, float(rtol), int(max_iter),
                                 int(check_every), ctypes.byref(it), ctypes.byref(rr), sp, _stream_handle(stream)))
     return dla, dx, du0, it.value, rr.value
+
+
+def server_slot_bytes(pattern: Pattern, dtype="f64") -> int:
+    """Device bytes of one server slot for systems on `pattern` in `dtype` (the unit of the HBM budget)."""
+    out = ctypes.c_size_t()
+    _check(_lib.tg_server_slot_bytes(pattern.handle, _dtype_code(dtype), ctypes.byref(out)))
+    return int(out.value)
 
 
 class Server:

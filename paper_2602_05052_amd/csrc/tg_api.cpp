@@ -36,7 +36,8 @@ void free_device(tg::DevicePattern &d) {
     void *ptrs[] = {d.conn,    d.inc_ptr, d.inc,      d.blk_row,     d.blk_desc, d.node_rp, d.node_ci, d.seg_ptr,
                     d.blk_vert, d.pair_lv,
                     d.slot,    d.ent16,   d.slot8,    d.row_ptr,     d.col_idx, d.diag_pos, d.constrained,
-                    d.work,    d.partials, d.state, d.dir_rows,  d.pcg_slot, d.pcg_list};
+                    d.work,    d.partials, d.state, d.dir_rows,  d.pcg_slot, d.pcg_list, d.sell_ptr,
+                    d.sell_col, d.sell_vals};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (d.ws) (void)hipFree(d.ws);
@@ -73,8 +74,17 @@ tg_status create_device(tg_pattern &pt) {
     TG_UP(diag_pos, diag_pos);
     TG_UP(constrained, constrained);
     TG_UP(dirichlet_rows, dir_rows);
+    TG_UP(sell_ptr, sell_ptr);
+    TG_UP(sell_col, sell_col);
 #undef TG_UP
     d.n_dir_rows = (int64_t)h.dirichlet_rows.size();
+    d.n_slices = h.sell_ptr.empty() ? 0 : (int64_t)h.sell_ptr.size() - 1;
+    d.sell_nnz = h.sell_ptr.empty() ? 0 : (int64_t)h.sell_ptr.back();
+    if (e == hipSuccess) {
+        const size_t sb = (size_t)std::max<int64_t>(1, d.sell_nnz) * sizeof(double);
+        e = hipMalloc((void **)&d.sell_vals, sb);
+        bytes += sb;
+    }
     if (e == hipSuccess) {
         const size_t wb = (size_t)kPcgWorkVectors * h.n_dofs * sizeof(double);
         e = hipMalloc((void **)&d.work, wb);

@@ -26,6 +26,7 @@ constexpr int kP2Threads = 192;  // three waves: one per set of column nodes
 constexpr int kP2BlockTarget = 52;
 constexpr int kP2BlockCap = 64;
 constexpr int kBlkDesc = 12;  // ints per row-block descriptor
+constexpr int kSellRows = 64;  // rows per slice of the sliced-ELL pattern: one per lane of a wave
 // Largest pair count of a row for the compact P1 routing: its one-byte
 // row-relative slot codes (pair offset * k + b) stay below 256.
 constexpr int compact_row_pairs(int k) { return 256 / k; }
@@ -73,6 +74,11 @@ struct HostPattern {
     std::vector<int32_t> row_ptr;   // [n_dofs+1]
     std::vector<int32_t> col_idx;   // [nnz]
     std::vector<int32_t> diag_pos;  // [n_dofs]
+    // Sliced-ELL copy of the scalar pattern (the CG iterations' SpMV): slices of
+    // kSellRows consecutive rows, entry k of row r at sell_ptr[r / kSellRows] +
+    // kSellRows k + r % kSellRows; padding entries name the row itself (value 0).
+    std::vector<int32_t> sell_ptr;  // [n_slices+1]
+    std::vector<int32_t> sell_col;  // [sell_ptr[n_slices]]
     // Dirichlet.
     std::vector<uint8_t> constrained;  // [n_dofs] 0/1
     std::vector<int32_t> constrained_list;
@@ -109,6 +115,7 @@ struct PcgState {
 // value).
 struct PcgSlot {
     const void *values;  // T[nnz], Dirichlet applied
+    const void *sell;    // T[sell_nnz]: the same values in the sliced-ELL layout (the iterations' SpMV)
     const void *b;       // T[n]
     void *x;             // T[n], the iterate (output)
     void *work;          // T[kPcgWorkVectors n]: records {r, w, s, dinv} x 2 (by parity), p
@@ -120,8 +127,9 @@ struct PcgSlot {
     int32_t warm = 0;    // 1: x holds the initial guess and the stop test is relative to ||b||
 };
 
-constexpr int kVecThreads = 1024;  // threads per block of the PCG kernels
-constexpr int kMaxGrid = 512;      // blocks of the PCG kernels (grid-stride beyond): 2 per CU
+constexpr int kVecThreads = 1024;  // threads per block of the PCG setup and residual kernels
+constexpr int kMaxGrid = 1024;     // blocks of any PCG kernel (grid-stride beyond)
+constexpr int kIterThreads = 512;  // threads per block of the CG iteration kernel: 8 slices
 // Per-block partial sums of the PCG kernels, kMaxGrid doubles each: r.u, w.u and r.r
 // of an iterate at kGam/kDel/kRr + 3 (iteration & 1), and the true residual at kResid.
 constexpr int kGam = 0, kDel = 1, kRr = 2, kResid = 6, kNumPartials = 7;
@@ -146,6 +154,10 @@ struct DevicePattern {
     int32_t *col_idx = nullptr;   // [nnz]
     int32_t *diag_pos = nullptr;  // [n_dofs]
     uint8_t *constrained = nullptr;  // [n_dofs]
+    int32_t *sell_ptr = nullptr;     // [n_slices+1] sliced-ELL pattern (HostPattern::sell_ptr)
+    int32_t *sell_col = nullptr;     // [sell_nnz]
+    int64_t n_slices = 0, sell_nnz = 0;
+    double *sell_vals = nullptr;     // the solo solver's sliced-ELL copy of the values (sell_nnz, used as T)
     // PCG workspace: kPcgWorkVectors vectors of n_dofs doubles (used as T), partials, state.
     double *work = nullptr;
     double *partials = nullptr;  // [kNumPartials][kMaxGrid]
@@ -185,6 +197,8 @@ hipError_t launch_dirichlet(const tg_pattern &p, tg_dtype dtype, void *values, v
                             hipStream_t s);
 hipError_t launch_spmv(const tg_pattern &p, tg_dtype dtype, const void *values, const void *x, void *y,
                        hipStream_t s);
+// The sliced-ELL copy of CSR values (both of dtype) for the CG iterations.
+hipError_t launch_sell_fill(const tg_pattern &p, tg_dtype dtype, const void *values, void *sell, hipStream_t s);
 // Adjoint of P1 assembly (tg_adjoint.hip): dlogc [E] (may be NULL) and dcoords [nv][dim]
 // (may be NULL) of scale * sum_m lam_m^T (A u_m - M w_m); scratch holds E*(dim+1)*dim doubles.
 hipError_t launch_adjoint_p1(const tg_pattern &p, tg_form form, tg_dtype dtype, int nbatch, const double *coords,

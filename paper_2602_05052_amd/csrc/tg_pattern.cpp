@@ -394,6 +394,39 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
         hp.diag_pos[r] = (int32_t)(std::lower_bound(b, e, (int32_t)r) - hp.col_idx.begin());
     }
 
+    // ---- sliced-ELL copy of the CSR pattern for the CG iterations: slice s holds
+    // rows [64 s, 64 s + 64) (one row per lane of a wave); entry k of row r sits at
+    // sell_ptr[s] + 64 k + (r - 64 s), and every row of a slice is padded to the
+    // slice's longest row (at least one entry) with its own index as column
+    {
+        const int64_t nsl = (hp.n_dofs + kSellRows - 1) / kSellRows;
+        hp.sell_ptr.assign(nsl + 1, 0);
+        int64_t off = 0;
+        for (int64_t s = 0; s < nsl; ++s) {
+            int32_t len = 1;
+            for (int64_t r = s * kSellRows; r < std::min<int64_t>(hp.n_dofs, (s + 1) * kSellRows); ++r)
+                len = std::max(len, hp.row_ptr[r + 1] - hp.row_ptr[r]);
+            hp.sell_ptr[s] = (int32_t)off;
+            off += (int64_t)len * kSellRows;
+            if (off > INT32_MAX) {
+                msg = "the padded sliced-ELL pattern exceeds 2^31 entries";
+                return TG_E_ARG;
+            }
+        }
+        hp.sell_ptr[nsl] = (int32_t)off;
+        hp.sell_col.assign(off, 0);
+        for (int64_t s = 0; s < nsl; ++s) {
+            const int64_t len = (hp.sell_ptr[s + 1] - hp.sell_ptr[s]) / kSellRows;
+            for (int64_t l = 0; l < kSellRows; ++l) {
+                const int64_t r = s * kSellRows + l;
+                const int32_t p0 = r < hp.n_dofs ? hp.row_ptr[r] : 0, m = r < hp.n_dofs ? hp.row_ptr[r + 1] - p0 : 0;
+                for (int64_t q = 0; q < len; ++q)
+                    hp.sell_col[hp.sell_ptr[s] + q * kSellRows + l] =
+                        q < m ? hp.col_idx[p0 + q] : (int32_t)(r < hp.n_dofs ? r : 0);
+            }
+        }
+    }
+
     // ---- Dirichlet DoFs
     std::vector<uint8_t> cvert(nv, 0);
     std::vector<FaceKey> bfaces;

@@ -49,7 +49,7 @@ struct Request {
 };
 
 struct SlotMem {
-    void *values = nullptr, *b = nullptr, *work = nullptr;
+    void *values = nullptr, *sell = nullptr, *b = nullptr, *work = nullptr;
     double *partials = nullptr;
 };
 
@@ -100,9 +100,15 @@ namespace {
 
 const size_t kPartialBytes = (size_t)tg::kNumPartials * tg::kMaxGrid * sizeof(double);
 
+size_t slot_bytes(const tg_pattern *p, tg_dtype dtype) {
+    const size_t elt = dtype == TG_F64 ? 8 : 4, n = (size_t)p->host.n_dofs;
+    return ((size_t)p->host.nnz + (size_t)p->dev.sell_nnz + (1 + tg::kPcgWorkVectors) * n) * elt + kPartialBytes;
+}
+
 void free_group(Group &g) {
     for (SlotMem &m : g.mem) {
         (void)hipFree(m.values);
+        (void)hipFree(m.sell);
         (void)hipFree(m.b);
         (void)hipFree(m.work);
         (void)hipFree(m.partials);
@@ -135,8 +141,8 @@ tg_status make_group(tg_server *srv, const tg_pattern *p, tg_dtype dtype, Group 
     g->p = p;
     g->dtype = dtype;
     g->max_slots = srv->max_slots;
-    const size_t elt = dtype == TG_F64 ? 8 : 4, n = (size_t)p->host.n_dofs, S = (size_t)srv->max_slots;
-    g->slot_bytes = ((size_t)p->host.nnz + (1 + tg::kPcgWorkVectors) * n) * elt + kPartialBytes;
+    const size_t S = (size_t)srv->max_slots;
+    g->slot_bytes = slot_bytes(p, dtype);
     const size_t table = S * (sizeof(PcgSlot) + sizeof(PcgState) + 4 * sizeof(int32_t));
     hipError_t e = hipMalloc((void **)&g->d_slots, S * sizeof(PcgSlot));
     if (e == hipSuccess) e = hipMalloc((void **)&g->d_states, S * sizeof(PcgState));
@@ -167,11 +173,13 @@ int take_slot(tg_server *srv, Group &g, tg_status &st) {
     const size_t elt = g.dtype == TG_F64 ? 8 : 4, n = (size_t)g.p->host.n_dofs;
     SlotMem m;
     hipError_t e = hipMalloc(&m.values, std::max<size_t>(1, g.p->host.nnz) * elt);
+    if (e == hipSuccess) e = hipMalloc(&m.sell, std::max<size_t>(1, (size_t)g.p->dev.sell_nnz) * elt);
     if (e == hipSuccess) e = hipMalloc(&m.b, std::max<size_t>(1, n) * elt);
     if (e == hipSuccess) e = hipMalloc(&m.work, std::max<size_t>(1, tg::kPcgWorkVectors * n) * elt);
     if (e == hipSuccess) e = hipMalloc((void **)&m.partials, kPartialBytes);
     if (e != hipSuccess) {
         (void)hipFree(m.values);
+        (void)hipFree(m.sell);
         (void)hipFree(m.b);
         (void)hipFree(m.work);
         (void)hipFree(m.partials);
@@ -218,7 +226,7 @@ tg_status admit(tg_server *srv, Group &g, std::vector<int> &fresh) {
         g.busy[s] = 1;
         g.req[s] = *it;
         const SlotMem &m = g.mem[s];
-        g.h_slots[s] = PcgSlot{m.values, m.b, it->x, m.work, m.partials, g.d_states + s, it->rtol * it->rtol,
+        g.h_slots[s] = PcgSlot{m.values, m.sell, m.b, it->x, m.work, m.partials, g.d_states + s, it->rtol * it->rtol,
                                g.step, it->max_iter};
         g.h_states[s] = PcgState{};  // all zero: not done, no iterations
         g.h_status[s] = TG_STATUS_CLEAN;
@@ -248,6 +256,7 @@ tg_status admit(tg_server *srv, Group &g, std::vector<int> &fresh) {
         const SlotMem &m = g.mem[s];
         e = tg::launch_assemble(r.p, r.form, r.dtype, 1, r.coords, r.coef, r.load, m.values, m.b, g.d_status + s, str);
         if (e == hipSuccess) e = tg::launch_dirichlet(*r.p, r.dtype, m.values, m.b, r.g, str);
+        if (e == hipSuccess) e = tg::launch_sell_fill(*r.p, r.dtype, m.values, m.sell, str);
     }
     if (e == hipSuccess) e = tg::launch_pcg_init(*g.p, g.dtype, g.d_slots, g.d_lists + S, (int)fresh.size(), str);
     if (e != hipSuccess) return hip_fail(e, "server admission failed");
@@ -434,6 +443,14 @@ tg_status tg_server_poll(tg_server *srv, int32_t max_results, tg_server_result *
         srv->done.pop_front();
     }
     *n_out = k;
+    return tg::api_ok();
+}
+
+tg_status tg_server_slot_bytes(const tg_pattern *p, tg_dtype dtype, size_t *bytes) {
+    if (!p || !bytes) return tg::api_fail(TG_E_ARG, "NULL pattern or output");
+    if (p->host_only) return tg::api_fail(TG_E_STATE, "pattern was created with TG_PATTERN_HOST_ONLY");
+    if (dtype != TG_F64 && dtype != TG_F32) return tg::api_fail(TG_E_ARG, "invalid dtype");
+    *bytes = slot_bytes(p, dtype);
     return tg::api_ok();
 }
 

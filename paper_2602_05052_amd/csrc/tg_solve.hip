@@ -2,9 +2,9 @@
 // CSR system (TensorGalerkin Sec. B.1.2: Jacobi-preconditioned Krylov solve of
 // the condensed system, stopped on ||K u - f|| / ||f||).
 //
-// One CG iteration is one kernel of at most 512 blocks of 1024 threads (512
-// for small systems; the single-reduction form described with the PCG kernels
-// below).  Every scalar
+// One CG iteration is one kernel of 512-thread blocks, one wave per slice of 64
+// rows of a sliced-ELL copy of the matrix (the single-reduction form described
+// with the PCG kernels below).  Every scalar
 // (alpha, beta, the stop decision) is recomputed by every block from the
 // previous launch's per-block partials, summed in one fixed order, so all
 // blocks agree bitwise and the solver is reproducible with no atomics, no
@@ -105,20 +105,10 @@ __device__ __forceinline__ void block_sum3_first(double &a, double &b, double &c
     }
 }
 
-// Sums of three partial arrays [0 .. n), n <= kVecThreads, identical in every
-// block (the fixed order of block_sum3_first), with one barrier:
-// load_partials3 fetches this thread's entries, reduce_partials3 sums them.
+// Sums of three partial values per thread, identical in every block (the fixed
+// order of block_sum3_first), delivered to every thread with one barrier.
 // sh: 3 W doubles, not written again by the caller's block in this launch (no
 // barrier protects its later reuse).
-__device__ __forceinline__ void load_partials3(const double *__restrict__ p0, const double *__restrict__ p1,
-                                               const double *__restrict__ p2, int n, double &a, double &b,
-                                               double &c) {
-    const bool in = (int)threadIdx.x < n;
-    a = in ? p0[threadIdx.x] : 0.0;
-    b = in ? p1[threadIdx.x] : 0.0;
-    c = in ? p2[threadIdx.x] : 0.0;
-}
-
 template <int W = kWaves>
 __device__ __forceinline__ void reduce_partials3(double *sh, double &a, double &b, double &c) {
     a = wave_sum_last(a);
@@ -375,12 +365,8 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_init_spmv_kernel(int n, co
     }
 }
 
-// Iteration `it` of the system: stop test on r.r of the current iterate, then
-// the updates of every owned row and w = K u for them, with the partials of
-// the next iterate.  CHECK_ONLY launches stop after the test, and so does
-// iteration max_iter.  n_prev: number of partials written by the previous launch.
-// The slot of this launch's system: by value for a solo system (no dependent
-// load before its state), else through the batch's table.
+// The slot of a launch's system: by value for a solo system (no dependent load
+// before its state), else through the batch's table.
 template <bool SOLO>
 __device__ __forceinline__ PcgSlot pick_slot(const PcgSlot *__restrict__ slots, const int32_t *__restrict__ list,
                                              const PcgSlot &solo) {
@@ -390,19 +376,37 @@ __device__ __forceinline__ PcgSlot pick_slot(const PcgSlot *__restrict__ slots, 
         return slots[list[blockIdx.y]];
 }
 
-// TPB: threads per block (kVecThreads, or half of it for small systems, whose
-// grid at kVecThreads stays below kMaxGrid).  n_prev_init: blocks of the kernel
-// that formed iteration 0's partials (pcg_init_spmv_kernel, kVecThreads wide);
-// n_prev: blocks of this kernel at TPB.
-template <typename T, int G, bool CHECK_ONLY, bool SOLO, int TPB>
-__global__ __launch_bounds__(TPB, 8) void pcg_iter_kernel(int n, const int32_t *__restrict__ row_ptr,
-                                                       const int32_t *__restrict__ col_idx,
-                                                       const PcgSlot *__restrict__ slots,
-                                                       const int32_t *__restrict__ list, PcgSlot solo, int step,
-                                                       int n_prev_init, int n_prev) {
-    constexpr int W = TPB / 64;
+// Entries of a row fetched per round of the iteration kernel's SpMV (the first
+// round before the reduction of the previous partials).
+constexpr int kIterRound = 4;
+
+// Iteration `it` of the system: stop test on r.r of the current iterate, then
+// the updates of every owned row and w = K u for them, with the partials of
+// the next iterate.  CHECK_ONLY launches stop after the test, and so does
+// iteration max_iter.  n_prev: number of partials written by the previous
+// launch (n_prev_init for iteration 0, whose partials come from
+// pcg_init_spmv_kernel); both are at most kMaxGrid = 2 kIterThreads.
+//
+// The SpMV runs on the sliced-ELL copy of the values: each wave owns slices of
+// 64 consecutive rows, one row per lane, and step k of the wave reads entry k of
+// its 64 rows from 64 consecutive places (coalesced values and columns; on a
+// structured mesh the gathered records are consecutive too).  A row's products
+// are added in entry order, so the result does not depend on the launch.  The
+// operands of the first slice (row entries, the columns' records, the row's
+// own record, p and x) do not depend on alpha and beta: the first kIterRound
+// entries are fetched before the reduction of the previous partials, so their
+// latencies overlap it.
+template <typename T, bool CHECK_ONLY, bool SOLO>
+__global__ __launch_bounds__(kIterThreads) __attribute__((amdgpu_waves_per_eu(6)))
+void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const int32_t *__restrict__ sell_col,
+                     const PcgSlot *__restrict__ slots, const int32_t *__restrict__ list, PcgSlot solo, int step,
+                     int n_prev_init, int n_prev) {
+    constexpr int W = kIterThreads / 64;
+    constexpr int R = kIterRound;
+    static_assert(kMaxGrid <= 2 * kIterThreads, "two partials per thread");
     __shared__ double sh[3 * W];   // the previous partials' reduction
     __shared__ double sh2[3 * W];  // this launch's block sums
+    __shared__ double sst[4];
     const PcgSlot S = pick_slot<SOLO>(slots, list, solo);
     PcgState *__restrict__ st = S.state;
     const int it = step - S.start;
@@ -410,57 +414,55 @@ __global__ __launch_bounds__(TPB, 8) void pcg_iter_kernel(int n, const int32_t *
     const SlotVecs<T> v(S, n);
     const TG_GLOBAL Rec<T> *__restrict__ ra = v.rec(it & 1);
     TG_GLOBAL Rec<T> *__restrict__ rb = v.rec((it + 1) & 1);
-    const TG_GLOBAL T *__restrict__ values = gl((const T *)S.values);
+    const TG_GLOBAL T *__restrict__ sv = gl((const T *)S.sell);
     TG_GLOBAL T *__restrict__ x = gl((T *)S.x);
-    const int lane = threadIdx.x % G;
-    const int rows_per_grid = gridDim.x * (TPB / G);
-    const int i_first = blockIdx.x * (TPB / G) + threadIdx.x / G;
-    // Small systems (TPB below kVecThreads: at most a few blocks take a second
-    // row): this thread's first row's operands do not depend on alpha and beta,
-    // so they are fetched here, before the reduction, and their latencies
-    // overlap it: the row's bounds, its first kPre entries of this lane
-    // (column, value, the column's record) and the row's own record, p and x.
-    constexpr int kPre = (!CHECK_ONLY && TPB < kVecThreads) ? 2 : 0;
-    int f_p0 = 0, f_p1 = 0;
-    T f_val[kPre > 0 ? kPre : 1];
-    Rec<T> f_rec[kPre > 0 ? kPre : 1];
+    const int lane = threadIdx.x & 63;
+    const int waves = gridDim.x * W;
+    const int sl0 = blockIdx.x * W + (int)(threadIdx.x >> 6);  // this wave's first slice
+
+    // ---- operands of the first slice (clamped: a wave past the last slice
+    // fetches the last one, unused; entries past a row's padded length re-read
+    // its first entry, not added)
+    const int s0 = min(sl0, nsl - 1);
+    int e0 = 0, len0 = 0;
+    T f_val[R];
+    Rec<T> f_rec[R];
     Rec<T> f_o{};
     T f_pold = 0, f_xold = 0;
-    if constexpr (kPre > 0) {
-        const int i0 = min(i_first, n - 1);  // clamped: a thread past the end fetches row n-1, unused
-        f_p0 = row_ptr[i0];
-        f_p1 = row_ptr[i0 + 1];
+    if constexpr (!CHECK_ONLY) {
+        e0 = sell_ptr[s0] + lane;
+        len0 = (sell_ptr[s0 + 1] - sell_ptr[s0]) >> 6;
     }
-    // The previous launch's partials (threads below n_prev <= kMaxGrid), and the
-    // stop flag and scalars written by earlier launches (the same values for
-    // every wave), loaded by the block's last thread: their latencies overlap,
-    // and the reduction's barrier publishes the scalars through LDS.
-    static_assert(kMaxGrid <= TPB, "one partial per thread");
-    __shared__ double sst[4];
-    double rr_cur, gam, del;
-    load_partials3(part(S.partials, kRr + cur), part(S.partials, kGam + cur), part(S.partials, kDel + cur),
-                   it == 0 ? n_prev_init : n_prev, rr_cur, gam, del);
-    if (threadIdx.x == TPB - 1) {
+    // the previous launch's partials (two per thread) and, by the block's last
+    // thread, the stop flag and scalars of earlier launches; the reduction's
+    // barrier publishes them through LDS
+    const int np = it == 0 ? n_prev_init : n_prev;
+    const TG_GLOBAL double *p_rr = gl(part(S.partials, kRr + cur)), *p_gam = gl(part(S.partials, kGam + cur)),
+                           *p_del = gl(part(S.partials, kDel + cur));
+    const int t0 = threadIdx.x, t1 = threadIdx.x + kIterThreads;
+    double rr_cur = t0 < np ? p_rr[t0] : 0.0, gam = t0 < np ? p_gam[t0] : 0.0, del = t0 < np ? p_del[t0] : 0.0;
+    const double rr_1 = t1 < np ? p_rr[t1] : 0.0, gam_1 = t1 < np ? p_gam[t1] : 0.0, del_1 = t1 < np ? p_del[t1] : 0.0;
+    if (threadIdx.x == kIterThreads - 1) {
         sst[0] = (double)st->done;
         sst[1] = st->tol2;
         sst[2] = st->gamma[(it + 1) & 1];
         sst[3] = st->alpha[(it + 1) & 1];
     }
-    if constexpr (kPre > 0) {
-        const int i0 = min(i_first, n - 1);
+    if constexpr (!CHECK_ONLY) {
 #pragma unroll
-        for (int u = 0; u < kPre; ++u) {
-            const int q = f_p0 + lane + u * G;
-            const int qc = q < f_p1 ? q : f_p0;  // every row holds its diagonal: f_p0 is an entry
-            f_val[u] = values[qc];
-            f_rec[u] = load_rec(ra, col_idx[qc]);
+        for (int u = 0; u < R; ++u) {
+            const int q = e0 + 64 * min(u, len0 - 1);
+            f_val[u] = sv[q];
+            f_rec[u] = load_rec(ra, sell_col[q]);
         }
-        if (lane == 0) {
-            f_o = load_rec(ra, i0);
-            f_pold = v.p[i0];
-            f_xold = x[i0];
-        }
+        const int i0 = min(s0 * 64 + lane, n - 1);
+        f_o = load_rec(ra, i0);
+        f_pold = v.p[i0];
+        f_xold = x[i0];
     }
+    rr_cur += rr_1;
+    gam += gam_1;
+    del += del_1;
     reduce_partials3<W>(sh, rr_cur, gam, del);
     if (sst[0] != 0.0) return;
     const double tol2_prev = sst[1], gam_prev = sst[2], alpha_prev = sst[3];
@@ -496,7 +498,7 @@ __global__ __launch_bounds__(TPB, 8) void pcg_iter_kernel(int n, const int32_t *
     }
     const T alpha = (T)alpha_d, beta = (T)beta_d;
     double gn = 0.0, dn = 0.0, rn = 0.0;
-    // the row's update by its group's lane 0, from its own record, p, x and w = (K u)_i
+    // row i's update from its own record, p, x and w = (K u)_i
     auto update_row = [&](int i, double acc, const Rec<T> &o, T p_old, T x_old) {
         const T pi = o.d * o.r + beta * p_old;  // u_i + beta p
         const T si = next_s(o, beta);
@@ -510,53 +512,62 @@ __global__ __launch_bounds__(TPB, 8) void pcg_iter_kernel(int n, const int32_t *
         dn += (double)wi * (double)ui;
         rn += (double)ri * (double)ri;
     };
-    int i_start = i_first;
-    if constexpr (kPre > 0) {
-        if (i_first < n) {
-            double acc = 0.0;
+    // entries [k0, len) of a row, starting at q = e + 64 k0, in rounds of R
+    auto row_tail = [&](int e, int k0, int len, double acc) {
+        for (int k = k0; k < len; k += R) {
+            T val[R];
+            Rec<T> rc[R];
 #pragma unroll
-            for (int u = 0; u < kPre; ++u)
-                if (f_p0 + lane + u * G < f_p1) acc += (double)f_val[u] * (double)next_u(f_rec[u], beta, alpha);
-            for (int q = f_p0 + lane + kPre * G; q < f_p1; q += G)  // rows longer than kPre G entries
-                acc += (double)values[q] * (double)next_u(load_rec(ra, col_idx[q]), beta, alpha);
-            acc = group_sum<G>(acc);
-            if (lane == 0) update_row(i_first, acc, f_o, f_pold, f_xold);
-        }
-        i_start += rows_per_grid;
-    }
-    for (int i = i_start; i < n; i += rows_per_grid) {
-        const int p0 = row_ptr[i], p1 = row_ptr[i + 1];
-        // the row's own record, p and x do not depend on the SpMV: fetch them first
-        // (up to 16 lanes per row; wider groups need the registers for the SpMV)
-        constexpr bool kEarly = G <= 16;
-        Rec<T> o{};
-        T p_old = 0, x_old = 0;
-        if (kEarly && lane == 0) {
-            o = load_rec(ra, i);
-            p_old = v.p[i];
-            x_old = x[i];
-        }
-        double acc = 0.0;
-#pragma unroll 2
-        for (int q = p0 + lane; q < p1; q += G) {
-            const int j = col_idx[q];
-            acc += (double)values[q] * (double)next_u(load_rec(ra, j), beta, alpha);
-        }
-        acc = group_sum<G>(acc);
-        if (lane == 0) {
-            if (!kEarly) {
-                o = load_rec(ra, i);
-                p_old = v.p[i];
-                x_old = x[i];
+            for (int u = 0; u < R; ++u) {
+                const int q = e + 64 * min(k + u, len - 1);
+                val[u] = sv[q];
+                rc[u] = load_rec(ra, sell_col[q]);
             }
-            update_row(i, acc, o, p_old, x_old);
+#pragma unroll
+            for (int u = 0; u < R; ++u)
+                if (k + u < len) acc += (double)val[u] * (double)next_u(rc[u], beta, alpha);
         }
+        return acc;
+    };
+    if (sl0 < nsl) {
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+            if (u < len0) acc += (double)f_val[u] * (double)next_u(f_rec[u], beta, alpha);
+        acc = row_tail(e0, R, len0, acc);
+        const int i = sl0 * 64 + lane;
+        if (i < n) update_row(i, acc, f_o, f_pold, f_xold);
+    }
+    for (int sl = sl0 + waves; sl < nsl; sl += waves) {  // systems with more slices than waves
+        const int e = sell_ptr[sl] + lane, len = (sell_ptr[sl + 1] - sell_ptr[sl]) >> 6;
+        const int i = sl * 64 + lane;
+        const int ic = min(i, n - 1);
+        const Rec<T> o = load_rec(ra, ic);
+        const T p_old = v.p[ic], x_old = x[ic];
+        const double acc = row_tail(e, 0, len, 0.0);
+        if (i < n) update_row(i, acc, o, p_old, x_old);
     }
     block_sum3_first<W>(gn, dn, rn, sh2);
     if (threadIdx.x == 0) {
         part(S.partials, kGam + nxt)[blockIdx.x] = gn;
         part(S.partials, kDel + nxt)[blockIdx.x] = dn;
         part(S.partials, kRr + nxt)[blockIdx.x] = rn;
+    }
+}
+
+// The sliced-ELL copy of CSR values: one wave per slice, lane l on row 64 s + l;
+// padding entries get 0.
+template <typename T>
+__global__ __launch_bounds__(kIterThreads) void sell_fill_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr,
+                                                                 const int32_t *__restrict__ row_ptr,
+                                                                 const T *__restrict__ values, T *__restrict__ sell) {
+    const int lane = threadIdx.x & 63;
+    for (int sl = blockIdx.x * (kIterThreads / 64) + (int)(threadIdx.x >> 6); sl < nsl;
+         sl += gridDim.x * (kIterThreads / 64)) {
+        const int e = sell_ptr[sl] + lane, len = (sell_ptr[sl + 1] - sell_ptr[sl]) >> 6;
+        const int i = sl * 64 + lane;
+        const int p0 = i < n ? row_ptr[i] : 0, m = i < n ? row_ptr[i + 1] - p0 : 0;
+        for (int k = 0; k < len; ++k) sell[e + 64 * k] = k < m ? values[p0 + k] : (T)0;
     }
 }
 
@@ -648,50 +659,42 @@ void launch_warm_init_t(const tg_pattern &pt, const PcgSlot *slots, const int32_
                        pt.dev.col_idx, slots, list);
 }
 
-// Threads per block of the iteration kernel: half of kVecThreads when the grid
-// at kVecThreads would stay below kMaxGrid (a small system: twice the blocks,
-// half the waves per barrier; measured 16% faster per FP64 iteration at 66k
-// rows), else kVecThreads (a grid-stride kernel at kMaxGrid blocks).
-template <int G>
-int iter_tpb(int64_t n) {
-    return n * G < (int64_t)kMaxGrid * kVecThreads ? kVecThreads / 2 : kVecThreads;
-}
-
-template <int G>
-int iter_blocks(int64_t n) {
-    const int64_t rows_per_block = iter_tpb<G>(n) / G;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxGrid, (n + rows_per_block - 1) / rows_per_block));
-}
-
-template <typename T, int G, int TPB>
-void launch_step_tpb(const tg_pattern &pt, const PcgSlot *slots, const int32_t *list, int count, int step,
-                     hipStream_t s, const PcgSlot *solo) {
-    const int n = (int)pt.host.n_dofs;
-    const int ns0 = spmv_blocks<G>(n), ns = iter_blocks<G>(n);
-    if (solo)
-        hipLaunchKernelGGL((pcg_iter_kernel<T, G, false, true, TPB>), dim3(ns, 1), dim3(TPB), 0, s, n, pt.dev.row_ptr,
-                           pt.dev.col_idx, slots, list, *solo, step, ns0, ns);
-    else
-        hipLaunchKernelGGL((pcg_iter_kernel<T, G, false, false, TPB>), dim3(ns, count), dim3(TPB), 0, s, n,
-                           pt.dev.row_ptr, pt.dev.col_idx, slots, list, PcgSlot{}, step, ns0, ns);
+// Blocks of the iteration kernel: one slice per wave, at most kMaxGrid blocks
+// (grid-stride over slices beyond).
+int iter_blocks(const tg_pattern &pt) {
+    const int64_t per = kIterThreads / 64;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxGrid, (pt.dev.n_slices + per - 1) / per));
 }
 
 template <typename T, int G>
 void launch_step_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *list, int count, int step,
                    hipStream_t s, const PcgSlot *solo) {
-    if (iter_tpb<G>(pt.host.n_dofs) == kVecThreads)
-        launch_step_tpb<T, G, kVecThreads>(pt, slots, list, count, step, s, solo);
+    const int n = (int)pt.host.n_dofs, nsl = (int)pt.dev.n_slices;
+    const int ns0 = spmv_blocks<G>(n), ns = iter_blocks(pt);
+    if (solo)
+        hipLaunchKernelGGL((pcg_iter_kernel<T, false, true>), dim3(ns, 1), dim3(kIterThreads), 0, s, n, nsl,
+                           pt.dev.sell_ptr, pt.dev.sell_col, slots, list, *solo, step, ns0, ns);
     else
-        launch_step_tpb<T, G, kVecThreads / 2>(pt, slots, list, count, step, s, solo);
+        hipLaunchKernelGGL((pcg_iter_kernel<T, false, false>), dim3(ns, count), dim3(kIterThreads), 0, s, n, nsl,
+                           pt.dev.sell_ptr, pt.dev.sell_col, slots, list, PcgSlot{}, step, ns0, ns);
 }
 
 template <typename T, int G>
 void launch_check_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *list, int count, int step,
                     hipStream_t s) {
     const int n = (int)pt.host.n_dofs;
-    hipLaunchKernelGGL((pcg_iter_kernel<T, G, true, false, kVecThreads>), dim3(1, count), dim3(kVecThreads), 0, s, n,
-                       pt.dev.row_ptr, pt.dev.col_idx, slots, list, PcgSlot{}, step, spmv_blocks<G>(n),
-                       iter_blocks<G>(n));
+    hipLaunchKernelGGL((pcg_iter_kernel<T, true, false>), dim3(1, count), dim3(kIterThreads), 0, s, n,
+                       (int)pt.dev.n_slices, pt.dev.sell_ptr, pt.dev.sell_col, slots, list, PcgSlot{}, step,
+                       spmv_blocks<G>(n), iter_blocks(pt));
+}
+
+template <typename T>
+hipError_t launch_sell_fill_t(const tg_pattern &pt, const void *values, void *sell, hipStream_t s) {
+    const int64_t per = kIterThreads / 64;
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(8192, (pt.dev.n_slices + per - 1) / per));
+    hipLaunchKernelGGL(sell_fill_kernel<T>, dim3(nb), dim3(kIterThreads), 0, s, (int)pt.host.n_dofs,
+                       (int)pt.dev.n_slices, pt.dev.sell_ptr, pt.dev.row_ptr, (const T *)values, (T *)sell);
+    return hipGetLastError();
 }
 
 template <typename T, int G>
@@ -732,6 +735,11 @@ hipError_t launch_spmv(const tg_pattern &p, tg_dtype dtype, const void *values, 
     return dtype == TG_F64 ? launch_spmv_g<double>(p, values, x, y, s) : launch_spmv_g<float>(p, values, x, y, s);
 }
 
+hipError_t launch_sell_fill(const tg_pattern &p, tg_dtype dtype, const void *values, void *sell, hipStream_t s) {
+    return dtype == TG_F64 ? launch_sell_fill_t<double>(p, values, sell, s)
+                           : launch_sell_fill_t<float>(p, values, sell, s);
+}
+
 hipError_t launch_pcg_init(const tg_pattern &p, tg_dtype dtype, const PcgSlot *slots, const int32_t *list, int count,
                            hipStream_t s) {
     if (count <= 0) return hipSuccess;
@@ -769,12 +777,18 @@ tg_status run_pcg(const tg_pattern &pt, tg_dtype dtype, const void *values, cons
             return TG_E_HIP;              \
         }                                 \
     } while (0)
+    if (pt.host.n_dofs == 0) {  // nothing to solve
+        if (iters) *iters = 0;
+        if (relres) *relres = 0.0;
+        return TG_OK;
+    }
     // The previous call ended with a stream synchronisation, so the pinned
     // staging copies are free to reuse.  Reset with copies, not memsets: a
     // caller may capture this stream.
     d.host_state->done = 0;
     d.host_state->iters = 0;
-    const PcgSlot slot{values, rhs, x, d.work, d.partials, d.state, rtol * rtol, 0, max_iter, warm ? 1 : 0};
+    TG_CHECK(launch_sell_fill(pt, dtype, values, d.sell_vals, s));
+    const PcgSlot slot{values, d.sell_vals, rhs, x, d.work, d.partials, d.state, rtol * rtol, 0, max_iter, warm ? 1 : 0};
     *d.host_pcg_slot = slot;
     TG_CHECK(hipMemcpyAsync(d.state, d.host_state, sizeof(PcgState), hipMemcpyHostToDevice, s));
     TG_CHECK(hipMemcpyAsync(d.pcg_slot, d.host_pcg_slot, sizeof(PcgSlot), hipMemcpyHostToDevice, s));

@@ -120,7 +120,8 @@ def test_server_budget_admission():
     d = meshgen.poisson_inputs(2, 20, seed=5)
     pat = tg.Pattern(d["conn"], len(d["coords"]))
     coords, a, f = _cuda(d["coords"]), _cuda(d["a"]), _cuda(d["f"])
-    slot = (pat.nnz + 10 * pat.n_dofs) * 8 + 7 * 512 * 8
+    slot = tg.server_slot_bytes(pat, torch.float64)
+    assert slot >= (pat.nnz + 10 * pat.n_dofs) * 8
     # too small for one slot: the request completes with TG_E_NOMEM
     srv = tg.Server(hbm_budget=slot // 2, max_slots=4)
     srv.submit(pat, tg.LAPLACE, coords, a, f)
