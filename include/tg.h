@@ -43,12 +43,15 @@ extern "C" {
 typedef enum {
     TG_OK = 0,
     TG_E_ARG = -1,        /* invalid argument (detected on the host, nothing enqueued) */
-    TG_E_DEGENERATE = -2, /* an element has det J == 0 (host-detected cases)          */
-    TG_E_NONFINITE = -3,  /* a non-finite value was found (host-detected cases)       */
+    TG_E_DEGENERATE = -2, /* a bad element: numerically singular (det J ~ 0) or with a */
+                          /* non-finite coefficient or load (server results)          */
+    TG_E_NONFINITE = -3,  /* a CG step length, inner product or residual is not finite */
     TG_E_NOMEM = -4,      /* hipMalloc or host allocation failed                      */
     TG_E_HIP = -5,        /* a HIP runtime call failed                                */
     TG_E_NOCONV = -6,     /* tg_pcg reached max_iter without meeting rtol             */
-    TG_E_STATE = -7       /* object in the wrong state (e.g. host-only pattern)       */
+    TG_E_STATE = -7,      /* object in the wrong state (e.g. host-only pattern)       */
+    TG_E_ACCURACY = -8    /* tg_pcg: the recursive residual met rtol but the true one  */
+                          /* stays above it (below the dtype's attainable accuracy)   */
 } tg_status;
 
 typedef enum { TG_F64 = 0, TG_F32 = 1 } tg_dtype;
@@ -93,7 +96,7 @@ typedef struct {
     int64_t n_blocks;          /* row blocks of the fused assembly kernel     */
     const int32_t *d_row_ptr;  /* device [n_dofs + 1], NULL if host-only     */
     const int32_t *d_col_idx;  /* device [nnz], NULL if host-only             */
-    size_t device_bytes;       /* device memory owned by the pattern          */
+    size_t device_bytes;       /* device memory owned by the pattern (host-only: what an upload would take) */
     int64_t n_slot;            /* length of the routing slot list             */
 } tg_pattern_info;
 
@@ -277,11 +280,21 @@ tg_status tg_spmv(const tg_pattern *p, tg_dtype dtype, const void *d_values, con
  *                     (>= 1); the host reads one chunk's state while the next
  *                     chunk runs, launches after convergence do nothing, and
  *                     the iteration count reported is exact regardless.
- *   iters, relres   : host outputs: iterations done, and the final TRUE
- *                     relative residual ||b - K x|| / ||b|| (eq. linres).
+ *   iters, relres   : host outputs: iterations done (all runs), and the final
+ *                     TRUE relative residual ||b - K x|| / ||b|| (eq. linres).
+ * TG_OK means the true residual met rtol.  When the recursive residual meets
+ * rtol but the true one does not (rounding in the recurrences, mostly FP32),
+ * CG restarts from the current x (residual replacement: r = b - K x formed
+ * with FP64 sums), at most 4 times and only while each restart at least halves
+ * the true residual; if it stays above rtol the call returns TG_E_ACCURACY
+ * (rtol is below what the dtype can reach: in FP32 the rounding of x alone
+ * leaves about 1e-7 to 1e-5 on Poisson and heat systems), with the best
+ * iterate in d_x.  The values are copied once per call into a sliced-ELL
+ * layout (64-row slices) that the iterations read.
  * Blocks until done (host syncs on `stream`).  Uses the pattern's own
  * workspace: calls on one pattern must not overlap.  Returns TG_E_NOCONV
- * (with the last iterate in d_x) if max_iter is reached.
+ * (with the last iterate in d_x) if max_iter is reached, TG_E_NONFINITE if a
+ * step length, inner product or the residual is not finite.
  */
 tg_status tg_pcg(const tg_pattern *p, tg_dtype dtype, const void *d_values, const void *d_rhs, void *d_x, double rtol,
                  int32_t max_iter, int32_t check_every, int32_t *iters, double *relres, void *stream);
@@ -326,7 +339,10 @@ tg_status tg_adjoint_p1(const tg_pattern *p, tg_form form, tg_dtype dtype, int32
  * with a_e = exp(log_a_e).  Per step: one SpMV with M, then Jacobi-PCG on
  * A = M + dt K(a) (both assembled once per call by the Map-Reduce kernels),
  * started from u^k (its constrained entries set to 0); the stop test is
- * ||r|| <= rtol ||M u^k|| as in tg_pcg.
+ * ||r|| <= rtol ||M u^k|| as in tg_pcg's recursive test (these solves do not
+ * restart on the true residual: in FP32 its floor, about 1e-5 at 256^2, is
+ * above the tolerances the gradients need, while the recursive test still
+ * resolves the smooth error components).
  *   d_coords  : device FP64 [n_vertices][dim].   d_log_a : device FP64 [n_elements].
  *   d_u0      : device [n_dofs] of dtype (entries on constrained DoFs enter M u^0).
  *   d_states  : device [nsteps+1][n_dofs] of dtype, out: row k = u^k (row 0 = u^0).
@@ -375,21 +391,34 @@ tg_status tg_heat_adjoint(const tg_pattern *p, tg_dtype dtype, const double *d_c
  * `stream` in every tg_server_step).  Each tg_server_step admits queued requests into free
  * slots (a slot is allocated when the server's HBM budget allows), runs
  * check_every CG iterations, then retires the converged systems (or those at
- * max_iter).  A request's solution and iteration count are bitwise the same as
- * a solo tg_assemble + tg_apply_dirichlet + tg_pcg of it: every slot's
- * reductions are its own, in the same fixed order.
+ * max_iter).  Queued requests are admitted oldest first across groups.  A
+ * request's solution and iteration count are bitwise the same as a solo
+ * tg_assemble + tg_apply_dirichlet + tg_pcg of it: every slot's reductions are
+ * its own, in the same fixed order, and a slot takes tg_pcg's decisions
+ * (including its restarts from x when the true residual is above rtol).
  *
- * Ownership: the server owns the slot buffers (freed by tg_server_destroy).
- * The caller owns every pointer of a request (coords, coef, load, g, x), which
- * must stay valid until the request's result has been polled, and the pattern,
- * which must outlive the server.  All work runs on `stream` (NULL: the default
- * stream); the server is not thread-safe.
+ * Memory: group tables, slots and the patterns the server builds
+ * (tg_server_submit_mesh) count against hbm_budget_bytes.  A request that
+ * needs memory the budget lacks first frees what no request uses, least
+ * recently used first (idle slots of other groups, groups without slots,
+ * cached patterns no request needs), else waits for running requests to
+ * finish; it fails with TG_E_NOMEM only if one slot of it (with the group's
+ * tables and its cached pattern) exceeds the whole budget.
+ *
+ * Ownership: the server owns the slot buffers and the patterns it builds
+ * (freed by tg_server_destroy or when evicted).  The caller owns every pointer
+ * of a request (coords, coef, load, g, x, and a mesh request's conn), which
+ * must stay valid until the request's result has been polled, and a pattern
+ * passed to tg_server_submit, which must outlive the server.  All work runs on
+ * `stream` (NULL: the default stream); the server is not thread-safe.
  */
 typedef struct tg_server tg_server; /* opaque */
 
 typedef struct {
     int64_t request_id;
-    int32_t status;      /* TG_OK, TG_E_NOCONV, TG_E_DEGENERATE (bad assembly), TG_E_NOMEM (budget too small) */
+    int32_t status;      /* TG_OK, TG_E_NOCONV, TG_E_DEGENERATE (bad element), TG_E_NONFINITE (non-finite
+                            CG scalars or residual), TG_E_NOMEM (one slot exceeds the budget), or a
+                            submit_mesh topology's tg_pattern_create status */
     int32_t iters;       /* CG iterations, as tg_pcg reports them */
     double relres;       /* true relative residual ||b - K x|| / ||b|| */
     int32_t bad_element; /* first numerically singular element, or -1 */
@@ -400,7 +429,11 @@ typedef struct {
 
 typedef struct {
     int64_t n_queued, n_active, n_slots, n_groups, n_results;
-    size_t hbm_used, hbm_budget;
+    size_t hbm_used, hbm_budget;          /* bytes counted against the budget, and the budget */
+    int64_t n_patterns;                   /* patterns the server holds for tg_server_submit_mesh */
+    int64_t n_pattern_builds;             /* pattern builds so far (cache misses) */
+    int64_t n_pattern_evictions;          /* cached patterns freed to make room */
+    double pattern_build_s;               /* host seconds spent building them */
 } tg_server_info;
 
 /* hbm_budget_bytes: cap on slot memory (tg_server_slot_bytes per slot);
@@ -415,6 +448,25 @@ tg_status tg_server_create(size_t hbm_budget_bytes, int32_t max_slots, int32_t c
 tg_status tg_server_submit(tg_server *srv, const tg_pattern *p, tg_form form, tg_dtype dtype, const double *d_coords,
                            const void *d_coef, const void *d_load, const void *d_g, void *d_x, double rtol,
                            int32_t max_iter, int64_t *request_id);
+
+/* Queue one request on a mesh given by its connectivity: the server keeps the
+ * CSR pattern of every topology it serves, keyed by (topology_key, dim,
+ * order, n_vertices, n_elements) -- topology_key is the caller's name for the
+ * connectivity, equal keys must mean equal connectivity -- and builds one on a
+ * miss (host build plus device upload, during a later tg_server_step, with
+ * homogeneous Dirichlet data on the whole boundary, as tg_pattern_create with
+ * TG_BOUNDARY_ALL).  Cached patterns count against the HBM budget and the least
+ * recently used one that no request needs is freed when memory is short.
+ * form: TG_LAPLACE or TG_MASS_LAPLACE (P1, scalar, dim 2 or 3) or
+ * TG_ELASTICITY (P2, dim 3); conn is host [n_elements][dim+1] and, like the
+ * device arrays, must stay valid until the request's result has been polled.
+ * A topology that tg_pattern_create rejects fails its requests with that
+ * status; a request that one slot cannot hold within the budget fails with
+ * TG_E_NOMEM. */
+tg_status tg_server_submit_mesh(tg_server *srv, int32_t dim, int64_t n_vertices, int64_t n_elements,
+                                const int32_t *conn, uint64_t topology_key, tg_form form, tg_dtype dtype,
+                                const double *d_coords, const void *d_coef, const void *d_load, void *d_x,
+                                double rtol, int32_t max_iter, int64_t *request_id);
 
 /* One scheduling round (blocks until its iterations are done).  Optional outputs: systems in flight, queued. */
 tg_status tg_server_step(tg_server *srv, int32_t *n_active, int32_t *n_queued);

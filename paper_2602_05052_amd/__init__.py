@@ -33,6 +33,7 @@ _lib = ctypes.CDLL(_LIB_PATH)
 # ---------------------------------------------------------------- C declarations
 
 TG_OK, TG_E_ARG, TG_E_DEGENERATE, TG_E_NONFINITE, TG_E_NOMEM, TG_E_HIP, TG_E_NOCONV, TG_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
+TG_E_ACCURACY = -8
 F64, F32 = 0, 1
 LAPLACE, MASS, ELASTICITY, MASS_LAPLACE = 0, 1, 2, 3
 BOUNDARY_ALL = -1
@@ -40,7 +41,7 @@ STATUS_CLEAN = 2 ** 31 - 1
 PATTERN_HOST_ONLY = 1
 
 _STATUS_NAMES = {0: "TG_OK", -1: "TG_E_ARG", -2: "TG_E_DEGENERATE", -3: "TG_E_NONFINITE", -4: "TG_E_NOMEM",
-                 -5: "TG_E_HIP", -6: "TG_E_NOCONV", -7: "TG_E_STATE"}
+                 -5: "TG_E_HIP", -6: "TG_E_NOCONV", -7: "TG_E_STATE", -8: "TG_E_ACCURACY"}
 
 
 class _Info(ctypes.Structure):
@@ -62,7 +63,9 @@ class ServerResult(ctypes.Structure):
 class _ServerInfo(ctypes.Structure):
     _fields_ = [("n_queued", ctypes.c_int64), ("n_active", ctypes.c_int64), ("n_slots", ctypes.c_int64),
                 ("n_groups", ctypes.c_int64), ("n_results", ctypes.c_int64), ("hbm_used", ctypes.c_size_t),
-                ("hbm_budget", ctypes.c_size_t)]
+                ("hbm_budget", ctypes.c_size_t), ("n_patterns", ctypes.c_int64),
+                ("n_pattern_builds", ctypes.c_int64), ("n_pattern_evictions", ctypes.c_int64),
+                ("pattern_build_s", ctypes.c_double)]
 
 
 _vp, _i32p, _i64, _i32 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64, ctypes.c_int32
@@ -101,6 +104,9 @@ _SIGS = {
     "tg_server_submit": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp,
                                         ctypes.c_double, _i32, ctypes.POINTER(_i64)]),
     "tg_server_step": (ctypes.c_int, [_vp, _i32p, _i32p]),
+    "tg_server_submit_mesh": (ctypes.c_int, [_vp, _i32, _i64, _i64, _vp, ctypes.c_uint64, ctypes.c_int,
+                                             ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_double, _i32,
+                                             ctypes.POINTER(_i64)]),
     "tg_server_poll": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ServerResult), _i32p]),
     "tg_server_query": (ctypes.c_int, [_vp, ctypes.POINTER(_ServerInfo)]),
     "tg_server_slot_bytes": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_size_t)]),
@@ -408,8 +414,10 @@ def spmv(pattern: Pattern, values, x, y=None, stream=None):
 
 
 def pcg(pattern: Pattern, values, rhs, rtol: float = 1e-8, max_iter: int = 10000, check_every: int = 10, x=None,
-        stream=None, raise_on_noconv: bool = True):
-    """Jacobi-PCG from x0 = 0 (tg_pcg).  Returns (x, iterations, true relative residual)."""
+        stream=None, raise_on_noconv: bool = True, return_status: bool = False):
+    """Jacobi-PCG from x0 = 0 (tg_pcg).  Returns (x, iterations, true relative residual).  With
+    raise_on_noconv=False, TG_E_NOCONV and TG_E_ACCURACY (rtol below the dtype's attainable true residual)
+    return the last iterate instead of raising; return_status adds the status as a fourth value."""
     torch = _torch()
     code = _dtype_code(values.dtype)
     if x is None:
@@ -420,9 +428,9 @@ def pcg(pattern: Pattern, values, rhs, rtol: float = 1e-8, max_iter: int = 10000
                      _dev(rhs, values.dtype, (pattern.n_dofs,), "rhs"), _dev(x, values.dtype, (pattern.n_dofs,), "x"),
                      float(rtol), int(max_iter), int(check_every), ctypes.byref(it), ctypes.byref(rr),
                      _stream_handle(stream))
-    if st != TG_OK and not (st == TG_E_NOCONV and not raise_on_noconv):
+    if st != TG_OK and not (st in (TG_E_NOCONV, TG_E_ACCURACY) and not raise_on_noconv):
         _check(st)
-    return x, it.value, rr.value
+    return (x, it.value, rr.value, st) if return_status else (x, it.value, rr.value)
 
 
 def adjoint_p1(pattern: Pattern, form: int, coords, coef, lam, u, w=None, scale: float = 1.0, dlogc=True,
@@ -565,6 +573,39 @@ class Server:
         self._keep[rid.value] = (pattern, coords, coef, load, g, x)
         return rid.value
 
+    def submit_mesh(self, conn, n_vertices: int, form: int, coords, coef, load, topology_key: int, x=None,
+                    rtol: float = 1e-8, max_iter: int = 10000, dtype=None) -> int:
+        """Queue a request on a mesh given by its connectivity (host int32 [E][dim+1]); the server builds and
+        caches its CSR pattern (Dirichlet on the whole boundary) under `topology_key` (equal keys must mean
+        equal connectivity)."""
+        import numpy as np
+        torch = _torch()
+        if dtype is None:
+            dtype = coef.dtype
+        code = _dtype_code(dtype)
+        tdt = _torch_dtype(code)
+        conn = np.ascontiguousarray(conn, dtype=np.int32)
+        E, dim = conn.shape[0], conn.shape[1] - 1
+        p2 = form == ELASTICITY
+        cp = _dev(coords, torch.float64, (int(n_vertices), dim), "coords")
+        if p2:
+            coef_p = _dev(coef, tdt, (2, E), "coef")
+            load_p = _dev(load, tdt, (E, 3), "load")
+        else:
+            coef_p = _dev(coef, tdt, (E,), "coef")
+            load_p = _dev(load, tdt, (E,), "load")
+        if x is None:
+            if p2:
+                raise ValueError("pass x (the P2 DoF count depends on the edges)")
+            x = torch.empty(int(n_vertices), dtype=tdt, device=coords.device)
+        xp = _dev(x, tdt, (x.numel(),), "x")
+        rid = ctypes.c_int64(0)
+        _check(_lib.tg_server_submit_mesh(self._h, dim, int(n_vertices), E, conn.ctypes.data_as(_vp), int(topology_key),
+                                          form, code, cp, coef_p, load_p, xp, float(rtol), int(max_iter),
+                                          ctypes.byref(rid)))
+        self._keep[rid.value] = (conn, coords, coef, load, None, x)
+        return rid.value
+
     def solution(self, request_id: int):
         return self._keep[request_id][5]
 
@@ -596,10 +637,15 @@ class Server:
             out.append(d)
         return out
 
-    def drain(self):
-        """Step until nothing is queued or in flight; returns every result."""
+    def drain(self, max_steps: int = 1_000_000):
+        """Step until nothing is queued or in flight; returns every result (RuntimeError after max_steps
+        scheduling rounds)."""
         res = []
+        steps = 0
         while self.pending():
+            if steps >= max_steps:
+                raise RuntimeError(f"server still busy after {max_steps} rounds: {self.info()}")
             self.step()
+            steps += 1
             res += self.poll()
         return res + self.poll()

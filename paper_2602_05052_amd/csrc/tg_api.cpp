@@ -48,6 +48,28 @@ void free_device(tg::DevicePattern &d) {
     d = tg::DevicePattern{};
 }
 
+// The host arrays a pattern uploads (host field, device field), one list for
+// the upload and for the byte count the request server plans with.
+#define TG_PATTERN_ARRAYS(X)                                                                                   \
+    X(conn, conn) X(inc_ptr, inc_ptr) X(inc, inc) X(blk_row, blk_row) X(blk_desc, blk_desc) X(blk_vert, blk_vert) \
+    X(pair_lv, pair_lv) X(node_rp, node_rp) X(node_ci, node_ci) X(seg_ptr, seg_ptr) X(slot, slot) X(ent16, ent16) \
+    X(slot8, slot8) X(row_ptr, row_ptr) X(col_idx, col_idx) X(diag_pos, diag_pos) X(constrained, constrained)    \
+    X(dirichlet_rows, dir_rows) X(sell_ptr, sell_ptr) X(sell_col, sell_col)
+
+template <typename V>
+size_t array_bytes(const std::vector<V> &h) {
+    return (h.size() ? h.size() : 1) * sizeof(V);
+}
+
+// Device bytes of the PCG workspace of a pattern: Krylov vectors, the sliced-ELL
+// copy of the values, partials, state, the solo slot and its list.
+size_t workspace_bytes(const tg::HostPattern &h) {
+    using namespace tg;
+    const int64_t sell_nnz = h.sell_ptr.empty() ? 0 : (int64_t)h.sell_ptr.back();
+    return (size_t)kPcgWorkVectors * h.n_dofs * sizeof(double) + (size_t)std::max<int64_t>(1, sell_nnz) * sizeof(double) +
+           (size_t)kNumPartials * kMaxGrid * sizeof(double) + sizeof(PcgState) + sizeof(PcgSlot) + sizeof(int32_t);
+}
+
 tg_status create_device(tg_pattern &pt) {
     using namespace tg;
     const HostPattern &h = pt.host;
@@ -55,27 +77,8 @@ tg_status create_device(tg_pattern &pt) {
     size_t bytes = 0;
     hipError_t e = hipGetDevice(&pt.device);
 #define TG_UP(vec, field) \
-    if (e == hipSuccess) e = upload(h.vec, &d.field, bytes)
-    TG_UP(conn, conn);
-    TG_UP(inc_ptr, inc_ptr);
-    TG_UP(inc, inc);
-    TG_UP(blk_row, blk_row);
-    TG_UP(blk_desc, blk_desc);
-    TG_UP(blk_vert, blk_vert);
-    TG_UP(pair_lv, pair_lv);
-    TG_UP(node_rp, node_rp);
-    TG_UP(node_ci, node_ci);
-    TG_UP(seg_ptr, seg_ptr);
-    TG_UP(slot, slot);
-    TG_UP(ent16, ent16);
-    TG_UP(slot8, slot8);
-    TG_UP(row_ptr, row_ptr);
-    TG_UP(col_idx, col_idx);
-    TG_UP(diag_pos, diag_pos);
-    TG_UP(constrained, constrained);
-    TG_UP(dirichlet_rows, dir_rows);
-    TG_UP(sell_ptr, sell_ptr);
-    TG_UP(sell_col, sell_col);
+    if (e == hipSuccess) e = upload(h.vec, &d.field, bytes);
+    TG_PATTERN_ARRAYS(TG_UP)
 #undef TG_UP
     d.n_dir_rows = (int64_t)h.dirichlet_rows.size();
     d.n_slices = h.sell_ptr.empty() ? 0 : (int64_t)h.sell_ptr.size() - 1;
@@ -120,7 +123,7 @@ tg_status create_device(tg_pattern &pt) {
         free_device(d);
         return fail(st, msg);
     }
-    d.bytes = bytes;
+    d.bytes = bytes;  // == device_bytes(h): the arrays above plus workspace_bytes(h)
     // lanes per row in the SpMV: about a quarter of the mean row length (two
     // entries per lane, more rows in flight per wave), power of two in [4, 32]
     const double mean_row = h.n_dofs ? (double)h.nnz / (double)h.n_dofs : 1.0;
@@ -134,6 +137,29 @@ tg_status create_device(tg_pattern &pt) {
 }
 
 bool valid_dtype(tg_dtype t) { return t == TG_F64 || t == TG_F32; }
+
+}  // namespace
+
+namespace tg {
+
+size_t device_bytes(const HostPattern &h) {
+    size_t bytes = 0;
+#define TG_SUM(vec, field) bytes += array_bytes(h.vec);
+    TG_PATTERN_ARRAYS(TG_SUM)
+#undef TG_SUM
+    return bytes + workspace_bytes(h);
+}
+
+tg_status upload_pattern(tg_pattern *p) {
+    if (!p || !p->host_only) return api_fail(TG_E_STATE, "pattern is already on the device");
+    const tg_status st = create_device(*p);
+    if (st == TG_OK) p->host_only = false;
+    return st;
+}
+
+}  // namespace tg
+
+namespace {
 
 tg_status check_device_pattern(const tg_pattern *p) {
     if (!p) return fail(TG_E_ARG, "pattern is NULL");
@@ -197,7 +223,7 @@ tg_status tg_pattern_query(const tg_pattern *p, tg_pattern_info *info) {
     info->n_blocks = h.n_blocks();
     info->d_row_ptr = p->dev.row_ptr;
     info->d_col_idx = p->dev.col_idx;
-    info->device_bytes = p->dev.bytes;
+    info->device_bytes = p->host_only ? tg::device_bytes(h) : p->dev.bytes;
     info->n_slot = (int64_t)h.slot.size();
     return ok();
 }
@@ -465,7 +491,8 @@ tg_status heat_solve(const tg_pattern *p, tg_dtype dtype, const void *vals_a, vo
     double rr = 0.0;
     std::string msg;
     const tg_status st =
-        tg::run_pcg(*p, dtype, vals_a, rhs, x, rtol, max_iter, check_every, &it, &rr, s, msg, x0 != nullptr);
+        tg::run_pcg(*p, dtype, vals_a, rhs, x, rtol, max_iter, check_every, &it, &rr, s, msg, x0 != nullptr,
+                    /*strict=*/false);
     iters += it;
     if (rr > worst) worst = rr;
     if (st != TG_OK) return fail(st, msg);

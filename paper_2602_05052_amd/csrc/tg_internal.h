@@ -211,6 +211,10 @@ hipError_t launch_scaled_exp(tg_dtype dtype, int64_t n, double dt, const double 
 // holds a system on pattern p in dtype.  One launch per iteration (tg_solve.hip).
 hipError_t launch_pcg_init(const tg_pattern &p, tg_dtype dtype, const PcgSlot *slots, const int32_t *list, int count,
                            hipStream_t s);
+// Warm start of the listed slots from their x (which holds the initial guess):
+// r = b - K x, p = s = 0, w = K u, and the stop test relative to ||b||.
+hipError_t launch_pcg_warm_init(const tg_pattern &p, tg_dtype dtype, const PcgSlot *slots, const int32_t *list,
+                                int count, hipStream_t s);
 // With solo (a host copy of the one slot of a solo solve), the iteration kernel
 // takes the slot by value and slots/list are not read.
 hipError_t launch_pcg_step(const tg_pattern &p, tg_dtype dtype, const PcgSlot *slots, const int32_t *list, int count,
@@ -218,6 +222,12 @@ hipError_t launch_pcg_step(const tg_pattern &p, tg_dtype dtype, const PcgSlot *s
 // Per-block partials of ||b - K x||^2 into each listed slot's RR partials; returns the block count.
 hipError_t launch_pcg_residual(const tg_pattern &p, tg_dtype dtype, const PcgSlot *slots, const int32_t *list,
                                int count, int *n_partials, hipStream_t s);
+// Device bytes a host-only pattern takes once uploaded (arrays and PCG
+// workspace, as tg_pattern_create allocates them), and its upload (the
+// request server builds patterns on the host first and uploads them when
+// they fit its budget).
+size_t device_bytes(const HostPattern &h);
+tg_status upload_pattern(tg_pattern *p);
 // ABI helpers shared by the entry-point files (tg_api.cpp): the thread's last
 // error message, pattern and argument checks, and the assembly dispatch.
 tg_status api_fail(tg_status st, const std::string &msg);
@@ -228,9 +238,24 @@ tg_status validate_assemble(const tg_pattern *p, tg_form form, tg_dtype dtype, i
 hipError_t launch_assemble(const tg_pattern *p, tg_form form, tg_dtype dtype, int32_t nbatch, const double *d_coords,
                            const void *d_coef, const void *d_load, void *d_values, void *d_rhs, int32_t *d_status,
                            hipStream_t s);
-// Runs the whole PCG; returns TG_OK / TG_E_NOCONV / TG_E_HIP with *msg on failure.
-// warm: x holds the initial guess (else x0 = 0); the stop test is ||r|| <= rtol ||b|| either way.
+// How a CG run ends.  A run stops on the recursive residual (||r_k|| <= rtol
+// ||b||); then the true relative residual ||b - K x|| / ||b|| is checked.  Above
+// rtol, the run is restarted from its x (residual replacement) while iterations
+// remain, at most kPcgRestarts times, and only while each restart at least
+// halves the true residual: when it does not, rtol is below what the dtype
+// can reach (in FP32 the rounding of x alone leaves a relative residual of
+// about 1e-7 to 1e-5 on Poisson and heat systems) and the run ends with
+// kAccuracy.  The solo solver and the request server take the same decisions.
+constexpr int kPcgRestarts = 4;
+enum class RunEnd { kOk, kRestart, kNoConv, kAccuracy, kNonFinite };
+RunEnd run_end(bool done, double relres, double prev_relres, double rtol, bool nonfinite, int run, int total,
+               int max_iter);
+bool state_finite(const PcgState &st);  // every scalar of the state is finite
+// Runs the whole PCG; returns TG_OK / TG_E_NOCONV / TG_E_ACCURACY / TG_E_NONFINITE / TG_E_HIP with *msg
+// on failure.  warm: x holds the initial guess (else x0 = 0); the stop test is ||r|| <= rtol ||b|| either
+// way.  strict: check the true residual and restart as run_end says; otherwise one run, stopped on the
+// recursive residual (relres still reports the true one).
 tg_status run_pcg(const tg_pattern &p, tg_dtype dtype, const void *values, const void *rhs, void *x, double rtol,
                   int32_t max_iter, int32_t check_every, int32_t *iters, double *relres, hipStream_t s,
-                  std::string &msg, bool warm = false);
+                  std::string &msg, bool warm = false, bool strict = true);
 }  // namespace tg

@@ -13,7 +13,7 @@
 #include <cmath>
 #include <vector>
 
-#include "tg_internal.h"
+#include "tg_device.h"
 
 namespace tg {
 namespace {
@@ -255,8 +255,8 @@ __device__ __forceinline__ void store_rec(TG_GLOBAL Rec<T> *__restrict__ a, int 
     q->v[3] = d;
 }
 
-// The one definition of the recurrences, shared by a row's owner and by every
-// block that needs the row's new u as an SpMV column.
+// The recurrences of a row's s, r and u: the owner's update, and (FP32
+// iterations) every neighbour's view of the row's new u as an SpMV column.
 template <typename T>
 __device__ __forceinline__ T next_s(const Rec<T> &o, T beta) { return o.w + beta * o.s; }
 template <typename T>
@@ -289,9 +289,10 @@ template <typename T, int G>
 __global__ __launch_bounds__(kVecThreads, 8) void pcg_warm_init_kernel(int n, const int32_t *__restrict__ row_ptr,
                                                                     const int32_t *__restrict__ col_idx,
                                                                     const PcgSlot *__restrict__ slots,
+                                                                    const int32_t *__restrict__ list,
                                                                     const int32_t *__restrict__ diag_pos) {
     __shared__ double sh[kWaves];
-    const PcgSlot S = *slots;
+    const PcgSlot S = slots[list[blockIdx.y]];
     const SlotVecs<T> v(S, n);
     const TG_GLOBAL T *__restrict__ b = gl((const T *)S.b);
     const TG_GLOBAL T *__restrict__ values = gl((const T *)S.values);
@@ -313,9 +314,10 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_warm_init_kernel(int n, co
 }
 
 // Warm start: b.b from the n_prev partials -> state bb and tol2 = rtol^2 b.b.
-__global__ __launch_bounds__(kVecThreads) void pcg_warm_tol_kernel(const PcgSlot *__restrict__ slots, int n_prev) {
+__global__ __launch_bounds__(kVecThreads) void pcg_warm_tol_kernel(const PcgSlot *__restrict__ slots,
+                                                                   const int32_t *__restrict__ list, int n_prev) {
     __shared__ double sh[kWaves];
-    const PcgSlot S = *slots;
+    const PcgSlot S = slots[list[blockIdx.y]];
     double bb = (int)threadIdx.x < n_prev ? part(S.partials, kResid)[threadIdx.x] : 0.0;
     bb = block_sum(bb, sh);
     if (threadIdx.x == 0) {
@@ -376,9 +378,84 @@ __device__ __forceinline__ PcgSlot pick_slot(const PcgSlot *__restrict__ slots, 
         return slots[list[blockIdx.y]];
 }
 
-// Entries of a row fetched per round of the iteration kernel's SpMV (the first
-// round before the reduction of the previous partials).
-constexpr int kIterRound = 4;
+// Entries of a row per round of the iteration kernel's SpMV (FP64 products,
+// FP32 new-u terms).
+constexpr int kIterRound = 3;
+constexpr int kIterRound32 = 4;
+
+// The three products of row i that give (K u_new)_i once alpha and beta are
+// known: with u_new = D r_new and r_new = r - alpha (w + beta s),
+//   K u_new = K D r - alpha (K D w + beta K D s),
+// and K D r, K D w, K D s need only the previous iterate's records.  Entries
+// [0, len) of the row start at q = e and stride 64 (sliced-ELL); each product
+// sums the row's terms in entry order.  The loop is software-pipelined: the
+// next round's columns and values are requested before this round's records
+// are consumed.
+template <typename T>
+__device__ __forceinline__ void row_products(const TG_GLOBAL T *__restrict__ sv, const int32_t *__restrict__ sell_col,
+                                             const TG_GLOBAL Rec<T> *__restrict__ ra, int e, int len, double &A,
+                                             double &B, double &C) {
+    constexpr int R = kIterRound;
+    int c[R];
+    T val[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        const int q = e + 64 * min(u, len - 1);  // clamped: entries past the row re-read its last one, unused
+        c[u] = sell_col[q];
+        val[u] = sv[q];
+    }
+    for (int k = 0; k < len; k += R) {
+        Rec<T> rc[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) rc[u] = load_rec(ra, c[u]);
+        int cn[R];
+        T vn[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int q = e + 64 * min(k + R + u, len - 1);
+            cn[u] = sell_col[q];
+            vn[u] = sv[q];
+        }
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+            if (k + u < len) {
+                const double vd = (double)val[u] * (double)rc[u].d;
+                A += vd * (double)rc[u].r;
+                B += vd * (double)rc[u].w;
+                C += vd * (double)rc[u].s;
+            }
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            c[u] = cn[u];
+            val[u] = vn[u];
+        }
+    }
+}
+
+// Entries [k0, len) of row i's (K u_new)_i with u_new of every column from its
+// previous record (next_u), in entry order and rounds of kIterRound32 (the FP32
+// iterations: u_new in FP32, products and sum in FP64).
+template <typename T>
+__device__ __forceinline__ double row_tail_new_u(const TG_GLOBAL T *__restrict__ sv,
+                                                 const int32_t *__restrict__ sell_col,
+                                                 const TG_GLOBAL Rec<T> *__restrict__ ra, int e, int k0, int len,
+                                                 T alpha, T beta, double acc) {
+    constexpr int R = kIterRound32;
+    for (int k = k0; k < len; k += R) {
+        T val[R];
+        Rec<T> rc[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int q = e + 64 * min(k + u, len - 1);
+            val[u] = sv[q];
+            rc[u] = load_rec(ra, sell_col[q]);
+        }
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+            if (k + u < len) acc += (double)val[u] * (double)next_u(rc[u], beta, alpha);
+    }
+    return acc;
+}
 
 // Iteration `it` of the system: stop test on r.r of the current iterate, then
 // the updates of every owned row and w = K u for them, with the partials of
@@ -390,19 +467,20 @@ constexpr int kIterRound = 4;
 // The SpMV runs on the sliced-ELL copy of the values: each wave owns slices of
 // 64 consecutive rows, one row per lane, and step k of the wave reads entry k of
 // its 64 rows from 64 consecutive places (coalesced values and columns; on a
-// structured mesh the gathered records are consecutive too).  A row's products
-// are added in entry order, so the result does not depend on the launch.  The
-// operands of the first slice (row entries, the columns' records, the row's
-// own record, p and x) do not depend on alpha and beta: the first kIterRound
-// entries are fetched before the reduction of the previous partials, so their
-// latencies overlap it.
+// structured mesh the gathered records are consecutive too).  In FP64 its
+// three products (row_products) do not depend on alpha and beta, so they run
+// before the reduction of the previous partials, whose loads are issued first
+// and whose latency the SpMV hides.  In FP32 (where three FP64 products per
+// entry cost more than they hide) the first kIterRound32 entries and their
+// records are fetched before the reduction and the new u of each column is
+// formed after it.  Waves own slices in XCD-contiguous ranges (neighbouring
+// rows' records stay in one L2).
 template <typename T, bool CHECK_ONLY, bool SOLO>
 __global__ __launch_bounds__(kIterThreads) __attribute__((amdgpu_waves_per_eu(6)))
 void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const int32_t *__restrict__ sell_col,
                      const PcgSlot *__restrict__ slots, const int32_t *__restrict__ list, PcgSlot solo, int step,
                      int n_prev_init, int n_prev) {
     constexpr int W = kIterThreads / 64;
-    constexpr int R = kIterRound;
     static_assert(kMaxGrid <= 2 * kIterThreads, "two partials per thread");
     __shared__ double sh[3 * W];   // the previous partials' reduction
     __shared__ double sh2[3 * W];  // this launch's block sums
@@ -418,21 +496,8 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
     TG_GLOBAL T *__restrict__ x = gl((T *)S.x);
     const int lane = threadIdx.x & 63;
     const int waves = gridDim.x * W;
-    const int sl0 = blockIdx.x * W + (int)(threadIdx.x >> 6);  // this wave's first slice
+    const int sl0 = xcd_swizzle(blockIdx.x, gridDim.x) * W + (int)(threadIdx.x >> 6);  // this wave's first slice
 
-    // ---- operands of the first slice (clamped: a wave past the last slice
-    // fetches the last one, unused; entries past a row's padded length re-read
-    // its first entry, not added)
-    const int s0 = min(sl0, nsl - 1);
-    int e0 = 0, len0 = 0;
-    T f_val[R];
-    Rec<T> f_rec[R];
-    Rec<T> f_o{};
-    T f_pold = 0, f_xold = 0;
-    if constexpr (!CHECK_ONLY) {
-        e0 = sell_ptr[s0] + lane;
-        len0 = (sell_ptr[s0 + 1] - sell_ptr[s0]) >> 6;
-    }
     // the previous launch's partials (two per thread) and, by the block's last
     // thread, the stop flag and scalars of earlier launches; the reduction's
     // barrier publishes them through LDS
@@ -441,28 +506,47 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
                            *p_del = gl(part(S.partials, kDel + cur));
     const int t0 = threadIdx.x, t1 = threadIdx.x + kIterThreads;
     double rr_cur = t0 < np ? p_rr[t0] : 0.0, gam = t0 < np ? p_gam[t0] : 0.0, del = t0 < np ? p_del[t0] : 0.0;
-    const double rr_1 = t1 < np ? p_rr[t1] : 0.0, gam_1 = t1 < np ? p_gam[t1] : 0.0, del_1 = t1 < np ? p_del[t1] : 0.0;
+    rr_cur += t1 < np ? p_rr[t1] : 0.0;
+    gam += t1 < np ? p_gam[t1] : 0.0;
+    del += t1 < np ? p_del[t1] : 0.0;
     if (threadIdx.x == kIterThreads - 1) {
         sst[0] = (double)st->done;
         sst[1] = st->tol2;
         sst[2] = st->gamma[(it + 1) & 1];
         sst[3] = st->alpha[(it + 1) & 1];
     }
+    // the first slice's SpMV products, then the row's own record, p and x (their
+    // latency overlaps the reduction).  A wave that finds the system already
+    // converged skips the products (launches after convergence cost little); a
+    // stale flag only costs the work, and the decision below is taken on the
+    // published flag and partials.
+    constexpr bool kSplit = sizeof(T) == 8;
+    constexpr int R32 = kIterRound32;
+    const int s0 = min(sl0, nsl - 1);
+    const int i0 = min(s0 * 64 + lane, n - 1);
+    Rec<T> f_o{};
+    T f_pold = 0, f_xold = 0;
+    double A = 0.0, B = 0.0, C = 0.0;
+    int e0 = 0, len0 = 0;
+    T f_val[kSplit ? 1 : R32];
+    Rec<T> f_rec[kSplit ? 1 : R32];
     if constexpr (!CHECK_ONLY) {
+        e0 = sell_ptr[s0] + lane;
+        len0 = (sell_ptr[s0 + 1] - sell_ptr[s0]) >> 6;
+        if constexpr (kSplit) {
+            if (sl0 < nsl && st->done == 0) row_products(sv, sell_col, ra, e0, len0, A, B, C);
+        } else {
 #pragma unroll
-        for (int u = 0; u < R; ++u) {
-            const int q = e0 + 64 * min(u, len0 - 1);
-            f_val[u] = sv[q];
-            f_rec[u] = load_rec(ra, sell_col[q]);
+            for (int u = 0; u < R32; ++u) {  // clamped: entries past the row re-read its last one, unused
+                const int q = e0 + 64 * min(u, len0 - 1);
+                f_val[u] = sv[q];
+                f_rec[u] = load_rec(ra, sell_col[q]);
+            }
         }
-        const int i0 = min(s0 * 64 + lane, n - 1);
         f_o = load_rec(ra, i0);
         f_pold = v.p[i0];
         f_xold = x[i0];
     }
-    rr_cur += rr_1;
-    gam += gam_1;
-    del += del_1;
     reduce_partials3<W>(sh, rr_cur, gam, del);
     if (sst[0] != 0.0) return;
     const double tol2_prev = sst[1], gam_prev = sst[2], alpha_prev = sst[3];
@@ -498,13 +582,13 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
     }
     const T alpha = (T)alpha_d, beta = (T)beta_d;
     double gn = 0.0, dn = 0.0, rn = 0.0;
-    // row i's update from its own record, p, x and w = (K u)_i
-    auto update_row = [&](int i, double acc, const Rec<T> &o, T p_old, T x_old) {
+    // row i's update from its own record, p, x and w = (K u_new)_i
+    auto update_row = [&](int i, double w, const Rec<T> &o, T p_old, T x_old) {
         const T pi = o.d * o.r + beta * p_old;  // u_i + beta p
         const T si = next_s(o, beta);
         const T ri = next_r(o, si, alpha);
         const T ui = o.d * ri;
-        const T wi = (T)acc;
+        const T wi = (T)w;
         x[i] = x_old + alpha * pi;
         v.p[i] = pi;
         store_rec(rb, i, ri, wi, si, o.d);
@@ -512,40 +596,34 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
         dn += (double)wi * (double)ui;
         rn += (double)ri * (double)ri;
     };
-    // entries [k0, len) of a row, starting at q = e + 64 k0, in rounds of R
-    auto row_tail = [&](int e, int k0, int len, double acc) {
-        for (int k = k0; k < len; k += R) {
-            T val[R];
-            Rec<T> rc[R];
-#pragma unroll
-            for (int u = 0; u < R; ++u) {
-                const int q = e + 64 * min(k + u, len - 1);
-                val[u] = sv[q];
-                rc[u] = load_rec(ra, sell_col[q]);
-            }
-#pragma unroll
-            for (int u = 0; u < R; ++u)
-                if (k + u < len) acc += (double)val[u] * (double)next_u(rc[u], beta, alpha);
-        }
-        return acc;
-    };
     if (sl0 < nsl) {
-        double acc = 0.0;
+        double w;
+        if constexpr (kSplit) {
+            w = A - alpha_d * (B + beta_d * C);
+        } else {
+            w = 0.0;
 #pragma unroll
-        for (int u = 0; u < R; ++u)
-            if (u < len0) acc += (double)f_val[u] * (double)next_u(f_rec[u], beta, alpha);
-        acc = row_tail(e0, R, len0, acc);
-        const int i = sl0 * 64 + lane;
-        if (i < n) update_row(i, acc, f_o, f_pold, f_xold);
+            for (int u = 0; u < R32; ++u)
+                if (u < len0) w += (double)f_val[u] * (double)next_u(f_rec[u], beta, alpha);
+            w = row_tail_new_u(sv, sell_col, ra, e0, R32, len0, alpha, beta, w);
+        }
+        if (s0 * 64 + lane < n) update_row(s0 * 64 + lane, w, f_o, f_pold, f_xold);
     }
     for (int sl = sl0 + waves; sl < nsl; sl += waves) {  // systems with more slices than waves
-        const int e = sell_ptr[sl] + lane, len = (sell_ptr[sl + 1] - sell_ptr[sl]) >> 6;
         const int i = sl * 64 + lane;
         const int ic = min(i, n - 1);
         const Rec<T> o = load_rec(ra, ic);
         const T p_old = v.p[ic], x_old = x[ic];
-        const double acc = row_tail(e, 0, len, 0.0);
-        if (i < n) update_row(i, acc, o, p_old, x_old);
+        const int e = sell_ptr[sl] + lane, len = (sell_ptr[sl + 1] - sell_ptr[sl]) >> 6;
+        double w;
+        if constexpr (kSplit) {
+            double a = 0.0, b = 0.0, c = 0.0;
+            row_products(sv, sell_col, ra, e, len, a, b, c);
+            w = a - alpha_d * (b + beta_d * c);
+        } else {
+            w = row_tail_new_u(sv, sell_col, ra, e, 0, len, alpha, beta, 0.0);
+        }
+        if (i < n) update_row(i, w, o, p_old, x_old);
     }
     block_sum3_first<W>(gn, dn, rn, sh2);
     if (threadIdx.x == 0) {
@@ -649,13 +727,13 @@ void launch_init_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *li
 }
 
 template <typename T, int G>
-void launch_warm_init_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *list, hipStream_t s) {
+void launch_warm_init_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *list, int count, hipStream_t s) {
     const int n = (int)pt.host.n_dofs;
     const int ns = spmv_blocks<G>(n);
-    hipLaunchKernelGGL((pcg_warm_init_kernel<T, G>), dim3(ns), dim3(kVecThreads), 0, s, n, pt.dev.row_ptr,
-                       pt.dev.col_idx, slots, pt.dev.diag_pos);
-    hipLaunchKernelGGL(pcg_warm_tol_kernel, dim3(1), dim3(kVecThreads), 0, s, slots, ns);
-    hipLaunchKernelGGL((pcg_init_spmv_kernel<T, G>), dim3(ns, 1), dim3(kVecThreads), 0, s, n, pt.dev.row_ptr,
+    hipLaunchKernelGGL((pcg_warm_init_kernel<T, G>), dim3(ns, count), dim3(kVecThreads), 0, s, n, pt.dev.row_ptr,
+                       pt.dev.col_idx, slots, list, pt.dev.diag_pos);
+    hipLaunchKernelGGL(pcg_warm_tol_kernel, dim3(1, count), dim3(kVecThreads), 0, s, slots, list, ns);
+    hipLaunchKernelGGL((pcg_init_spmv_kernel<T, G>), dim3(ns, count), dim3(kVecThreads), 0, s, n, pt.dev.row_ptr,
                        pt.dev.col_idx, slots, list);
 }
 
@@ -724,6 +802,22 @@ auto dispatch(const tg_pattern &pt, tg_dtype dtype, F &&f) {
 
 }  // namespace
 
+bool state_finite(const PcgState &st) {
+    return std::isfinite(st.bb) && std::isfinite(st.alpha[0]) && std::isfinite(st.alpha[1]) &&
+           std::isfinite(st.gamma[0]) && std::isfinite(st.gamma[1]);
+}
+
+RunEnd run_end(bool done, double relres, double prev_relres, double rtol, bool nonfinite, int run, int total,
+               int max_iter) {
+    if (nonfinite || !std::isfinite(relres)) return RunEnd::kNonFinite;
+    if (!done) return RunEnd::kNoConv;
+    if (relres <= rtol) return RunEnd::kOk;
+    const bool progress = run == 0 || relres <= 0.5 * prev_relres;
+    if (!progress) return RunEnd::kAccuracy;
+    if (run < kPcgRestarts && total < max_iter) return RunEnd::kRestart;
+    return total < max_iter ? RunEnd::kAccuracy : RunEnd::kNoConv;
+}
+
 hipError_t launch_dirichlet(const tg_pattern &p, tg_dtype dtype, void *values, void *rhs, const void *g,
                             hipStream_t s) {
     return dtype == TG_F64 ? launch_dirichlet_t<double>(p, values, rhs, g, s)
@@ -747,6 +841,13 @@ hipError_t launch_pcg_init(const tg_pattern &p, tg_dtype dtype, const PcgSlot *s
     return hipGetLastError();
 }
 
+hipError_t launch_pcg_warm_init(const tg_pattern &p, tg_dtype dtype, const PcgSlot *slots, const int32_t *list,
+                                int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    dispatch(p, dtype, [&]<typename T, int G>() { launch_warm_init_t<T, G>(p, slots, list, count, s); });
+    return hipGetLastError();
+}
+
 hipError_t launch_pcg_step(const tg_pattern &p, tg_dtype dtype, const PcgSlot *slots, const int32_t *list, int count,
                            int step, hipStream_t s, const PcgSlot *solo) {
     if (count <= 0) return hipSuccess;
@@ -766,7 +867,7 @@ hipError_t launch_pcg_residual(const tg_pattern &p, tg_dtype dtype, const PcgSlo
 
 tg_status run_pcg(const tg_pattern &pt, tg_dtype dtype, const void *values, const void *rhs, void *x, double rtol,
                   int32_t max_iter, int32_t check_every, int32_t *iters, double *relres, hipStream_t s,
-                  std::string &msg, bool warm) {
+                  std::string &msg, bool warm, bool strict) {
     const DevicePattern &d = pt.dev;
     hipError_t err;
 #define TG_CHECK(call)                    \
@@ -782,64 +883,91 @@ tg_status run_pcg(const tg_pattern &pt, tg_dtype dtype, const void *values, cons
         if (relres) *relres = 0.0;
         return TG_OK;
     }
-    // The previous call ended with a stream synchronisation, so the pinned
-    // staging copies are free to reuse.  Reset with copies, not memsets: a
-    // caller may capture this stream.
-    d.host_state->done = 0;
-    d.host_state->iters = 0;
     TG_CHECK(launch_sell_fill(pt, dtype, values, d.sell_vals, s));
-    const PcgSlot slot{values, d.sell_vals, rhs, x, d.work, d.partials, d.state, rtol * rtol, 0, max_iter, warm ? 1 : 0};
-    *d.host_pcg_slot = slot;
-    TG_CHECK(hipMemcpyAsync(d.state, d.host_state, sizeof(PcgState), hipMemcpyHostToDevice, s));
-    TG_CHECK(hipMemcpyAsync(d.pcg_slot, d.host_pcg_slot, sizeof(PcgSlot), hipMemcpyHostToDevice, s));
-    if (warm) {
-        dispatch(pt, dtype, [&]<typename T, int G>() { launch_warm_init_t<T, G>(pt, d.pcg_slot, d.pcg_list, s); });
-        TG_CHECK(hipGetLastError());
-    } else {
-        TG_CHECK(launch_pcg_init(pt, dtype, d.pcg_slot, d.pcg_list, 1, s));
-    }
-    // Iterations go out in chunks of check_every, each followed by a copy of the
-    // state into one of two pinned mirrors and an event.  The host polls a chunk's
-    // state while the next chunk already runs, so the GPU never idles on the
-    // round trip; launches after convergence return at once (the stop test is
-    // taken on the device), so the result is the same as stopping exactly.
-    int it = 0;
-    auto chunk = [&](int buf) -> hipError_t {
-        for (int k = 0; k < check_every && it < max_iter; ++k, ++it) {
-            const hipError_t e = launch_pcg_step(pt, dtype, d.pcg_slot, d.pcg_list, 1, it, s, &slot);
-            if (e != hipSuccess) return e;
+    int total = 0;              // iterations of all runs
+    double prev_rel = INFINITY;  // the previous run's true residual
+    for (int run = 0;; ++run) {
+        // The previous run (or call) ended with a stream synchronisation, so the
+        // pinned staging copies are free to reuse.  Reset with copies, not
+        // memsets: a caller may capture this stream.
+        const int32_t budget = max_iter - total;
+        const bool warm_run = warm || run > 0;
+        d.host_state->done = 0;
+        d.host_state->iters = 0;
+        const PcgSlot slot{values, d.sell_vals, rhs, x, d.work, d.partials, d.state, rtol * rtol, 0, budget,
+                           warm_run ? 1 : 0};
+        *d.host_pcg_slot = slot;
+        TG_CHECK(hipMemcpyAsync(d.state, d.host_state, sizeof(PcgState), hipMemcpyHostToDevice, s));
+        TG_CHECK(hipMemcpyAsync(d.pcg_slot, d.host_pcg_slot, sizeof(PcgSlot), hipMemcpyHostToDevice, s));
+        if (warm_run) {
+            TG_CHECK(launch_pcg_warm_init(pt, dtype, d.pcg_slot, d.pcg_list, 1, s));
+        } else {
+            TG_CHECK(launch_pcg_init(pt, dtype, d.pcg_slot, d.pcg_list, 1, s));
         }
-        const hipError_t e = hipMemcpyAsync(d.host_state + buf, d.state, sizeof(PcgState), hipMemcpyDeviceToHost, s);
-        return e != hipSuccess ? e : hipEventRecord(d.poll_ev[buf], s);
-    };
-    TG_CHECK(chunk(0));
-    for (int cur = 0;; cur ^= 1) {
-        const bool more = it < max_iter;
-        if (more) TG_CHECK(chunk(cur ^ 1));
-        TG_CHECK(hipEventSynchronize(d.poll_ev[cur]));
-        if (d.host_state[cur].done || !more) break;
+        // Iterations go out in chunks of check_every, each followed by a copy of the
+        // state into one of two pinned mirrors and an event.  The host polls a chunk's
+        // state while the next chunk already runs, so the GPU never idles on the
+        // round trip; launches after convergence return at once (the stop test is
+        // taken on the device), so the result is the same as stopping exactly.  A
+        // non-finite step length or inner product ends the run.
+        int it = 0;
+        bool nonfinite = false;
+        auto chunk = [&](int buf) -> hipError_t {
+            for (int k = 0; k < check_every && it < budget; ++k, ++it) {
+                const hipError_t e = launch_pcg_step(pt, dtype, d.pcg_slot, d.pcg_list, 1, it, s, &slot);
+                if (e != hipSuccess) return e;
+            }
+            const hipError_t e =
+                hipMemcpyAsync(d.host_state + buf, d.state, sizeof(PcgState), hipMemcpyDeviceToHost, s);
+            return e != hipSuccess ? e : hipEventRecord(d.poll_ev[buf], s);
+        };
+        TG_CHECK(chunk(0));
+        for (int cur = 0;; cur ^= 1) {
+            const bool more = it < budget;
+            if (more) TG_CHECK(chunk(cur ^ 1));
+            TG_CHECK(hipEventSynchronize(d.poll_ev[cur]));
+            nonfinite = !state_finite(d.host_state[cur]);
+            if (d.host_state[cur].done || !more || nonfinite) break;
+        }
+        // stop test on the last update (sets done/iters if it converged)
+        dispatch(pt, dtype,
+                 [&]<typename T, int G>() { launch_check_t<T, G>(pt, d.pcg_slot, d.pcg_list, 1, it, s); });
+        int ns = 0;
+        TG_CHECK(launch_pcg_residual(pt, dtype, d.pcg_slot, d.pcg_list, 1, &ns, s));
+        std::vector<double> host_parts(ns);
+        TG_CHECK(hipMemcpyAsync(d.host_state, d.state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+        TG_CHECK(hipMemcpyAsync(host_parts.data(), d.partials + (size_t)kResid * kMaxGrid, sizeof(double) * ns,
+                                hipMemcpyDeviceToHost, s));
+        TG_CHECK(hipStreamSynchronize(s));
+        const bool done = d.host_state->done != 0;
+        double rr = 0.0;
+        for (double v : host_parts) rr += v;
+        const double bb = d.host_state->bb;
+        const double rel = bb > 0.0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+        total += done ? d.host_state->iters : std::min(it, budget);
+        if (iters) *iters = total;
+        if (relres) *relres = rel;
+        const bool bad = nonfinite || !state_finite(*d.host_state);
+        RunEnd end = run_end(done, rel, prev_rel, rtol, bad, run, total, max_iter);
+        if (!strict && (end == RunEnd::kRestart || end == RunEnd::kAccuracy)) end = RunEnd::kOk;
+        prev_rel = rel;
+        if (end == RunEnd::kRestart) continue;
+        if (end == RunEnd::kAccuracy) {
+            msg = "the recursive residual met rtol but the true residual stays above it (restarts from x no "
+                  "longer reduce it): rtol is below the attainable accuracy of this dtype";
+            return TG_E_ACCURACY;
+        }
+        if (end == RunEnd::kNonFinite) {
+            msg = "PCG met a non-finite value (check the matrix and right-hand side)";
+            return TG_E_NONFINITE;
+        }
+        if (end == RunEnd::kNoConv) {
+            msg = "PCG did not reach rtol within max_iter iterations";
+            return TG_E_NOCONV;
+        }
+        return TG_OK;
     }
-    // stop test on the last update (sets done/iters if it converged)
-    dispatch(pt, dtype, [&]<typename T, int G>() { launch_check_t<T, G>(pt, d.pcg_slot, d.pcg_list, 1, it, s); });
-    int ns = 0;
-    TG_CHECK(launch_pcg_residual(pt, dtype, d.pcg_slot, d.pcg_list, 1, &ns, s));
-    std::vector<double> host_parts(ns);
-    TG_CHECK(hipMemcpyAsync(d.host_state, d.state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-    TG_CHECK(hipMemcpyAsync(host_parts.data(), d.partials + (size_t)kResid * kMaxGrid, sizeof(double) * ns,
-                            hipMemcpyDeviceToHost, s));
-    TG_CHECK(hipStreamSynchronize(s));
 #undef TG_CHECK
-    const bool done = d.host_state->done != 0;
-    double rr = 0.0;
-    for (double v : host_parts) rr += v;
-    const double bb = d.host_state->bb;
-    if (iters) *iters = done ? d.host_state->iters : it;
-    if (relres) *relres = bb > 0.0 ? std::sqrt(rr / bb) : std::sqrt(rr);
-    if (!done) {
-        msg = "PCG did not reach rtol within max_iter iterations";
-        return TG_E_NOCONV;
-    }
-    return TG_OK;
 }
 
 }  // namespace tg

@@ -11,6 +11,7 @@ import scipy.sparse as sp
 
 import meshgen
 import oracle
+import special_meshes
 
 pytestmark = pytest.mark.gpu
 
@@ -343,3 +344,84 @@ def test_batched_argument_errors():
     st = tg._lib.tg_assemble_batched(pat.handle, tg.LAPLACE, tg.F64, 0, coords.data_ptr(), 8, None, 8, None, None,
                                      None)
     assert st == tg.TG_E_ARG
+
+
+# ---------------------------------------------------------------- blocks past the kernels' thread counts
+
+def _special(name):
+    return {"star255": lambda: special_meshes.sphere_star(255, 1),
+            "star170": lambda: special_meshes.sphere_star(170, 2),
+            "disjoint2": lambda: special_meshes.disjoint_simplices(2, 600, 3),
+            "disjoint3": lambda: special_meshes.disjoint_simplices(3, 400, 4)}[name]()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("mesh", ["star255", "star170", "disjoint2", "disjoint3"])
+def test_p1_blocks_beyond_thread_counts_parity(mesh, dtype):
+    """A row with 506 / 336 pairs, 256 CSR entries and more than 256 routing units (sphere stars: the Map of
+    pairs past the 256th thread and the routing and segment copies past it), and blocks of many one-pair
+    rows: Laplace, mass, M + K(c) and batched members against the oracle."""
+    d = _special(mesh)
+    print(f"p1 beyond-threads mesh={mesh} dtype={dtype}", flush=True)
+    _check_p1(d, dtype)
+    _check_p1(d, dtype, form=tg.MASS)
+    pat = tg.Pattern(d["conn"], len(d["coords"]))
+    coords = torch.from_numpy(d["coords"]).cuda()
+    c = 1e-2 * d["a"]
+    vals, rhs = tg.assemble(pat, tg.MASS_LAPLACE, coords, torch.from_numpy(c).to(dtype).cuda(),
+                            torch.from_numpy(d["f"]).to(dtype).cuda())
+    M = oracle.assemble_p1(d["coords"], d["conn"], form="mass").scipy()
+    A = oracle.assemble_p1(d["coords"], d["conn"], c, d["f"])
+    rp, ci = pat.csr()
+    K = sp.csr_matrix((vals.double().cpu().numpy(), ci, rp), shape=(A.n, A.n))
+    assert _norm_rel(K, M + A.scipy()) <= TOL[dtype]
+    E = len(d["conn"])
+    rng = np.random.default_rng(11)
+    a = torch.from_numpy(np.exp(rng.standard_normal((3, E)))).to(dtype).cuda()
+    f = torch.from_numpy(rng.uniform(-1, 1, (3, E))).to(dtype).cuda()
+    vb, rb = tg.assemble_batched(pat, tg.LAPLACE, coords, a, f)
+    for b in range(3):
+        v, r = tg.assemble(pat, tg.LAPLACE, coords, a[b].contiguous(), f[b].contiguous())
+        assert torch.equal(vb[b], v) and torch.equal(rb[b], r)
+    A2 = oracle.assemble_p1(d["coords"], d["conn"], a[2].double().cpu().numpy(), f[2].double().cpu().numpy())
+    K2 = sp.csr_matrix((vb[2].double().cpu().numpy(), ci, rp), shape=(A2.n, A2.n))
+    assert _norm_rel(K2, A2.scipy()) <= TOL[dtype]
+    assert _vec_rel(rb[2].double().cpu().numpy(), A2.rhs) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_p2_blocks_beyond_thread_counts_parity(dtype):
+    """P2 row blocks with 520 node entries and 208 staged vertices (the copies past 2 x 192 entries and
+    past 192 vertices)."""
+    print(f"p2 beyond-threads dtype={dtype}", flush=True)
+    _check_p2(special_meshes.disjoint_simplices(3, 120, 5), dtype)
+
+
+_P2_32 = {}
+
+
+def _p2_32cube_oracle():
+    if not _P2_32:
+        d = meshgen.elasticity_inputs(32, seed=0)
+        print("p2 32^3: the FP64 oracle assembly (about a minute on the host) ...", flush=True)
+        _P2_32["d"] = d
+        _P2_32["A"] = oracle.assemble_p2_elasticity(d["coords"], d["conn"], d["lam"], d["mu"], d["b"])
+    return _P2_32["d"], _P2_32["A"]
+
+
+@pytest.mark.timeout(600)  # the oracle's serial assembly of 69M entries takes about a minute on the host
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_p2_full_32cube_every_row(dtype):
+    """The 32^3 P2 matrix (69,108,489 entries) and load the elasticity benchmark times, against the oracle
+    normwise over every row (max absolute row sum), with an identical pattern."""
+    d, A = _p2_32cube_oracle()
+    print(f"p2 32^3 every row dtype={dtype}", flush=True)
+    pat, vals, rhs = _gpu_elasticity(d, dtype)
+    rp, ci = pat.csr()
+    np.testing.assert_array_equal(rp, A.row_ptr)
+    np.testing.assert_array_equal(ci, A.col_idx)
+    row = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    err = np.bincount(row, np.abs(vals - A.vals)).max() / np.bincount(row, np.abs(A.vals)).max()
+    print(f"p2 32^3 {dtype}: normwise {err:.3e}", flush=True)
+    assert err <= TOL[dtype], err
+    assert _vec_rel(rhs, A.rhs) <= TOL[dtype]

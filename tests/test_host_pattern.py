@@ -14,6 +14,7 @@ import pytest
 
 import meshgen
 import oracle
+import special_meshes
 
 tg = pytest.importorskip("paper_2602_05052_amd")
 
@@ -57,7 +58,32 @@ def _pair_of_slot(r, k):
 
 @pytest.mark.parametrize("dim,n", [(2, 1), (2, 7), (3, 1), (3, 4)])
 def test_p1_pattern_routing_equals_oracle(dim, n):
-    d = meshgen.poisson_inputs(dim, n, seed=1)
+    _replay_p1_against_oracle(meshgen.poisson_inputs(dim, n, seed=1), compact=True)
+
+
+@pytest.mark.parametrize("mesh", ["star255", "star170", "disjoint2", "disjoint3"])
+def test_p1_routing_beyond_thread_counts(mesh):
+    """Blocks past the P1 kernel's 256 threads: a row with 506 or 336 pairs and (506 pairs) 256 CSR
+    entries (257 wide segment pointers) and more than 256 four-slot routing units (sphere stars, the wide
+    routing); blocks of 85 and 63 one-pair rows (disjoint simplices, the compact routing).  The routing still reproduces the
+    oracle's scatter-add bit for bit."""
+    d = {"star255": lambda: special_meshes.sphere_star(255, 1), "star170": lambda: special_meshes.sphere_star(170, 2),
+         "disjoint2": lambda: special_meshes.disjoint_simplices(2, 600, 3),
+         "disjoint3": lambda: special_meshes.disjoint_simplices(3, 400, 4)}[mesh]()
+    pat = tg.Pattern(d["conn"], len(d["coords"]), host_only=True)
+    rows, pairs, ents, verts = special_meshes.block_shapes(pat)
+    assert verts.max() <= 256 and ents.max() <= 256
+    if mesh.startswith("star"):
+        k = 4
+        slot_units = -(-pairs.max() * (k - 1) // 4) + 1
+        assert pairs.max() > 256
+        if mesh == "star255":  # nent + 1 = 257 wide segment pointers, over 256 routing units
+            assert ents.max() == 256 and slot_units > 256
+    _replay_p1_against_oracle(d, compact=not mesh.startswith("star"))
+
+
+def _replay_p1_against_oracle(d, compact):
+    dim = d["coords"].shape[1]
     pat = tg.Pattern(d["conn"], len(d["coords"]), host_only=True)
     A = oracle.assemble_p1(d["coords"], d["conn"], d["a"], d["f"])
     rp, ci = pat.csr()
@@ -85,10 +111,11 @@ def test_p1_pattern_routing_equals_oracle(dim, n):
     vals[diag] = _sequential_segment_sum(Kl[r["inc"] // k, r["inc"] % k, r["inc"] % k], r["inc_ptr"])
     assert np.array_equal(vals, A.vals)  # bitwise
     # the compact routing the kernel reads names the same slots in the same order
-    assert pat.compact_routing() is not None
-    cvals = _compact_replay(pat, r, Kl, k)
-    cvals[diag] = vals[diag]
-    assert np.array_equal(cvals, A.vals)
+    assert (pat.compact_routing() is not None) == compact
+    if compact:
+        cvals = _compact_replay(pat, r, Kl, k)
+        cvals[diag] = vals[diag]
+        assert np.array_equal(cvals, A.vals)
     rhs = _sequential_segment_sum(Fl[r["inc"] // k, r["inc"] % k], r["inc_ptr"])
     assert np.array_equal(rhs, A.rhs)
     # pairs ascending by element inside every node
@@ -346,3 +373,12 @@ def test_p2_block_capacity(m, ok):
     else:
         with pytest.raises(tg.TGError, match="block capacity"):
             tg.Pattern(conn, m + 2, order=2, ncomp=3, host_only=True)
+
+
+def test_p2_blocks_beyond_thread_counts():
+    """Interleaved disjoint tets: P2 row blocks with more node entries (520) than two per thread of the
+    192-thread kernel and more staged vertices (208) than threads."""
+    d = special_meshes.disjoint_simplices(3, 120, 5)
+    pat = tg.Pattern(d["conn"], len(d["coords"]), order=2, ncomp=3, host_only=True)
+    rows, pairs, ents, verts = special_meshes.block_shapes(pat)
+    assert ents.max() > 2 * 192 - 1 and verts.max() > 192 and pairs.max() <= 64

@@ -273,3 +273,16 @@ def test_condensed_solve_residual():
     u = oracle.condensed_solve(A, bnd)
     assert oracle.relres_lin(A, u, bnd) < 1e-12
     assert np.all(u[bnd] == 0.0)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 9), (3, 5)])
+def test_parallel_oracle_bitwise_equals_serial(dim, n):
+    """The multi-core CPU baseline (OpenMP Map, per-row sums in ascending element order) gives the serial
+    element loop's values and load bit for bit, at any thread count."""
+    d = meshgen.poisson_inputs(dim, n, seed=3)
+    A = oracle.assemble_p1(d["coords"], d["conn"], d["a"], d["f"])
+    inc_ptr, inc = oracle.p1_incidence(len(d["coords"]), d["conn"])
+    for threads in (1, 3, 8):
+        v, r = oracle.assemble_p1_values_parallel(d["coords"], d["conn"], d["a"], d["f"], A.row_ptr, A.col_idx,
+                                                  inc_ptr, inc, threads)
+        assert np.array_equal(v, A.vals) and np.array_equal(r, A.rhs)
