@@ -40,11 +40,12 @@ class OracleError(RuntimeError):
 
 
 def build(force: bool = False) -> str:
-    """Compile tg_oracle.c into liboracle.so (gcc -O3, no fast-math)."""
+    """Compile tg_oracle.c into liboracle.so (gcc -O3, OpenMP for the multi-core baseline, no fast-math)."""
     with _lock:
         if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             tmp = _LIB + ".tmp%d" % os.getpid()
-            subprocess.check_call(["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+            subprocess.check_call(["gcc", "-O3", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC,
+                                   "-lm"])
             os.replace(tmp, _LIB)
     return _LIB
 
@@ -65,6 +66,9 @@ def _load():
         lib.oracle_free.argtypes = [ctypes.c_void_p]
         lib.oracle_assemble_p1.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, _dp, ctypes.c_int64, _i32p,
                                            _dp, _dp, _i64p, _i64p, _dp, _dp, _i64p]
+        lib.oracle_assemble_p1_parallel.argtypes = [ctypes.c_int, ctypes.c_int64, _dp, ctypes.c_int64, _i32p, _dp,
+                                                    _dp, _i64p, _i64p, _i64p, _i64p, _dp, _dp, _dp, _dp, ctypes.c_int,
+                                                    _i64p]
         lib.oracle_assemble_p2_elasticity.argtypes = [ctypes.c_int64, _dp, ctypes.c_int64, _i32p, _i64p, _dp, _dp,
                                                       _dp, _i64p, _i64p, _dp, _dp, _i64p]
         lib.oracle_p1_adjoint_element.argtypes = [ctypes.c_int, _dp, ctypes.c_double, _dp, _dp, _dp, ctypes.c_int,
@@ -234,6 +238,36 @@ def assemble_p1_values(coords, conn, a, f, row_ptr, col_idx):
                                     _ptr(_f64(a), _dp), _ptr(_f64(f), _dp), _ptr(row_ptr, _i64p),
                                     _ptr(col_idx, _i64p), _ptr(vals, _dp), _ptr(rhs, _dp), ctypes.byref(bad))
     _check(rc, "assemble_p1_values", bad.value)
+    return vals, rhs
+
+
+def p1_incidence(nv: int, conn):
+    """(inc_ptr [nv+1], inc): every vertex's (element e, local node a) pairs as codes e*k + a, in ascending e."""
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    E, k = conn.shape
+    codes = np.arange(E * k, dtype=np.int64)
+    order = np.argsort(conn.reshape(-1), kind="stable")  # stable: ascending code (so e) within a vertex
+    inc_ptr = np.zeros(nv + 1, dtype=np.int64)
+    np.cumsum(np.bincount(conn.reshape(-1), minlength=nv), out=inc_ptr[1:])
+    return inc_ptr, codes[order]
+
+
+def assemble_p1_values_parallel(coords, conn, a, f, row_ptr, col_idx, inc_ptr, inc, threads: int = 0):
+    """assemble_p1_values on several threads (OpenMP Map over elements, then per-row sums in ascending element
+    order): bitwise the same values and load as the serial element loop."""
+    coords = _f64(coords)
+    conn = np.ascontiguousarray(conn, dtype=np.int32)
+    nv, dim = coords.shape
+    E, k = conn.shape
+    vals = np.empty(col_idx.shape[0])
+    rhs = np.empty(nv)
+    ke, fe = np.empty(E * k * k), np.empty(E * k)
+    bad = ctypes.c_int64(-1)
+    rc = _load().oracle_assemble_p1_parallel(dim, nv, _ptr(coords, _dp), E, _ptr(conn, _i32p), _ptr(_f64(a), _dp),
+                                             _ptr(_f64(f), _dp), _ptr(row_ptr, _i64p), _ptr(col_idx, _i64p),
+                                             _ptr(inc_ptr, _i64p), _ptr(inc, _i64p), _ptr(ke, _dp), _ptr(fe, _dp),
+                                             _ptr(vals, _dp), _ptr(rhs, _dp), int(threads), ctypes.byref(bad))
+    _check(rc, "assemble_p1_values_parallel", bad.value)
     return vals, rhs
 
 

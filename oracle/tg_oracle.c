@@ -36,6 +36,7 @@
  *   CSR: sorted columns, both triangles, entries that cancel to 0 kept.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -413,6 +414,56 @@ int oracle_assemble_p1(int dim, int form, int64_t nv, const double *coords, int6
             for (int b = 0; b < k; ++b) vals[csr_find(row_ptr, col_idx, g[a], g[b])] += Ke[a * k + b];
             if (rhs && form == 0 && load) rhs[g[a]] += Fe[a];
         }
+    }
+    return ORC_OK;
+}
+
+/*
+ * The same P1 Laplace value and load assembly on several CPU threads, with the
+ * same additions in the same order as oracle_assemble_p1, so the result is
+ * bitwise identical to it (the multi-core CPU baseline):
+ *   Map    : every element's K_e and F_e (independent; elements split among
+ *            the threads) into Ke_all [E][k][k] and Fe_all [E][k];
+ *   Reduce : every row i (rows split among the threads) adds, for its incident
+ *            (element e, local node a) pairs in ascending e, K_e[a][b] into
+ *            entry (i, g_e(b)) and F_e[a] into rhs[i].  Entry (i, j) thus
+ *            receives its terms in ascending element order, exactly as the
+ *            serial element loop adds them.
+ * inc_ptr [nv+1] / inc [E k]: pair code e k + a of every row, ascending e.
+ * Ke_all and Fe_all are caller scratch; vals and rhs need not be zeroed.
+ * threads <= 0: the OpenMP default.
+ */
+int oracle_assemble_p1_parallel(int dim, int64_t nv, const double *coords, int64_t E, const int32_t *conn,
+                                const double *coef, const double *load, const int64_t *row_ptr,
+                                const int64_t *col_idx, const int64_t *inc_ptr, const int64_t *inc, double *Ke_all,
+                                double *Fe_all, double *vals, double *rhs, int threads, int64_t *bad)
+{
+    const int k = dim + 1;
+    int64_t first_bad = E;
+    if (threads <= 0) threads = omp_get_max_threads();
+#pragma omp parallel for num_threads(threads) schedule(static) reduction(min : first_bad)
+    for (int64_t e = 0; e < E; ++e) {
+        double X[4 * 3];
+        gather_vertices(dim, coords, conn + e * k, k, X);
+        if (oracle_p1_laplace_element(dim, X, coef[e], load ? load[e] : 0.0, Ke_all + e * k * k, Fe_all + e * k))
+            first_bad = e < first_bad ? e : first_bad;
+    }
+    if (first_bad < E) {
+        if (bad) *bad = first_bad;
+        return ORC_E_DEGENERATE;
+    }
+#pragma omp parallel for num_threads(threads) schedule(static)
+    for (int64_t i = 0; i < nv; ++i) {
+        for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) vals[q] = 0.0;
+        double fi = 0.0;
+        for (int64_t t = inc_ptr[i]; t < inc_ptr[i + 1]; ++t) {
+            const int64_t e = inc[t] / k;
+            const int a = (int)(inc[t] - e * k);
+            const int32_t *g = conn + e * k;
+            for (int b = 0; b < k; ++b) vals[csr_find(row_ptr, col_idx, i, g[b])] += Ke_all[(e * k + a) * k + b];
+            fi += Fe_all[e * k + a];
+        }
+        if (rhs) rhs[i] = load ? fi : 0.0;
     }
     return ORC_OK;
 }
