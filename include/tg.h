@@ -98,6 +98,7 @@ typedef struct {
     const int32_t *d_col_idx;  /* device [nnz], NULL if host-only             */
     size_t device_bytes;       /* device memory owned by the pattern (host-only: what an upload would take) */
     int64_t n_slot;            /* length of the routing slot list             */
+    size_t scratch_bytes;      /* the pattern's scratch grown by tg_adjoint_p1 / tg_heat_* (0 until used) */
 } tg_pattern_info;
 
 /* Text of the last error on the calling thread; valid until its next tg_ call. */
@@ -330,6 +331,26 @@ tg_status tg_pcg(const tg_pattern *p, tg_dtype dtype, const void *d_values, cons
 tg_status tg_adjoint_p1(const tg_pattern *p, tg_form form, tg_dtype dtype, int32_t nbatch, const double *d_coords,
                         const void *d_coef, const void *d_lam, const void *d_u, const void *d_w, int64_t stride,
                         double scale, double *d_dlogc, double *d_dcoords, int32_t *d_status, void *stream);
+
+/*
+ * tg_adjoint_p1 for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, kernels and results (bitwise), but the kernels'
+ * staging array [n_elements][dim+1][dim] of doubles lives in a fixed array of
+ * the library (2^22 doubles = 32 MiB on each GPU the library runs on, held
+ * until the process ends) instead of the pattern's scratch that tg_adjoint_p1
+ * grows with hipMalloc; this call allocates nothing and frees nothing.
+ * Limit: n_elements (dim+1) dim <= 4,194,304 (699,050 triangles or 349,525
+ * tetrahedra); beyond it TG_E_ARG.  Every call on one GPU shares the array and
+ * it keeps the last call's contents (each call overwrites the entries it
+ * reads): calls that overlap on one GPU (different streams or threads) race
+ * and give wrong results, so serialise them.  The current device must be the
+ * pattern's (else TG_E_STATE).  Other errors as tg_adjoint_p1.
+ */
+tg_status tg_adjoint_p1_noalloc(const tg_pattern *p, tg_form form, tg_dtype dtype, int32_t nbatch,
+                                const double *d_coords, const void *d_coef, const void *d_lam, const void *d_u,
+                                const void *d_w, int64_t stride, double scale, double *d_dlogc, double *d_dcoords,
+                                int32_t *d_status, void *stream);
 
 /*
  * Implicit-Euler rollout of the method-of-lines system M U' + K(a) U = 0

@@ -51,7 +51,7 @@ class _Info(ctypes.Structure):
                 ("n_dofs", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n_constrained", ctypes.c_int64),
                 ("n_blocks", ctypes.c_int64),
                 ("d_row_ptr", ctypes.c_void_p), ("d_col_idx", ctypes.c_void_p), ("device_bytes", ctypes.c_size_t),
-                ("n_slot", ctypes.c_int64)]
+                ("n_slot", ctypes.c_int64), ("scratch_bytes", ctypes.c_size_t)]
 
 
 class ServerResult(ctypes.Structure):
@@ -94,6 +94,8 @@ _SIGS = {
                               ctypes.POINTER(ctypes.c_double), _vp]),
     "tg_adjoint_p1": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i32, _vp, _vp, _vp, _vp, _vp, _i64,
                                      ctypes.c_double, _vp, _vp, _vp, _vp]),
+    "tg_adjoint_p1_noalloc": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i32, _vp, _vp, _vp, _vp, _vp, _i64,
+                                             ctypes.c_double, _vp, _vp, _vp, _vp]),
     "tg_heat_rollout": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_double, _i32, _vp, _vp,
                                        ctypes.c_double, _i32, _i32, ctypes.POINTER(_i64),
                                        ctypes.POINTER(ctypes.c_double), _vp, _vp]),
@@ -227,6 +229,12 @@ class Pattern:
         self.device_bytes = info.device_bytes
         self.n_slot = info.n_slot
         self.host_only = host_only
+
+    def scratch_bytes(self) -> int:
+        """Bytes of the pattern's scratch (grown by tg_adjoint_p1 / tg_heat_*; 0 until first used)."""
+        info = _Info()
+        _check(_lib.tg_pattern_query(self._h, ctypes.byref(info)))
+        return int(info.scratch_bytes)
 
     def __del__(self, _destroy=_lib.tg_pattern_destroy, _finalizing=sys.is_finalizing):
         h = getattr(self, "_h", None)

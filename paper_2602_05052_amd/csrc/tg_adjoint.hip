@@ -18,10 +18,12 @@
 // from d|T|/dx_v = |T| G_v and d(G_a)/dx_v = -G_v G_a^T (affine map).
 //
 // Kernel 1 (one lane per element) writes dPhi/dlog c_e and the k vertex
-// gradients of the element to a scratch array [E][k][d].  Kernel 2 (one lane
-// per vertex) is the S_vec-type Reduce of Alg. 2: it sums the scratch entries
+// gradients of the element to a staging array [E][k][d].  Kernel 2 (one lane
+// per vertex) is the S_vec-type Reduce of Alg. 2: it sums the staged entries
 // of the vertex's incident (element, local vertex) pairs in ascending element
 // order, so the result is bitwise reproducible and needs no atomics.
+#include <mutex>
+
 #include "tg_device.h"
 
 namespace tg {
@@ -33,7 +35,7 @@ template <int D, typename T, int FORM>
 __global__ __launch_bounds__(kAdjThreads) void p1_adjoint_element_kernel(
     const int32_t *__restrict__ conn, const double *__restrict__ coords, const T *__restrict__ coef,
     const T *__restrict__ lam, const T *__restrict__ u, const T *__restrict__ w, unsigned stride, int nbatch,
-    unsigned n_elem, double scale, double *__restrict__ dlogc, double *__restrict__ scratch,
+    unsigned n_elem, double scale, double *__restrict__ dlogc, double *__restrict__ stage,
     int32_t *__restrict__ status) {
     constexpr int K = D + 1;
     constexpr bool HAS_K = FORM != TG_MASS;           // A contains K(c)
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(kAdjThreads) void p1_adjoint_element_kernel(
             double q = 0.0;
 #pragma unroll
             for (int j = 0; j < D; ++j) q += (Pc[i][j] + Pc[j][i]) * C[a][j];
-            stg(scratch, (e * K + a) * D + i, scale * rd * (diag * C[a][i] - kfac * q));
+            stg(stage, (e * K + a) * D + i, scale * rd * (diag * C[a][i] - kfac * q));
         }
     }
 }
@@ -133,7 +135,7 @@ __global__ __launch_bounds__(kAdjThreads) void p1_adjoint_element_kernel(
 template <int D>
 __global__ __launch_bounds__(kAdjThreads) void vertex_reduce_kernel(const int32_t *__restrict__ inc_ptr,
                                                                     const int32_t *__restrict__ inc,
-                                                                    const double *__restrict__ scratch, unsigned nv,
+                                                                    const double *__restrict__ stage, unsigned nv,
                                                                     double *__restrict__ out) {
     const unsigned v = blockIdx.x * kAdjThreads + threadIdx.x;
     if (v >= nv) return;
@@ -144,7 +146,7 @@ __global__ __launch_bounds__(kAdjThreads) void vertex_reduce_kernel(const int32_
     for (int q = p0; q < p1; ++q) {
         const unsigned code = (unsigned)ldg(inc, (unsigned)q);
 #pragma unroll
-        for (int i = 0; i < D; ++i) acc[i] += ldg(scratch, code * D + i);
+        for (int i = 0; i < D; ++i) acc[i] += ldg(stage, code * D + i);
     }
 #pragma unroll
     for (int i = 0; i < D; ++i) stg(out, v * D + i, acc[i]);
@@ -160,32 +162,32 @@ __global__ __launch_bounds__(kAdjThreads) void scaled_exp_kernel(unsigned n, dou
 template <int D, typename T, int FORM>
 hipError_t launch_adjoint_t(const tg_pattern &p, int nbatch, const double *coords, const void *coef,
                             const void *lam, const void *u, const void *w, int64_t stride, double scale,
-                            double *dlogc, double *dcoords, double *scratch, int32_t *status, hipStream_t s) {
+                            double *dlogc, double *dcoords, double *stage, int32_t *status, hipStream_t s) {
     const unsigned E = (unsigned)p.host.E, nv = (unsigned)p.host.nv;
     if (E > 0)
         hipLaunchKernelGGL((p1_adjoint_element_kernel<D, T, FORM>), dim3((E + kAdjThreads - 1) / kAdjThreads),
                            dim3(kAdjThreads), 0, s, p.dev.conn, coords, (const T *)coef, (const T *)lam,
-                           (const T *)u, (const T *)w, (unsigned)stride, nbatch, E, scale, dlogc, scratch, status);
+                           (const T *)u, (const T *)w, (unsigned)stride, nbatch, E, scale, dlogc, stage, status);
     if (dcoords && nv > 0)
         hipLaunchKernelGGL(vertex_reduce_kernel<D>, dim3((nv + kAdjThreads - 1) / kAdjThreads), dim3(kAdjThreads), 0,
-                           s, p.dev.inc_ptr, p.dev.inc, scratch, nv, dcoords);
+                           s, p.dev.inc_ptr, p.dev.inc, stage, nv, dcoords);
     return hipGetLastError();
 }
 
 template <int D, typename T>
 hipError_t launch_adjoint_d(const tg_pattern &p, tg_form form, int nbatch, const double *coords, const void *coef,
                             const void *lam, const void *u, const void *w, int64_t stride, double scale,
-                            double *dlogc, double *dcoords, double *scratch, int32_t *status, hipStream_t s) {
+                            double *dlogc, double *dcoords, double *stage, int32_t *status, hipStream_t s) {
     switch (form) {
         case TG_LAPLACE:
             return launch_adjoint_t<D, T, TG_LAPLACE>(p, nbatch, coords, coef, lam, u, w, stride, scale, dlogc,
-                                                      dcoords, scratch, status, s);
+                                                      dcoords, stage, status, s);
         case TG_MASS:
             return launch_adjoint_t<D, T, TG_MASS>(p, nbatch, coords, coef, lam, u, w, stride, scale, dlogc, dcoords,
-                                                   scratch, status, s);
+                                                   stage, status, s);
         case TG_MASS_LAPLACE:
             return launch_adjoint_t<D, T, TG_MASS_LAPLACE>(p, nbatch, coords, coef, lam, u, w, stride, scale, dlogc,
-                                                           dcoords, scratch, status, s);
+                                                           dcoords, stage, status, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -194,20 +196,46 @@ hipError_t launch_adjoint_d(const tg_pattern &p, tg_form form, int nbatch, const
 
 hipError_t launch_adjoint_p1(const tg_pattern &p, tg_form form, tg_dtype dtype, int nbatch, const double *coords,
                              const void *coef, const void *lam, const void *u, const void *w, int64_t stride,
-                             double scale, double *dlogc, double *dcoords, double *scratch, int32_t *status,
+                             double scale, double *dlogc, double *dcoords, double *stage, int32_t *status,
                              hipStream_t s) {
     if (p.host.dim == 2) {
         if (dtype == TG_F64)
             return launch_adjoint_d<2, double>(p, form, nbatch, coords, coef, lam, u, w, stride, scale, dlogc,
-                                               dcoords, scratch, status, s);
+                                               dcoords, stage, status, s);
         return launch_adjoint_d<2, float>(p, form, nbatch, coords, coef, lam, u, w, stride, scale, dlogc, dcoords,
-                                          scratch, status, s);
+                                          stage, status, s);
     }
     if (dtype == TG_F64)
         return launch_adjoint_d<3, double>(p, form, nbatch, coords, coef, lam, u, w, stride, scale, dlogc, dcoords,
-                                           scratch, status, s);
+                                           stage, status, s);
     return launch_adjoint_d<3, float>(p, form, nbatch, coords, coef, lam, u, w, stride, scale, dlogc, dcoords,
-                                      scratch, status, s);
+                                      stage, status, s);
+}
+
+// The staging array of the allocation-free adjoint entry point: a file-scope
+// device array, so each GPU the library runs on holds its own copy from the
+// library's load until the process ends, and no call allocates.  Host code
+// never uses the array's name as an address (on the host it is only a stand-in
+// symbol): each device's address comes from hipGetSymbolAddress, called once
+// per device with that device current.
+static __device__ __align__(256) double scratch[kNoAllocStageDoubles];
+
+hipError_t noalloc_stage(double **out) {
+    static std::mutex mu;
+    static double *addr[kNoAllocMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<double *>(p);
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_scaled_exp(tg_dtype dtype, int64_t n, double dt, const double *x, void *y, hipStream_t s) {

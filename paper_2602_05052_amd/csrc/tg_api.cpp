@@ -224,6 +224,7 @@ tg_status tg_pattern_query(const tg_pattern *p, tg_pattern_info *info) {
     info->d_row_ptr = p->dev.row_ptr;
     info->d_col_idx = p->dev.col_idx;
     info->device_bytes = p->host_only ? tg::device_bytes(h) : p->dev.bytes;
+    info->scratch_bytes = p->host_only ? 0 : p->dev.ws_bytes;
     info->n_slot = (int64_t)h.slot.size();
     return ok();
 }
@@ -416,6 +417,30 @@ tg_status tg_pcg(const tg_pattern *p, tg_dtype dtype, const void *d_values, cons
 
 namespace {
 
+bool p1_scalar(const tg_pattern *p) { return p->host.order == 1 && p->host.ncomp == 1; }
+
+// Argument checks shared by tg_adjoint_p1 and tg_adjoint_p1_noalloc.
+tg_status check_adjoint(const tg_pattern *p, tg_form form, tg_dtype dtype, int32_t nbatch, const double *d_coords,
+                        const void *d_coef, const void *d_lam, const void *d_u, int64_t stride, const double *d_dlogc,
+                        const double *d_dcoords) {
+    tg_status st = check_device_pattern(p);
+    if (st != TG_OK) return st;
+    if (!valid_dtype(dtype)) return fail(TG_E_ARG, "invalid dtype");
+    if (!p1_scalar(p)) return fail(TG_E_ARG, "tg_adjoint_p1 needs a P1 scalar pattern (order 1, ncomp 1)");
+    if (form != TG_LAPLACE && form != TG_MASS && form != TG_MASS_LAPLACE) return fail(TG_E_ARG, "invalid form");
+    if (!d_coords || !d_lam || !d_u) return fail(TG_E_ARG, "d_coords, d_lam and d_u are required");
+    if (form != TG_MASS && !d_coef) return fail(TG_E_ARG, "this form needs d_coef");
+    if (!d_dlogc && !d_dcoords) return fail(TG_E_ARG, "nothing to compute: d_dlogc and d_dcoords are NULL");
+    const tg::HostPattern &h = p->host;
+    if (nbatch < 1) return fail(TG_E_ARG, "nbatch must be >= 1");
+    if (stride < h.n_dofs) return fail(TG_E_ARG, "stride must be >= n_dofs");
+    const uint64_t elt = dtype == TG_F64 ? 8 : 4, lim = (uint64_t)1 << 32;
+    if (((uint64_t)(nbatch - 1) * stride + h.n_dofs) * elt >= lim || (uint64_t)h.E * h.k * h.dim * 8 >= lim ||
+        (uint64_t)h.nv * h.dim * 8 >= lim)
+        return fail(TG_E_ARG, "an array of this call exceeds 4 GiB, beyond the kernels' 32-bit offsets");
+    return TG_OK;
+}
+
 // Grows the pattern's scratch to at least `bytes` (previous contents are lost).
 tg_status ensure_workspace(const tg_pattern *p, size_t bytes) {
     tg::DevicePattern &d = const_cast<tg_pattern *>(p)->dev;
@@ -442,8 +467,6 @@ struct Carve {
         return at;
     }
 };
-
-bool p1_scalar(const tg_pattern *p) { return p->host.order == 1 && p->host.ncomp == 1; }
 
 tg_status check_heat(const tg_pattern *p, tg_dtype dtype, const double *d_coords, const double *d_log_a, double dt,
                      int32_t nsteps, double rtol, int32_t max_iter, int32_t check_every) {
@@ -506,26 +529,39 @@ extern "C" {
 tg_status tg_adjoint_p1(const tg_pattern *p, tg_form form, tg_dtype dtype, int32_t nbatch, const double *d_coords,
                         const void *d_coef, const void *d_lam, const void *d_u, const void *d_w, int64_t stride,
                         double scale, double *d_dlogc, double *d_dcoords, int32_t *d_status, void *stream) {
-    tg_status st = check_device_pattern(p);
+    tg_status st = check_adjoint(p, form, dtype, nbatch, d_coords, d_coef, d_lam, d_u, stride, d_dlogc, d_dcoords);
     if (st != TG_OK) return st;
-    if (!valid_dtype(dtype)) return fail(TG_E_ARG, "invalid dtype");
-    if (!p1_scalar(p)) return fail(TG_E_ARG, "tg_adjoint_p1 needs a P1 scalar pattern (order 1, ncomp 1)");
-    if (form != TG_LAPLACE && form != TG_MASS && form != TG_MASS_LAPLACE) return fail(TG_E_ARG, "invalid form");
-    if (!d_coords || !d_lam || !d_u) return fail(TG_E_ARG, "d_coords, d_lam and d_u are required");
-    if (form != TG_MASS && !d_coef) return fail(TG_E_ARG, "this form needs d_coef");
-    if (!d_dlogc && !d_dcoords) return fail(TG_E_ARG, "nothing to compute: d_dlogc and d_dcoords are NULL");
     const tg::HostPattern &h = p->host;
-    if (nbatch < 1) return fail(TG_E_ARG, "nbatch must be >= 1");
-    if (stride < h.n_dofs) return fail(TG_E_ARG, "stride must be >= n_dofs");
-    const uint64_t elt = dtype == TG_F64 ? 8 : 4, lim = (uint64_t)1 << 32;
-    if (((uint64_t)(nbatch - 1) * stride + h.n_dofs) * elt >= lim || (uint64_t)h.E * h.k * h.dim * 8 >= lim ||
-        (uint64_t)h.nv * h.dim * 8 >= lim)
-        return fail(TG_E_ARG, "an array of this call exceeds 4 GiB, beyond the kernels' 32-bit offsets");
     st = ensure_workspace(p, std::max<size_t>(256, (size_t)h.E * h.k * h.dim * sizeof(double)));
     if (st != TG_OK) return st;
     const hipError_t e =
         tg::launch_adjoint_p1(*p, form, dtype, nbatch, d_coords, d_coef, d_lam, d_u, d_w, stride, scale, d_dlogc,
                               d_dcoords, (double *)p->dev.ws, d_status, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(TG_E_HIP, std::string("adjoint launch failed: ") + hipGetErrorString(e));
+    return ok();
+}
+
+tg_status tg_adjoint_p1_noalloc(const tg_pattern *p, tg_form form, tg_dtype dtype, int32_t nbatch,
+                                const double *d_coords, const void *d_coef, const void *d_lam, const void *d_u,
+                                const void *d_w, int64_t stride, double scale, double *d_dlogc, double *d_dcoords,
+                                int32_t *d_status, void *stream) {
+    tg_status st = check_adjoint(p, form, dtype, nbatch, d_coords, d_coef, d_lam, d_u, stride, d_dlogc, d_dcoords);
+    if (st != TG_OK) return st;
+    const tg::HostPattern &h = p->host;
+    const uint64_t need = (uint64_t)h.E * h.k * h.dim;
+    if (need > tg::kNoAllocStageDoubles)
+        return fail(TG_E_ARG, "tg_adjoint_p1_noalloc: n_elements * (dim + 1) * dim = " + std::to_string(need) +
+                                  " doubles exceeds its fixed staging array of " +
+                                  std::to_string(tg::kNoAllocStageDoubles) + " (use tg_adjoint_p1)");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+        return fail(TG_E_STATE, "tg_adjoint_p1_noalloc: the current device is not the pattern's device");
+    double *stage = nullptr;
+    hipError_t e = tg::noalloc_stage(&stage);
+    if (e != hipSuccess)
+        return fail(TG_E_HIP, std::string("tg_adjoint_p1_noalloc: staging array address: ") + hipGetErrorString(e));
+    e = tg::launch_adjoint_p1(*p, form, dtype, nbatch, d_coords, d_coef, d_lam, d_u, d_w, stride, scale, d_dlogc,
+                              d_dcoords, stage, d_status, (hipStream_t)stream);
     if (e != hipSuccess) return fail(TG_E_HIP, std::string("adjoint launch failed: ") + hipGetErrorString(e));
     return ok();
 }

@@ -200,11 +200,16 @@ hipError_t launch_spmv(const tg_pattern &p, tg_dtype dtype, const void *values, 
 // The sliced-ELL copy of CSR values (both of dtype) for the CG iterations.
 hipError_t launch_sell_fill(const tg_pattern &p, tg_dtype dtype, const void *values, void *sell, hipStream_t s);
 // Adjoint of P1 assembly (tg_adjoint.hip): dlogc [E] (may be NULL) and dcoords [nv][dim]
-// (may be NULL) of scale * sum_m lam_m^T (A u_m - M w_m); scratch holds E*(dim+1)*dim doubles.
+// (may be NULL) of scale * sum_m lam_m^T (A u_m - M w_m); stage holds E*(dim+1)*dim doubles.
 hipError_t launch_adjoint_p1(const tg_pattern &p, tg_form form, tg_dtype dtype, int nbatch, const double *coords,
                              const void *coef, const void *lam, const void *u, const void *w, int64_t stride,
-                             double scale, double *dlogc, double *dcoords, double *scratch, int32_t *status,
+                             double scale, double *dlogc, double *dcoords, double *stage, int32_t *status,
                              hipStream_t s);
+// The allocation-free adjoint entry point's staging array: kNoAllocStageDoubles
+// doubles per GPU (32 MiB), its address on the current device.
+constexpr size_t kNoAllocStageDoubles = size_t(1) << 22;
+constexpr int kNoAllocMaxDevices = 64;
+hipError_t noalloc_stage(double **out);
 // y[i] = dt * exp(x[i]) in dtype (FP64 input).
 hipError_t launch_scaled_exp(tg_dtype dtype, int64_t n, double dt, const double *x, void *y, hipStream_t s);
 // Batched PCG over the slots listed in `list` (device int32[count]); every slot
