@@ -30,6 +30,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes of one FP64 CG iteration on the 64^3 Poisson system (274,625 rows, 4,018,753 nonzeros):
+# the SpMV's values and column indices once (48.2 MB), row pointers, and about ten FP64 vector passes
+PCG_ITER_BYTES_64 = 75.7e6
 METRIC = "assembled elements/s + HBM GB/s (FP64 vs FP32); p50/p99 assemble+solve latency"
 
 
@@ -65,9 +68,11 @@ def kernel_key(name: str) -> str:
     return name.replace(" ", "")
 
 
-def traffic_from_pmc(fetch_csv: str, write_csv: str, out_json: str, copy_kernel: str = "CUDAFunctorOnSelf_add"):
-    """HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each
-    scaled so that the 1 GiB read-modify-write `add_` of the cold protocol reads 1 GiB and writes 1 GiB."""
+def traffic_from_pmc(fetch_csv: str, write_csv: str, out_json: str, workload: str,
+                     copy_kernel: str = "CUDAFunctorOnSelf_add"):
+    """HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per dispatch) of one
+    workload, each scaled so that the 1 GiB read-modify-write `add_` of the cold protocol reads 1 GiB and
+    writes 1 GiB; stored under "<workload>:<kernel>" (a kernel's traffic depends on the mesh it ran on)."""
     import csv
     from collections import defaultdict
 
@@ -82,32 +87,44 @@ def traffic_from_pmc(fetch_csv: str, write_csv: str, out_json: str, copy_kernel:
     gib_kib = float(1 << 20)
     cal_f = [v for k, vs in fetch.items() if copy_kernel in k for v in vs]
     cal_w = [v for k, vs in write.items() if copy_kernel in k for v in vs]
-    fs, ws = gib_kib / (sum(cal_f) / len(cal_f)), gib_kib / (sum(cal_w) / len(cal_w))
-    rec = {"_calibration": {"kernel": copy_kernel, "bytes_read": 1 << 30, "bytes_written": 1 << 30,
-                            "fetch_kib": sum(cal_f) / len(cal_f), "write_kib": sum(cal_w) / len(cal_w),
-                            "fetch_scale": fs, "write_scale": ws}}
+    if cal_f and cal_w:
+        fs, ws = gib_kib / (sum(cal_f) / len(cal_f)), gib_kib / (sum(cal_w) / len(cal_w))
+        rec = {"_calibration": {"kernel": copy_kernel, "bytes_read": 1 << 30, "bytes_written": 1 << 30,
+                                "fetch_kib": sum(cal_f) / len(cal_f), "write_kib": sum(cal_w) / len(cal_w),
+                                "fetch_scale": fs, "write_scale": ws}}
+    else:  # a workload without the 1 GiB copy: the stored calibration (same counters, same GPU model)
+        with open(out_json) as fh:
+            cal = json.load(fh)["_calibration"]
+        fs, ws = cal["fetch_scale"], cal["write_scale"]
+        rec = {}
     for name in fetch:
         if copy_kernel in name or name not in write or "tg::" not in name:
             continue
         f = sum(fetch[name]) / len(fetch[name])
         w = sum(write[name]) / len(write[name])
-        rec[kernel_key(name)] = {"source_hash": source_hash(), "fetch_kib_raw": f, "write_kib_raw": w,
+        rec[f"{workload}:{kernel_key(name)}"] = {"source_hash": source_hash(), "fetch_kib_raw": f, "write_kib_raw": w,
                                  "fetch_scale": fs, "write_scale": ws,
                                  "bytes_per_launch": int(round((f * fs + w * ws) * 1024)),
                                  "dispatches": len(fetch[name])}
+    try:  # merge into the stored measurements (other workloads' kernels stay)
+        with open(out_json) as fh:
+            old = json.load(fh)
+    except (OSError, ValueError):
+        old = {}
+    old.update(rec)
     with open(out_json, "w") as fh:
-        json.dump(rec, fh, indent=1, sort_keys=True)
+        json.dump(old, fh, indent=1, sort_keys=True)
     return rec
 
 
-def stored_traffic(kernel: str):
+def stored_traffic(kernel: str, workload: str = "poisson3d"):
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    ent = rec.get(kernel)
+    ent = rec.get(f"{workload}:{kernel}")
     if not ent or ent.get("source_hash") != source_hash():
         return None
     return ent.get("bytes_per_launch")
@@ -148,6 +165,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle timing sample")
+    ap.add_argument("--samples", type=int, default=100,
+                    help="latency samples and side-measurement repeats (fewer for profiler runs)")
     ap.add_argument("--workload", choices=["poisson3d", "elasticity", "heat", "batched", "serve", "c1"],
                     default="poisson3d",
                     help="poisson3d: the benchmark line; elasticity: P2 32^3 assembly-only timing; heat: "
@@ -161,15 +180,17 @@ def main():
                     help="request arrivals per second for --workload serve (0: 0.5x and 0.8x of saturation)")
     ap.add_argument("--budget-gib", type=float, default=8.0, help="server HBM budget for --workload serve")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write profiles/traffic.json from two rocprofv3 --pmc runs of this script and exit")
+                    help="merge into profiles/traffic.json the traffic of two rocprofv3 --pmc runs of this script "
+                         "(of --workload) and exit")
     args = ap.parse_args()
     if args.traffic_from:
-        rec = traffic_from_pmc(*args.traffic_from, os.path.join(ROOT, "profiles", "traffic.json"))
+        rec = traffic_from_pmc(*args.traffic_from, os.path.join(ROOT, "profiles", "traffic.json"), args.workload)
         for k, v in sorted(rec.items()):
             if not k.startswith("_"):
                 print(f"| `{k}` | {v['dispatches']} | {v['fetch_kib_raw']:.1f} | {v['write_kib_raw']:.1f} | "
                       f"{v['bytes_per_launch'] / 1e6:.1f} MB |")
-        print(json.dumps(rec["_calibration"]))
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+            print(json.dumps(json.load(fh)["_calibration"]))
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -198,7 +219,7 @@ def main():
     if args.workload == "c1":
         s = torch.cuda.Stream(device=dev)
         print(json.dumps(measure_c1(dev, s, torch.zeros(1 << 28, dtype=torch.float32, device=dev),
-                                    cpu=not args.no_cpu_baseline)))
+                                    cpu=not args.no_cpu_baseline, reps=args.samples)))
         return
 
     # ---------------------------------------------------------------- inputs (resident in HBM)
@@ -270,15 +291,15 @@ def main():
         torch.cuda.synchronize()
         return np.array([e0.elapsed_time(e1) for e0, e1 in evs]) * 1e-3
 
-    t64_warm = time_kernel(assemble64, 50, cold=False)
-    t32_cold = time_kernel(assemble32, 50, cold=True)
-    t32_warm = time_kernel(assemble32, 50, cold=False)
+    t64_warm = time_kernel(assemble64, max(2, args.samples // 2), cold=False)
+    t32_cold = time_kernel(assemble32, max(2, args.samples // 2), cold=True)
+    t32_warm = time_kernel(assemble32, max(2, args.samples // 2), cold=False)
     # attainable HBM bandwidth: the 1 GiB read-modify-write of the flush (2 GiB moved per launch)
     t_copy = time_kernel(lambda: flush.add_(1.0), 10, cold=False)
     attainable_gbs = 2.0 * flush.numel() * 4 / float(np.median(t_copy)) / 1e9
     # assemble + Dirichlet + solve latency over at least 100 repeats (after the timed steps; p99 needs the
     # samples), the cold flush before each as in the timed steps
-    n_lat = max(100, args.steps)
+    n_lat = max(args.samples, args.steps)
     lat_ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(n_lat)]
     with torch.cuda.stream(s):
         for e0, e1 in lat_ev:
@@ -290,7 +311,40 @@ def main():
             e1.record(s)
     torch.cuda.synchronize()
     t_lat = np.array([a.elapsed_time(b) for a, b in lat_ev]) * 1e-3
-    c1 = measure_c1(dev, s, flush, cpu=not args.no_cpu_baseline)
+    c1 = measure_c1(dev, s, flush, cpu=not args.no_cpu_baseline, reps=args.samples)
+    # the CG iteration kernel (the step's dominant kernel): its time per launch from two fixed-length solves
+    # (50 and 250 iterations, unreachable rtol, the same chunks of launches as the timed solves), differenced
+    # so that the setup kernels cancel; HIP events on the solver's stream
+    it_lo, it_hi = 50, 250
+    t_it = {it_lo: [], it_hi: []}
+    with torch.cuda.stream(s):
+        for rep in range(4 if args.samples >= 20 else 2):
+            for n_it in (it_lo, it_hi):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                tg.pcg(pat, vals, rhs, rtol=1e-30, max_iter=n_it, x=x, stream=s, check_every=25,
+                       raise_on_noconv=False)
+                e1.record(s)
+                torch.cuda.synchronize()
+                if rep:
+                    t_it[n_it].append(e0.elapsed_time(e1) * 1e-3)
+    t_iter = (float(np.median(t_it[it_hi])) - float(np.median(t_it[it_lo]))) / (it_hi - it_lo)
+    # the FP32 system: Dirichlet + Jacobi-PCG to 1e-6 (true residual), beside the FP64 one
+    t32 = []
+    with torch.cuda.stream(s):
+        x32 = torch.empty(pat.n_dofs, dtype=torch.float32, device=dev)
+        for rep in range(3):
+            assemble32()
+            tg.apply_dirichlet(pat, vals32, rhs32, stream=s)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            _, it32, rr32, st32 = tg.pcg(pat, vals32, rhs32, rtol=1e-6, x=x32, stream=s, check_every=25,
+                                         raise_on_noconv=False, return_status=True)
+            e1.record(s)
+            torch.cuda.synchronize()
+            t32.append(e0.elapsed_time(e1) * 1e-3)
+    solve32 = {"rtol": 1e-6, "pcg_iterations": int(it32), "relres": float(rr32), "status": tg._STATUS_NAMES[st32],
+               "solve_ms_p50": float(np.median(t32)) * 1e3, "us_per_iteration": float(np.median(t32)) / it32 * 1e6}
     # bitwise repeatability of the FP64 assembly (two fresh assemblies; the loops above leave Dirichlet-
     # eliminated values behind)
     assemble64()
@@ -327,7 +381,17 @@ def main():
             "constrained_dofs": pat.n_constrained, "parallelism": "single GPU",
         },
         "roofline": {
-            "bound": "hbm", "kernel": "p1_assemble_kernel<3,double,laplace>",
+            "bound": "hbm", "kernel": "pcg_iter_kernel<double,false,true> (one CG iteration; the step's dominant "
+                                      "kernel: iterations x time per launch is most of ms_per_step)",
+            "achieved": PCG_ITER_BYTES_64 / t_iter / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": PCG_ITER_BYTES_64 / t_iter / 1e9 / HBM_PEAK_GBS,
+            "traffic": stored_traffic("pcg_iter_kernel<double,false,true>"),
+            "algorithmic_bytes_per_launch": PCG_ITER_BYTES_64, "us_per_launch": t_iter * 1e6,
+            "launches_per_step": int(np.median(iters)),
+            "attainable_gbs": attainable_gbs,
+        },
+        "roofline_assembly": {
+            "bound": "hbm", "kernel": "p1_assemble_kernel<3,double,laplace> (the assembly: value = its elements/s)",
             "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
             "traffic": traffic,
             "algorithmic_bytes_per_launch": balg64, "bytes_per_element": balg64 / E,
@@ -350,6 +414,7 @@ def main():
             "pcg_iterations": int(np.median(iters)), "relres_max": float(max(relres)),
             "solve_ms_p50": float(np.median(t_solve)) * 1e3,
             "us_per_iteration": float(np.median(t_solve) / max(1, np.median(iters))) * 1e6,
+            "fp32": solve32,
         },
         "latency_ms": {"assemble_solve_p50": float(np.percentile(t_lat, 50)) * 1e3,
                        "assemble_solve_p99": float(np.percentile(t_lat, 99)) * 1e3,
@@ -404,7 +469,7 @@ def main():
     print(json.dumps(out))
 
 
-def measure_c1(dev, s, flush, cpu=True):
+def measure_c1(dev, s, flush, cpu=True, reps=100):
     """The 2D P1 Poisson config on 64^2 x 2 triangles (8,192 elements), FP64: assembly latency (cold and
     warm, HIP events on the stream), launch-bound; error against the oracle."""
     import numpy as np
@@ -422,7 +487,7 @@ def measure_c1(dev, s, flush, cpu=True):
     rhs = torch.empty(pat.n_dofs, dtype=torch.float64, device=dev)
     res = {}
     for cold in (True, False):
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(100)]
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
         with torch.cuda.stream(s):
             for _ in range(5):
                 tg.assemble(pat, tg.LAPLACE, coords, a, f, values=vals, rhs=rhs, stream=s)
@@ -499,7 +564,9 @@ def run_elasticity(args, dev):
             res[f"{name}_{'cold' if cold else 'warm'}"] = {
                 "us": float(t.mean()) * 1e6, "elements_per_s": E / float(t.mean()),
                 "gbs_b_alg": balg / float(t.mean()) / 1e9, "gbs_b_min": bmin / float(t.mean()) / 1e9,
-                "frac_b_alg": balg / float(t.mean()) / 1e9 / HBM_PEAK_GBS}
+                "frac_b_alg": balg / float(t.mean()) / 1e9 / HBM_PEAK_GBS, "b_alg_bytes": balg,
+                "traffic": stored_traffic(f"p2_elasticity_kernel<{'double' if dt == torch.float64 else 'float'}>",
+                                          "elasticity")}
         torch.cuda.synchronize()
         res[f"{name}_result"] = (vals.double().cpu().numpy(), rhs.double().cpu().numpy())
     out = {"workload": f"3D linear elasticity P2 tets, {n}^3 x 6 Kuhn, lambda,mu~U(0.5,2), b~N(0,1)^3, seed 0",
@@ -598,6 +665,9 @@ def run_heat(args, dev):
                      "adjoint_kernel_us": t_adj * 1e6, "adjoint_gbs": badj / t_adj / 1e9,
                      "adjoint_bytes": badj, "pcg_rtol": r}
         res[name]["_grads"] = (dla, dx, du0, g)
+    ta = stored_traffic("p1_adjoint_element_kernel<2,double,3>", "heat")
+    tr = stored_traffic("vertex_reduce_kernel<2>", "heat")
+    adjoint_traffic = ta + tr if ta is not None and tr is not None else None
     out = {"metric": "differentiable heat: gradient evaluations/s (forward rollout + adjoint)",
            "value": res["fp64"]["grad_evals_per_s"], "unit": "grad/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": (res["fp64"]["forward_ms"] + res["fp64"]["backward_ms"]),
@@ -609,7 +679,7 @@ def run_heat(args, dev):
            "roofline": {"bound": "hbm", "kernel": "p1_adjoint_element_kernel<2,double,mass_laplace> + "
                                                   "vertex_reduce_kernel<2> (nbatch 20)",
                         "achieved": res["fp64"]["adjoint_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": res["fp64"]["adjoint_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                        "frac": res["fp64"]["adjoint_gbs"] / HBM_PEAK_GBS, "traffic": adjoint_traffic,
                         "algorithmic_bytes_per_launch": res["fp64"]["adjoint_bytes"],
                         "note": "the step time is dominated by the 40 PCG solves, not by this kernel"}}
     if not args.no_cpu_baseline:
