@@ -128,8 +128,16 @@ struct PcgSlot {
 };
 
 constexpr int kVecThreads = 1024;  // threads per block of the PCG setup and residual kernels
-constexpr int kMaxGrid = 1024;     // blocks of any PCG kernel (grid-stride beyond)
-constexpr int kIterThreads = 512;  // threads per block of the CG iteration kernel: 8 slices
+constexpr int kMaxGrid = 2048;       // partial sums per kind: the CG iteration kernel's block cap
+constexpr int kSetupMaxGrid = 1024;  // blocks of the PCG setup and residual kernels (grid-stride beyond)
+// Threads per block of the CG iteration kernel: 4 slices in FP64, whose 1000+
+// blocks on a 64^3 mesh then spread more evenly over the 256 CUs, 8 in FP32,
+// where the wider block measured faster.
+template <typename T>
+constexpr int iter_threads() {
+    return sizeof(T) == 8 ? 256 : 512;
+}
+constexpr int kFillThreads = 512;  // threads per block of the sliced-ELL fill: 8 slices
 // Per-block partial sums of the PCG kernels, kMaxGrid doubles each: r.u, w.u and r.r
 // of an iterate at kGam/kDel/kRr + 3 (iteration & 1), and the true residual at kResid.
 constexpr int kGam = 0, kDel = 1, kRr = 2, kResid = 6, kNumPartials = 7;

@@ -462,7 +462,7 @@ __device__ __forceinline__ double row_tail_new_u(const TG_GLOBAL T *__restrict__
 // the next iterate.  CHECK_ONLY launches stop after the test, and so does
 // iteration max_iter.  n_prev: number of partials written by the previous
 // launch (n_prev_init for iteration 0, whose partials come from
-// pcg_init_spmv_kernel); both are at most kMaxGrid = 2 kIterThreads.
+// pcg_init_spmv_kernel); both are at most kMaxGrid.
 //
 // The SpMV runs on the sliced-ELL copy of the values: each wave owns slices of
 // 64 consecutive rows, one row per lane, and step k of the wave reads entry k of
@@ -476,12 +476,11 @@ __device__ __forceinline__ double row_tail_new_u(const TG_GLOBAL T *__restrict__
 // formed after it.  Waves own slices in XCD-contiguous ranges (neighbouring
 // rows' records stay in one L2).
 template <typename T, bool CHECK_ONLY, bool SOLO>
-__global__ __launch_bounds__(kIterThreads) __attribute__((amdgpu_waves_per_eu(6)))
+__global__ __launch_bounds__(iter_threads<T>()) __attribute__((amdgpu_waves_per_eu(6)))
 void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const int32_t *__restrict__ sell_col,
                      const PcgSlot *__restrict__ slots, const int32_t *__restrict__ list, PcgSlot solo, int step,
                      int n_prev_init, int n_prev) {
-    constexpr int W = kIterThreads / 64;
-    static_assert(kMaxGrid <= 2 * kIterThreads, "two partials per thread");
+    constexpr int kThreads = iter_threads<T>(), W = kThreads / 64;
     __shared__ double sh[3 * W];   // the previous partials' reduction
     __shared__ double sh2[3 * W];  // this launch's block sums
     __shared__ double sst[4];
@@ -498,18 +497,19 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
     const int waves = gridDim.x * W;
     const int sl0 = xcd_swizzle(blockIdx.x, gridDim.x) * W + (int)(threadIdx.x >> 6);  // this wave's first slice
 
-    // the previous launch's partials (two per thread) and, by the block's last
+    // the previous launch's partials (strided over the threads) and, by the block's last
     // thread, the stop flag and scalars of earlier launches; the reduction's
     // barrier publishes them through LDS
     const int np = it == 0 ? n_prev_init : n_prev;
     const TG_GLOBAL double *p_rr = gl(part(S.partials, kRr + cur)), *p_gam = gl(part(S.partials, kGam + cur)),
                            *p_del = gl(part(S.partials, kDel + cur));
-    const int t0 = threadIdx.x, t1 = threadIdx.x + kIterThreads;
-    double rr_cur = t0 < np ? p_rr[t0] : 0.0, gam = t0 < np ? p_gam[t0] : 0.0, del = t0 < np ? p_del[t0] : 0.0;
-    rr_cur += t1 < np ? p_rr[t1] : 0.0;
-    gam += t1 < np ? p_gam[t1] : 0.0;
-    del += t1 < np ? p_del[t1] : 0.0;
-    if (threadIdx.x == kIterThreads - 1) {
+    double rr_cur = 0.0, gam = 0.0, del = 0.0;
+    for (int t = threadIdx.x; t < np; t += kThreads) {
+        rr_cur += p_rr[t];
+        gam += p_gam[t];
+        del += p_del[t];
+    }
+    if (threadIdx.x == kThreads - 1) {
         sst[0] = (double)st->done;
         sst[1] = st->tol2;
         sst[2] = st->gamma[(it + 1) & 1];
@@ -636,12 +636,12 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
 // The sliced-ELL copy of CSR values: one wave per slice, lane l on row 64 s + l;
 // padding entries get 0.
 template <typename T>
-__global__ __launch_bounds__(kIterThreads) void sell_fill_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr,
+__global__ __launch_bounds__(kFillThreads) void sell_fill_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr,
                                                                  const int32_t *__restrict__ row_ptr,
                                                                  const T *__restrict__ values, T *__restrict__ sell) {
     const int lane = threadIdx.x & 63;
-    for (int sl = blockIdx.x * (kIterThreads / 64) + (int)(threadIdx.x >> 6); sl < nsl;
-         sl += gridDim.x * (kIterThreads / 64)) {
+    for (int sl = blockIdx.x * (kFillThreads / 64) + (int)(threadIdx.x >> 6); sl < nsl;
+         sl += gridDim.x * (kFillThreads / 64)) {
         const int e = sell_ptr[sl] + lane, len = (sell_ptr[sl + 1] - sell_ptr[sl]) >> 6;
         const int i = sl * 64 + lane;
         const int p0 = i < n ? row_ptr[i] : 0, m = i < n ? row_ptr[i + 1] - p0 : 0;
@@ -675,13 +675,13 @@ __global__ __launch_bounds__(kVecThreads) void residual_kernel(int n, const int3
 }
 
 int vec_blocks(int64_t n) {
-    return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxGrid, (n + kVecThreads - 1) / kVecThreads));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kSetupMaxGrid, (n + kVecThreads - 1) / kVecThreads));
 }
 
 template <int G>
 int spmv_blocks(int64_t n) {
     const int64_t rows_per_block = kVecThreads / G;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxGrid, (n + rows_per_block - 1) / rows_per_block));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kSetupMaxGrid, (n + rows_per_block - 1) / rows_per_block));
 }
 
 template <int G>
@@ -739,8 +739,9 @@ void launch_warm_init_t(const tg_pattern &pt, const PcgSlot *slots, const int32_
 
 // Blocks of the iteration kernel: one slice per wave, at most kMaxGrid blocks
 // (grid-stride over slices beyond).
+template <typename T>
 int iter_blocks(const tg_pattern &pt) {
-    const int64_t per = kIterThreads / 64;
+    const int64_t per = iter_threads<T>() / 64;
     return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxGrid, (pt.dev.n_slices + per - 1) / per));
 }
 
@@ -748,12 +749,12 @@ template <typename T, int G>
 void launch_step_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *list, int count, int step,
                    hipStream_t s, const PcgSlot *solo) {
     const int n = (int)pt.host.n_dofs, nsl = (int)pt.dev.n_slices;
-    const int ns0 = spmv_blocks<G>(n), ns = iter_blocks(pt);
+    const int ns0 = spmv_blocks<G>(n), ns = iter_blocks<T>(pt);
     if (solo)
-        hipLaunchKernelGGL((pcg_iter_kernel<T, false, true>), dim3(ns, 1), dim3(kIterThreads), 0, s, n, nsl,
+        hipLaunchKernelGGL((pcg_iter_kernel<T, false, true>), dim3(ns, 1), dim3(iter_threads<T>()), 0, s, n, nsl,
                            pt.dev.sell_ptr, pt.dev.sell_col, slots, list, *solo, step, ns0, ns);
     else
-        hipLaunchKernelGGL((pcg_iter_kernel<T, false, false>), dim3(ns, count), dim3(kIterThreads), 0, s, n, nsl,
+        hipLaunchKernelGGL((pcg_iter_kernel<T, false, false>), dim3(ns, count), dim3(iter_threads<T>()), 0, s, n, nsl,
                            pt.dev.sell_ptr, pt.dev.sell_col, slots, list, PcgSlot{}, step, ns0, ns);
 }
 
@@ -761,16 +762,16 @@ template <typename T, int G>
 void launch_check_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *list, int count, int step,
                     hipStream_t s) {
     const int n = (int)pt.host.n_dofs;
-    hipLaunchKernelGGL((pcg_iter_kernel<T, true, false>), dim3(1, count), dim3(kIterThreads), 0, s, n,
+    hipLaunchKernelGGL((pcg_iter_kernel<T, true, false>), dim3(1, count), dim3(iter_threads<T>()), 0, s, n,
                        (int)pt.dev.n_slices, pt.dev.sell_ptr, pt.dev.sell_col, slots, list, PcgSlot{}, step,
-                       spmv_blocks<G>(n), iter_blocks(pt));
+                       spmv_blocks<G>(n), iter_blocks<T>(pt));
 }
 
 template <typename T>
 hipError_t launch_sell_fill_t(const tg_pattern &pt, const void *values, void *sell, hipStream_t s) {
-    const int64_t per = kIterThreads / 64;
+    const int64_t per = kFillThreads / 64;
     const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(8192, (pt.dev.n_slices + per - 1) / per));
-    hipLaunchKernelGGL(sell_fill_kernel<T>, dim3(nb), dim3(kIterThreads), 0, s, (int)pt.host.n_dofs,
+    hipLaunchKernelGGL(sell_fill_kernel<T>, dim3(nb), dim3(kFillThreads), 0, s, (int)pt.host.n_dofs,
                        (int)pt.dev.n_slices, pt.dev.sell_ptr, pt.dev.row_ptr, (const T *)values, (T *)sell);
     return hipGetLastError();
 }
