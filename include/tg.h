@@ -164,9 +164,9 @@ tg_status tg_pattern_copy_element_nodes(const tg_pattern *p, int32_t *h_nodes);
  *       ascending element order; a slot is b * n + (pair - f), where f is the
  *       first pair and n the number of pairs of the entry's row block: local
  *       entry (a, b) of the pair's element.  For ncomp = 3 each slot is a 3x3
- *       block.  For P1 the diagonal entry (i, i) has an empty segment: its
- *       value is the sum of K_e[a][a] over the pairs (i, e, a) of node i, in
- *       their S_vec (ascending element) order.  n_slot (tg_pattern_info) is
+ *       block.  The diagonal entry (i, i) has an empty segment: its value
+ *       (P2: 3x3 block) is the sum of K_e[a][a] over the pairs (i, e, a) of
+ *       node i, in their S_vec (ascending element) order.  n_slot (tg_pattern_info) is
  *       h_seg_ptr[Z] rounded up to a multiple of 4; the tail is unused.
  */
 /*

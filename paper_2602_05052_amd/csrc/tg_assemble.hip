@@ -702,13 +702,35 @@ __device__ __forceinline__ void p2_reduce(const BlockLds<T> &L, const int *sRp, 
     }
 }
 
+// Diagonal blocks of the rows whose node is in this phase's class (vertex or
+// edge node: the class of its local index in every element): component z of
+// row r is the sum, over the row's pairs t in S_vec (ascending element) order,
+// of component z of the pair's block (a_t, a_t); nine lanes per row.  The
+// routing lists no slots for these entries.  Written at the scalar CSR
+// positions diag_pos[3 i + c] + (c' - c).
+template <typename T>
+__device__ __forceinline__ void p2_reduce_diagonal(const BlockLds<T> &L, const int *sIp, const uint8_t *sA,
+                                                   const int *sDp, int nrows, int np, bool edge,
+                                                   T *__restrict__ values) {
+    const int cs = np * 9, b0 = edge ? 4 : 0;
+    for (int u = threadIdx.x; u < 9 * nrows; u += kP2Threads) {
+        const int r = u / 9, z = u - 9 * r;
+        const int t0 = sIp[r], t1 = sIp[r + 1];
+        if (t0 == t1 || ((int)sA[t0] >= 4) != edge) continue;
+        T acc = 0;
+        for (int t = t0; t < t1; ++t) acc += L.K[((int)sA[t] - b0) * cs + t * 9 + z];
+        const int c = z / 3;
+        values[sDp[3 * r + c] + (z - 3 * c) - c] = acc;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     const int32_t *__restrict__ blk_desc, const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc,
     const int32_t *__restrict__ node_rp, const int32_t *__restrict__ seg_ptr, const uint16_t *__restrict__ slot,
-    const int32_t *__restrict__ blk_vert, const uint32_t *__restrict__ pair_lv, const double *__restrict__ coords,
-    const T *__restrict__ coef, const T *__restrict__ load, T *__restrict__ values, T *__restrict__ rhs,
-    int32_t *__restrict__ status, int nblk, int E, int mp, int me) {
+    const int32_t *__restrict__ blk_vert, const uint32_t *__restrict__ pair_lv, const int32_t *__restrict__ diag_pos,
+    const double *__restrict__ coords, const T *__restrict__ coef, const T *__restrict__ load, T *__restrict__ values,
+    T *__restrict__ rhs, int32_t *__restrict__ status, int nblk, int E, int mp, int me) {
     constexpr int K = 10;
     constexpr int VS = VertLds<3>::VS;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -717,6 +739,8 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
         reinterpret_cast<double *>(smem + VertLds<3>::offset(BlockLds<T>::bytes(mp, me, 9 * kP2PhaseCols, 3, K)));
     __shared__ int sRp[kP2BlockCap + 1];  // row starts in the block's node-level entries
     __shared__ int sIp[kP2BlockCap + 1];  // row starts in the block's pairs
+    __shared__ int sDp[3 * kP2BlockCap];  // diagonal positions of the block's DoF rows
+    __shared__ uint8_t sA[kP2BlockCap];   // local node of every pair
 
     static_assert(kP2Threads == 3 * 64, "one wave per set of column nodes");
     static_assert(kP2BlockCap <= 64, "one lane per pair in each wave");
@@ -726,7 +750,9 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     const int r0 = dsc.x, r1 = dsc.y, q0 = dsc.z, q1 = dsc.w, rp0 = dsv.x, rp1 = dsv.y, w0 = dsv.z, w1 = dsv.w;
     const int np = q1 - q0, nent = rp1 - rp0, nvb = w1 - w0;
     const int nrows = r1 - r0;
-    const int s0 = q0 * K;
+    // the block's slots: K - 1 per pair (a diagonal block has none), from s0,
+    // copied in 4-byte units of two from the even sb
+    const int s0 = q0 * (K - 1), sb = s0 & ~1;
     const int tid = threadIdx.x, lane = tid & 63;
 
     if (np == 0) {  // rows of nodes that belong to no element: no values, zero loads
@@ -742,8 +768,8 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     // this thread stages; then the loads that need one of them (coordinates,
     // coefficients, body force).  Two memory latencies in all for blocks of at
     // most 2 kP2Threads - 1 entries and kP2Threads vertices.
-    const int nsu = np * K / 2;  // s0 and np K are even: 4-byte units of two slots
-    const uint32_t *__restrict__ slot_u = reinterpret_cast<const uint32_t *>(slot + s0);
+    const int nsu = (q1 * (K - 1) - sb + 1) >> 1;
+    const uint32_t *__restrict__ slot_u = reinterpret_cast<const uint32_t *>(slot + sb);
     const int tp = min(lane, np - 1);
     const int code = ldg(inc, (unsigned)(q0 + tp));
     const uint32_t lv = ldg(pair_lv, (unsigned)(q0 + tp));
@@ -754,6 +780,7 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     const uint32_t su_a = ldg(slot_u, (unsigned)min(tid, nsu - 1));
     const uint32_t su_b = ldg(slot_u, (unsigned)min(tid + kP2Threads, nsu - 1));
     const unsigned vid = (unsigned)ldg(blk_vert, (unsigned)(w0 + min(tid, nvb - 1)));
+    const int dp_reg = ldg(diag_pos, (unsigned)(3 * r0 + min(tid, 3 * nrows - 1)));
     const int e = code / K, a = code - e * K;
     const T lam_t = ldg(coef, (unsigned)e), mu_t = ldg(coef, (unsigned)(E + e));
     // the body force of the pair's element (or, with no load, a valid dummy read)
@@ -775,14 +802,15 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     // value its owner writes there.
     sRp[min(tid, nrows)] = rp_reg - rp0;
     sIp[min(tid, nrows)] = ip_reg - q0;
-    L.seg[min(tid, nent)] = sg_a - s0;
-    L.seg[min(tid + kP2Threads, nent)] = sg_b - s0;
+    L.seg[min(tid, nent)] = sg_a - sb;
+    L.seg[min(tid + kP2Threads, nent)] = sg_b - sb;
+    sDp[min(tid, 3 * nrows - 1)] = dp_reg;
     reinterpret_cast<uint32_t *>(L.slot)[min(tid, nsu - 1)] = su_a;
     reinterpret_cast<uint32_t *>(L.slot)[min(tid + kP2Threads, nsu - 1)] = su_b;
 #pragma unroll
     for (int c = 0; c < 3; ++c) Lx[min(tid, nvb - 1) * VS + c] = vx[c];
     // remainders of large blocks (more entries or vertices than the above covers)
-    for (int u = tid + 2 * kP2Threads; u <= nent; u += kP2Threads) L.seg[u] = ldg(seg_ptr, (unsigned)(rp0 + u)) - s0;
+    for (int u = tid + 2 * kP2Threads; u <= nent; u += kP2Threads) L.seg[u] = ldg(seg_ptr, (unsigned)(rp0 + u)) - sb;
     for (int l = tid + kP2Threads; l < nvb; l += kP2Threads) {
         const unsigned v = (unsigned)ldg(blk_vert, (unsigned)(w0 + l));
 #pragma unroll
@@ -816,6 +844,7 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
         pr.mu = mu_t;
         pr.init(a, (T)(adet * Deg2Rule<3>::w));
         if (wave == 0) {
+            sA[lane] = (uint8_t)a;
             pr.template block<0>(dst);
             pr.template block<1>(dst + cs);
         } else if (wave == 1) {
@@ -838,6 +867,7 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     }
     __syncthreads();
     p2_reduce<T>(L, sRp, np, nent, false, values + 9 * (size_t)rp0);
+    p2_reduce_diagonal<T>(L, sIp, sA, sDp, nrows, np, false, values);
     __syncthreads();  // the edge-column blocks reuse the LDS of the vertex-column ones
     if (own) {
         if (wave == 0) {
@@ -853,6 +883,7 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     }
     __syncthreads();
     p2_reduce<T>(L, sRp, np, nent, true, values + 9 * (size_t)rp0);
+    p2_reduce_diagonal<T>(L, sIp, sA, sDp, nrows, np, true, values);
     if (rhs && load) {
         for (int u = threadIdx.x; u < 3 * nrows; u += kP2Threads) {
             const int r = u / 3, c = u - 3 * r;
@@ -934,13 +965,13 @@ hipError_t launch_assemble_p2(const tg_pattern &p, tg_dtype dtype, const double 
     if (dtype == TG_F64)
         hipLaunchKernelGGL(p2_elasticity_kernel<double>, dim3(nblk), dim3(kP2Threads),
                            VertLds<3>::offset(BlockLds<double>::bytes(mp, me, 9 * kP2PhaseCols, 3, 10)) + verts, s, d.blk_desc,
-                           d.inc_ptr, d.inc, d.node_rp, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, coords,
+                           d.inc_ptr, d.inc, d.node_rp, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, d.diag_pos, coords,
                            (const double *)coef, (const double *)load, (double *)values, (double *)rhs, status, nblk,
                            E, mp, me);
     else
         hipLaunchKernelGGL(p2_elasticity_kernel<float>, dim3(nblk), dim3(kP2Threads),
                            VertLds<3>::offset(BlockLds<float>::bytes(mp, me, 9 * kP2PhaseCols, 3, 10)) + verts, s, d.blk_desc,
-                           d.inc_ptr, d.inc, d.node_rp, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, coords,
+                           d.inc_ptr, d.inc, d.node_rp, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, d.diag_pos, coords,
                            (const float *)coef, (const float *)load, (float *)values, (float *)rhs, status, nblk, E,
                            mp, me);
     return hipGetLastError();

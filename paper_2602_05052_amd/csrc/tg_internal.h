@@ -59,6 +59,7 @@ struct HostPattern {
     std::vector<uint32_t> pair_lv;  // [n_pairs]
     // S_mat routing: node-level entry p sums slots slot[seg_ptr[p] .. seg_ptr[p+1]),
     // ascending element order; slot = b * (pairs of the block) + (pair - first pair of the block).
+    // Diagonal entries have empty segments (the kernels sum them from the row's pairs).
     // P1: the diagonal entry of a row has an empty segment; its value is the sum over
     // the row's pairs (S_vec order) of the element's diagonal entry K_e[a][a].
     std::vector<int32_t> seg_ptr;  // [nnz_nodes+1]

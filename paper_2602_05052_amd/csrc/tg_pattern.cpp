@@ -8,11 +8,14 @@
 // builder stores them in that form:
 //   S_vec: for each node i, its (element, local node) pairs in ascending
 //          element order  (inc_ptr / inc);
-//   S_mat: for each node-level CSR entry (i, j), the element slots (pair of row
-//          i, local column b) that land on it, in ascending element order
-//          (seg_ptr / slot).  Slot ids are relative to the row block of the
-//          fused kernel and index its local matrices in LDS, stored column by
-//          column: slot = b * (pairs of the block) + (pair - first pair).
+//   S_mat: for each off-diagonal node-level CSR entry (i, j), the element
+//          slots (pair of row i, local column b) that land on it, in ascending
+//          element order (seg_ptr / slot).  Slot ids are relative to the row
+//          block of the fused kernel and index its local matrices in LDS,
+//          stored column by column: slot = b * (pairs of the block) + (pair -
+//          first pair).  A diagonal entry (i, i) sums exactly the blocks (a, a)
+//          of row i's pairs in S_vec order, so it has no slots; the kernels sum
+//          it per row.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -245,9 +248,10 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
     // ---- S_mat routing, row by row
     hp.seg_ptr.clear();
     hp.seg_ptr.reserve((size_t)hp.node_ci.size() + 1);
-    // P1 diagonal entries take no slots: the kernel sums the pairs' own diagonal
-    // entries row by row (the same terms in the same order).
-    const bool skip_diag = p1;
+    // Diagonal entries take no slots: the kernels sum the pairs' own diagonal
+    // entries (P1) or 3x3 diagonal blocks (P2) row by row, the same terms in
+    // the same order.
+    const bool skip_diag = true;
     hp.slot.resize((size_t)E * k * (skip_diag ? k - 1 : k) + 3);
     int64_t slot_fill = 0;
     int64_t blk = 0;

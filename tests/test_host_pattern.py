@@ -169,12 +169,21 @@ def test_p2_pattern_routing_equals_oracle():
     pair, b = _pair_of_slot(r, k)
     code = r["inc"][pair]
     e, a = code // k, code % k
-    # scalar value of node entry z, components (c, c') -> CSR position
+    # diagonal entries carry no slots: each sums its row's pairs' blocks (a, a) in S_vec order
     node_rp = r["node_rp"]
+    node_of_entry = np.repeat(np.arange(pat.n_nodes), np.diff(node_rp))
+    node_ci = np.concatenate([ci[9 * node_rp[i]:9 * node_rp[i] + 3 * (node_rp[i + 1] - node_rp[i]):3] // 3
+                              for i in range(pat.n_nodes)])
+    diag = np.flatnonzero(node_ci == node_of_entry)
+    assert len(diag) == pat.n_nodes and np.all(np.diff(r["seg_ptr"])[diag] == 0)
+    assert np.all(np.diff(r["seg_ptr"])[np.setdiff1d(np.arange(len(node_ci)), diag)] > 0)
+    pe, pa = r["inc"] // k, r["inc"] % k
+    # scalar value of node entry z, components (c, c') -> CSR position
     vals = np.zeros(pat.nnz)
     for c in range(3):
         for cc in range(3):
             v = _sequential_segment_sum(Kl[e, a, c, b, cc], r["seg_ptr"])
+            v[diag] = _sequential_segment_sum(Kl[pe, pa, c, pa, cc], r["inc_ptr"])
             for i in range(pat.n_nodes):
                 m = node_rp[i + 1] - node_rp[i]
                 base = 9 * node_rp[i] + c * 3 * m
