@@ -99,6 +99,9 @@ typedef struct {
     size_t device_bytes;       /* device memory owned by the pattern (host-only: what an upload would take) */
     int64_t n_slot;            /* length of the routing slot list             */
     size_t scratch_bytes;      /* the pattern's scratch grown by tg_adjoint_p1 / tg_heat_* (0 until used) */
+    int64_t sell_index_bytes;  /* bytes per column index of the CG iterations' sliced-ELL
+                                  pattern: 2 (offsets from the row, when every column lies
+                                  within 32767 of it) or 4 */
 } tg_pattern_info;
 
 /* Text of the last error on the calling thread; valid until its next tg_ call. */

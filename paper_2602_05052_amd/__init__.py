@@ -51,7 +51,8 @@ class _Info(ctypes.Structure):
                 ("n_dofs", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n_constrained", ctypes.c_int64),
                 ("n_blocks", ctypes.c_int64),
                 ("d_row_ptr", ctypes.c_void_p), ("d_col_idx", ctypes.c_void_p), ("device_bytes", ctypes.c_size_t),
-                ("n_slot", ctypes.c_int64), ("scratch_bytes", ctypes.c_size_t)]
+                ("n_slot", ctypes.c_int64), ("scratch_bytes", ctypes.c_size_t),
+                ("sell_index_bytes", ctypes.c_int64)]
 
 
 class ServerResult(ctypes.Structure):
@@ -228,6 +229,7 @@ class Pattern:
         self.n_constrained, self.n_blocks = info.n_constrained, info.n_blocks
         self.device_bytes = info.device_bytes
         self.n_slot = info.n_slot
+        self.sell_index_bytes = info.sell_index_bytes
         self.host_only = host_only
 
     def scratch_bytes(self) -> int:

@@ -37,7 +37,7 @@ void free_device(tg::DevicePattern &d) {
                     d.blk_vert, d.pair_lv,
                     d.slot,    d.ent16,   d.slot8,    d.row_ptr,     d.col_idx, d.diag_pos, d.constrained,
                     d.work,    d.partials, d.state, d.dir_rows,  d.pcg_slot, d.pcg_list, d.sell_ptr,
-                    d.sell_col, d.sell_vals};
+                    d.sell_col, d.sell_off, d.sell_vals};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (d.ws) (void)hipFree(d.ws);
@@ -54,7 +54,7 @@ void free_device(tg::DevicePattern &d) {
     X(conn, conn) X(inc_ptr, inc_ptr) X(inc, inc) X(blk_row, blk_row) X(blk_desc, blk_desc) X(blk_vert, blk_vert) \
     X(pair_lv, pair_lv) X(node_rp, node_rp) X(node_ci, node_ci) X(seg_ptr, seg_ptr) X(slot, slot) X(ent16, ent16) \
     X(slot8, slot8) X(row_ptr, row_ptr) X(col_idx, col_idx) X(diag_pos, diag_pos) X(constrained, constrained)    \
-    X(dirichlet_rows, dir_rows) X(sell_ptr, sell_ptr) X(sell_col, sell_col)
+    X(dirichlet_rows, dir_rows) X(sell_ptr, sell_ptr) X(sell_col, sell_col) X(sell_off, sell_off)
 
 template <typename V>
 size_t array_bytes(const std::vector<V> &h) {
@@ -83,6 +83,7 @@ tg_status create_device(tg_pattern &pt) {
     d.n_dir_rows = (int64_t)h.dirichlet_rows.size();
     d.n_slices = h.sell_ptr.empty() ? 0 : (int64_t)h.sell_ptr.size() - 1;
     d.sell_nnz = h.sell_ptr.empty() ? 0 : (int64_t)h.sell_ptr.back();
+    d.sell16 = !h.sell_off.empty();
     if (e == hipSuccess) {
         const size_t sb = (size_t)std::max<int64_t>(1, d.sell_nnz) * sizeof(double);
         e = hipMalloc((void **)&d.sell_vals, sb);
@@ -226,6 +227,7 @@ tg_status tg_pattern_query(const tg_pattern *p, tg_pattern_info *info) {
     info->device_bytes = p->host_only ? tg::device_bytes(h) : p->dev.bytes;
     info->scratch_bytes = p->host_only ? 0 : p->dev.ws_bytes;
     info->n_slot = (int64_t)h.slot.size();
+    info->sell_index_bytes = h.sell_off.empty() ? 4 : 2;
     return ok();
 }
 

@@ -77,9 +77,13 @@ struct HostPattern {
     std::vector<int32_t> diag_pos;  // [n_dofs]
     // Sliced-ELL copy of the scalar pattern (the CG iterations' SpMV): slices of
     // kSellRows consecutive rows, entry k of row r at sell_ptr[r / kSellRows] +
-    // kSellRows k + r % kSellRows; padding entries name the row itself (value 0).
+    // kSellRows k + r % kSellRows; padding entries name the row itself (rows past
+    // the last DoF: the last DoF), value 0.  When every column lies within 32767
+    // of its row's clamped index min(r, n_dofs - 1), the columns are kept as
+    // 16-bit offsets from it (sell_off) and sell_col is empty.
     std::vector<int32_t> sell_ptr;  // [n_slices+1]
-    std::vector<int32_t> sell_col;  // [sell_ptr[n_slices]]
+    std::vector<int32_t> sell_col;  // [sell_ptr[n_slices]] or empty
+    std::vector<int16_t> sell_off;  // [sell_ptr[n_slices]] or empty
     // Dirichlet.
     std::vector<uint8_t> constrained;  // [n_dofs] 0/1
     std::vector<int32_t> constrained_list;
@@ -164,7 +168,9 @@ struct DevicePattern {
     int32_t *diag_pos = nullptr;  // [n_dofs]
     uint8_t *constrained = nullptr;  // [n_dofs]
     int32_t *sell_ptr = nullptr;     // [n_slices+1] sliced-ELL pattern (HostPattern::sell_ptr)
-    int32_t *sell_col = nullptr;     // [sell_nnz]
+    int32_t *sell_col = nullptr;     // [sell_nnz] 32-bit columns, or
+    int16_t *sell_off = nullptr;     // [sell_nnz] 16-bit offsets from the row (sell16)
+    bool sell16 = false;
     int64_t n_slices = 0, sell_nnz = 0;
     double *sell_vals = nullptr;     // the solo solver's sliced-ELL copy of the values (sell_nnz, used as T)
     // PCG workspace: kPcgWorkVectors vectors of n_dofs doubles (used as T), partials, state.

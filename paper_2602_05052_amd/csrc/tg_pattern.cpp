@@ -426,8 +426,29 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
                 const int32_t p0 = r < hp.n_dofs ? hp.row_ptr[r] : 0, m = r < hp.n_dofs ? hp.row_ptr[r + 1] - p0 : 0;
                 for (int64_t q = 0; q < len; ++q)
                     hp.sell_col[hp.sell_ptr[s] + q * kSellRows + l] =
-                        q < m ? hp.col_idx[p0 + q] : (int32_t)(r < hp.n_dofs ? r : 0);
+                        q < m ? hp.col_idx[p0 + q] : (int32_t)std::min<int64_t>(r, hp.n_dofs - 1);
             }
+        }
+        // 16-bit offsets from the clamped row when they all fit (banded numberings:
+        // half the index bytes the CG iterations read)
+        bool fits = true;
+        for (int64_t s = 0; s < nsl && fits; ++s)
+            for (int64_t q = hp.sell_ptr[s]; q < hp.sell_ptr[s + 1]; ++q) {
+                const int64_t d = (int64_t)hp.sell_col[q] - std::min<int64_t>(s * kSellRows + (q % kSellRows), hp.n_dofs - 1);
+                if (d < -32767 || d > 32767) {
+                    fits = false;
+                    break;
+                }
+            }
+        hp.sell_off.clear();
+        if (fits && off > 0) {
+            hp.sell_off.resize(off);
+            for (int64_t s = 0; s < nsl; ++s)
+                for (int64_t q = hp.sell_ptr[s]; q < hp.sell_ptr[s + 1]; ++q)
+                    hp.sell_off[q] = (int16_t)((int64_t)hp.sell_col[q] -
+                                               std::min<int64_t>(s * kSellRows + (q % kSellRows), hp.n_dofs - 1));
+            hp.sell_col.clear();
+            hp.sell_col.shrink_to_fit();
         }
     }
 

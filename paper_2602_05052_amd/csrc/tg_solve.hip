@@ -11,6 +11,7 @@
 // fences and no extra launches.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "tg_device.h"
@@ -378,6 +379,19 @@ __device__ __forceinline__ PcgSlot pick_slot(const PcgSlot *__restrict__ slots, 
         return slots[list[blockIdx.y]];
 }
 
+// Column of sliced-ELL entry q of a row whose clamped index is rb: the 32-bit
+// column itself, or rb plus a 16-bit offset when the pattern's columns all lie
+// within 32767 of their rows (half the index bytes of every iteration).
+template <typename CI> struct SellCols;
+template <> struct SellCols<int32_t> {
+    const int32_t *__restrict__ c;
+    __device__ __forceinline__ int operator()(int q, int) const { return c[q]; }
+};
+template <> struct SellCols<int16_t> {
+    const int16_t *__restrict__ c;
+    __device__ __forceinline__ int operator()(int q, int rb) const { return rb + (int)c[q]; }
+};
+
 // Entries of a row per round of the iteration kernel's SpMV (FP64 products,
 // FP32 new-u terms).
 constexpr int kIterRound = 3;
@@ -391,8 +405,8 @@ constexpr int kIterRound32 = 4;
 // sums the row's terms in entry order.  The loop is software-pipelined: the
 // next round's columns and values are requested before this round's records
 // are consumed.
-template <typename T>
-__device__ __forceinline__ void row_products(const TG_GLOBAL T *__restrict__ sv, const int32_t *__restrict__ sell_col,
+template <typename T, typename CI>
+__device__ __forceinline__ void row_products(const TG_GLOBAL T *__restrict__ sv, const SellCols<CI> &cols, int rb,
                                              const TG_GLOBAL Rec<T> *__restrict__ ra, int e, int len, double &A,
                                              double &B, double &C) {
     constexpr int R = kIterRound;
@@ -401,7 +415,7 @@ __device__ __forceinline__ void row_products(const TG_GLOBAL T *__restrict__ sv,
 #pragma unroll
     for (int u = 0; u < R; ++u) {
         const int q = e + 64 * min(u, len - 1);  // clamped: entries past the row re-read its last one, unused
-        c[u] = sell_col[q];
+        c[u] = cols(q, rb);
         val[u] = sv[q];
     }
     for (int k = 0; k < len; k += R) {
@@ -413,7 +427,7 @@ __device__ __forceinline__ void row_products(const TG_GLOBAL T *__restrict__ sv,
 #pragma unroll
         for (int u = 0; u < R; ++u) {
             const int q = e + 64 * min(k + R + u, len - 1);
-            cn[u] = sell_col[q];
+            cn[u] = cols(q, rb);
             vn[u] = sv[q];
         }
 #pragma unroll
@@ -435,9 +449,8 @@ __device__ __forceinline__ void row_products(const TG_GLOBAL T *__restrict__ sv,
 // Entries [k0, len) of row i's (K u_new)_i with u_new of every column from its
 // previous record (next_u), in entry order and rounds of kIterRound32 (the FP32
 // iterations: u_new in FP32, products and sum in FP64).
-template <typename T>
-__device__ __forceinline__ double row_tail_new_u(const TG_GLOBAL T *__restrict__ sv,
-                                                 const int32_t *__restrict__ sell_col,
+template <typename T, typename CI>
+__device__ __forceinline__ double row_tail_new_u(const TG_GLOBAL T *__restrict__ sv, const SellCols<CI> &cols, int rb,
                                                  const TG_GLOBAL Rec<T> *__restrict__ ra, int e, int k0, int len,
                                                  T alpha, T beta, double acc) {
     constexpr int R = kIterRound32;
@@ -448,7 +461,7 @@ __device__ __forceinline__ double row_tail_new_u(const TG_GLOBAL T *__restrict__
         for (int u = 0; u < R; ++u) {
             const int q = e + 64 * min(k + u, len - 1);
             val[u] = sv[q];
-            rc[u] = load_rec(ra, sell_col[q]);
+            rc[u] = load_rec(ra, cols(q, rb));
         }
 #pragma unroll
         for (int u = 0; u < R; ++u)
@@ -475,9 +488,9 @@ __device__ __forceinline__ double row_tail_new_u(const TG_GLOBAL T *__restrict__
 // records are fetched before the reduction and the new u of each column is
 // formed after it.  Waves own slices in XCD-contiguous ranges (neighbouring
 // rows' records stay in one L2).
-template <typename T, bool CHECK_ONLY, bool SOLO>
+template <typename T, bool CHECK_ONLY, bool SOLO, typename CI>
 __global__ __launch_bounds__(iter_threads<T>()) __attribute__((amdgpu_waves_per_eu(6)))
-void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const int32_t *__restrict__ sell_col,
+void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const CI *__restrict__ sell_col,
                      const PcgSlot *__restrict__ slots, const int32_t *__restrict__ list, PcgSlot solo, int step,
                      int n_prev_init, int n_prev) {
     constexpr int kThreads = iter_threads<T>(), W = kThreads / 64;
@@ -494,6 +507,7 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
     const TG_GLOBAL T *__restrict__ sv = gl((const T *)S.sell);
     TG_GLOBAL T *__restrict__ x = gl((T *)S.x);
     const int lane = threadIdx.x & 63;
+    const SellCols<CI> cols{sell_col};
     const int waves = gridDim.x * W;
     const int sl0 = xcd_swizzle(blockIdx.x, gridDim.x) * W + (int)(threadIdx.x >> 6);  // this wave's first slice
 
@@ -534,13 +548,13 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
         e0 = sell_ptr[s0] + lane;
         len0 = (sell_ptr[s0 + 1] - sell_ptr[s0]) >> 6;
         if constexpr (kSplit) {
-            if (sl0 < nsl && st->done == 0) row_products(sv, sell_col, ra, e0, len0, A, B, C);
+            if (sl0 < nsl && st->done == 0) row_products(sv, cols, i0, ra, e0, len0, A, B, C);
         } else {
 #pragma unroll
             for (int u = 0; u < R32; ++u) {  // clamped: entries past the row re-read its last one, unused
                 const int q = e0 + 64 * min(u, len0 - 1);
                 f_val[u] = sv[q];
-                f_rec[u] = load_rec(ra, sell_col[q]);
+                f_rec[u] = load_rec(ra, cols(q, i0));
             }
         }
         f_o = load_rec(ra, i0);
@@ -605,7 +619,7 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
 #pragma unroll
             for (int u = 0; u < R32; ++u)
                 if (u < len0) w += (double)f_val[u] * (double)next_u(f_rec[u], beta, alpha);
-            w = row_tail_new_u(sv, sell_col, ra, e0, R32, len0, alpha, beta, w);
+            w = row_tail_new_u(sv, cols, i0, ra, e0, R32, len0, alpha, beta, w);
         }
         if (s0 * 64 + lane < n) update_row(s0 * 64 + lane, w, f_o, f_pold, f_xold);
     }
@@ -618,10 +632,10 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
         double w;
         if constexpr (kSplit) {
             double a = 0.0, b = 0.0, c = 0.0;
-            row_products(sv, sell_col, ra, e, len, a, b, c);
+            row_products(sv, cols, ic, ra, e, len, a, b, c);
             w = a - alpha_d * (b + beta_d * c);
         } else {
-            w = row_tail_new_u(sv, sell_col, ra, e, 0, len, alpha, beta, 0.0);
+            w = row_tail_new_u(sv, cols, ic, ra, e, 0, len, alpha, beta, 0.0);
         }
         if (i < n) update_row(i, w, o, p_old, x_old);
     }
@@ -750,19 +764,26 @@ void launch_step_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *li
                    hipStream_t s, const PcgSlot *solo) {
     const int n = (int)pt.host.n_dofs, nsl = (int)pt.dev.n_slices;
     const int ns0 = spmv_blocks<G>(n), ns = iter_blocks<T>(pt);
-    if (solo)
-        hipLaunchKernelGGL((pcg_iter_kernel<T, false, true>), dim3(ns, 1), dim3(iter_threads<T>()), 0, s, n, nsl,
-                           pt.dev.sell_ptr, pt.dev.sell_col, slots, list, *solo, step, ns0, ns);
+    auto go = [&](auto *cols) {
+        using CI = std::remove_const_t<std::remove_pointer_t<decltype(cols)>>;
+        if (solo)
+            hipLaunchKernelGGL((pcg_iter_kernel<T, false, true, CI>), dim3(ns, 1), dim3(iter_threads<T>()), 0, s, n,
+                               nsl, pt.dev.sell_ptr, cols, slots, list, *solo, step, ns0, ns);
+        else
+            hipLaunchKernelGGL((pcg_iter_kernel<T, false, false, CI>), dim3(ns, count), dim3(iter_threads<T>()), 0, s,
+                               n, nsl, pt.dev.sell_ptr, cols, slots, list, PcgSlot{}, step, ns0, ns);
+    };
+    if (pt.dev.sell16)
+        go((const int16_t *)pt.dev.sell_off);
     else
-        hipLaunchKernelGGL((pcg_iter_kernel<T, false, false>), dim3(ns, count), dim3(iter_threads<T>()), 0, s, n, nsl,
-                           pt.dev.sell_ptr, pt.dev.sell_col, slots, list, PcgSlot{}, step, ns0, ns);
+        go((const int32_t *)pt.dev.sell_col);
 }
 
 template <typename T, int G>
 void launch_check_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *list, int count, int step,
                     hipStream_t s) {
     const int n = (int)pt.host.n_dofs;
-    hipLaunchKernelGGL((pcg_iter_kernel<T, true, false>), dim3(1, count), dim3(iter_threads<T>()), 0, s, n,
+    hipLaunchKernelGGL((pcg_iter_kernel<T, true, false, int32_t>), dim3(1, count), dim3(iter_threads<T>()), 0, s, n,
                        (int)pt.dev.n_slices, pt.dev.sell_ptr, pt.dev.sell_col, slots, list, PcgSlot{}, step,
                        spmv_blocks<G>(n), iter_blocks<T>(pt));
 }

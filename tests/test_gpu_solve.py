@@ -63,6 +63,29 @@ def test_pcg_fp64_matches_condensed_direct_solve(dim, n):
     assert err <= 1e-6
 
 
+def test_pcg_32bit_and_16bit_columns_agree():
+    """A random renumbering of a 35,937-vertex mesh puts columns more than 32767 from their rows, so the
+    CG iterations read 32-bit columns; the banded original numbering uses 16-bit offsets.  Both solves
+    reach the tolerance and agree after undoing the permutation."""
+    d = meshgen.poisson_inputs(3, 32, seed=0)
+    nv = len(d["coords"])
+    perm = np.random.default_rng(3).permutation(nv).astype(np.int32)
+    coords_p = np.empty_like(d["coords"])
+    coords_p[perm] = d["coords"]
+    xs = []
+    for conn, coords, width in ((d["conn"], d["coords"], 2), (perm[d["conn"]], coords_p, 4)):
+        pat = tg.Pattern(conn, nv)
+        assert pat.sell_index_bytes == width
+        vals, rhs = tg.assemble(pat, tg.LAPLACE, torch.from_numpy(coords).cuda(), torch.from_numpy(d["a"]).cuda(),
+                                torch.from_numpy(d["f"]).cuda())
+        tg.apply_dirichlet(pat, vals, rhs)
+        x, iters, relres = tg.pcg(pat, vals, rhs, rtol=1e-10, max_iter=10000)
+        assert relres <= 1e-10
+        xs.append(x.cpu().numpy())
+    x16, x32 = xs[0], xs[1][perm]
+    assert np.linalg.norm(x32 - x16) <= 1e-8 * np.linalg.norm(x16)
+
+
 def test_pcg_fp32():
     d, pat, vals, rhs = _setup(3, 12, dtype=torch.float32)
     tg.apply_dirichlet(pat, vals, rhs)

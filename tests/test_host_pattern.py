@@ -391,3 +391,17 @@ def test_p2_blocks_beyond_thread_counts():
     pat = tg.Pattern(d["conn"], len(d["coords"]), order=2, ncomp=3, host_only=True)
     rows, pairs, ents, verts = special_meshes.block_shapes(pat)
     assert ents.max() > 2 * 192 - 1 and verts.max() > 192 and pairs.max() <= 64
+
+
+def test_sell_index_width():
+    """The CG iterations read 16-bit column offsets when every column of the sliced-ELL pattern lies
+    within 32767 of its row (banded numberings), 32-bit columns otherwise."""
+    d = meshgen.poisson_inputs(3, 32, seed=0)
+    nv = len(d["coords"])
+    assert nv > 32768
+    assert tg.Pattern(d["conn"], nv, host_only=True).sell_index_bytes == 2
+    perm = np.random.default_rng(3).permutation(nv).astype(np.int32)
+    assert tg.Pattern(perm[d["conn"]], nv, host_only=True).sell_index_bytes == 4
+    small = meshgen.poisson_inputs(2, 12, seed=0)
+    sp = np.random.default_rng(4).permutation(len(small["coords"])).astype(np.int32)
+    assert tg.Pattern(sp[small["conn"]], len(small["coords"]), host_only=True).sell_index_bytes == 2
