@@ -22,8 +22,9 @@ constexpr int kP1BlockVerts = 256;  // distinct vertices of a block (8-bit local
 constexpr int kP2Threads = 192;  // three waves: one per set of column nodes
 // P2: one lane per pair in each wave, so at most 64 pairs; the target keeps an
 // FP64 block's LDS (about 0.55 KB per pair) within a fifth of the CU's 160 KB,
-// as many blocks as the FP64 kernel's registers allow.
-constexpr int kP2BlockTarget = 52;
+// as many blocks as the FP64 kernel's registers allow (measured at 32^3: 48
+// pairs FP64 as fast as 52, FP32 5% faster; 56 slower in both).
+constexpr int kP2BlockTarget = 48;
 constexpr int kP2BlockCap = 64;
 constexpr int kBlkDesc = 12;  // ints per row-block descriptor
 constexpr int kSellRows = 64;  // rows per slice of the sliced-ELL pattern: one per lane of a wave

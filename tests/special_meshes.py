@@ -8,6 +8,8 @@
   that element e owns vertices e, e + E, ..., e + d E: consecutive vertex rows belong to different
   elements, so a row block gathers many rows (P1: 256 rows of one pair each) and, in P2, many staged
   vertices and node entries.
+- private_star: m tets that share one vertex and nothing else: the shared vertex's row (m pairs, one
+  block of its own) stages 1 + 3 m distinct vertices and, in P2, holds 1 + 9 m node entries.
 """
 import numpy as np
 
@@ -50,3 +52,18 @@ def block_shapes(pat):
     br, ip, rp = r["blk_row"], r["inc_ptr"], r["node_rp"]
     vptr, _, _ = pat.block_vertices()
     return np.diff(br), ip[br[1:]] - ip[br[:-1]], rp[br[1:]] - rp[br[:-1]], np.diff(vptr)
+
+
+def private_star(m: int, seed: int):
+    rng = np.random.default_rng(seed)
+    coords = np.zeros((1 + 3 * m, 3))
+    conn = np.zeros((m, 4), dtype=np.int32)
+    for t in range(m):
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        u = np.cross(d, rng.standard_normal(3))
+        u /= np.linalg.norm(u)
+        w = np.cross(d, u)
+        coords[1 + 3 * t:4 + 3 * t] = [2.0 * d, 2.0 * d + 0.5 * u, 2.0 * d + 0.5 * w]
+        conn[t] = [0, 1 + 3 * t, 2 + 3 * t, 3 + 3 * t]
+    return {"coords": coords, "conn": conn, **_coefficients(m, rng)}

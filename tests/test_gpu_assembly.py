@@ -389,12 +389,14 @@ def test_p1_blocks_beyond_thread_counts_parity(mesh, dtype):
     assert _vec_rel(rb[2].double().cpu().numpy(), A2.rhs) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("mesh", ["disjoint", "star"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_p2_blocks_beyond_thread_counts_parity(dtype):
-    """P2 row blocks with 520 node entries and 208 staged vertices (the copies past 2 x 192 entries and
-    past 192 vertices)."""
-    print(f"p2 beyond-threads dtype={dtype}", flush=True)
-    _check_p2(special_meshes.disjoint_simplices(3, 120, 5), dtype)
+def test_p2_blocks_beyond_thread_counts_parity(dtype, mesh):
+    """P2 row blocks with 480 (disjoint tets) or 577 (a star of 64 tets sharing one vertex) node entries
+    and 193 staged vertices (the star): the copies past 2 x 192 entries and past 192 vertices."""
+    print(f"p2 beyond-threads mesh={mesh} dtype={dtype}", flush=True)
+    d = special_meshes.disjoint_simplices(3, 120, 5) if mesh == "disjoint" else special_meshes.private_star(64, 6)
+    _check_p2(d, dtype)
 
 
 _P2_32 = {}

@@ -385,12 +385,17 @@ def test_p2_block_capacity(m, ok):
 
 
 def test_p2_blocks_beyond_thread_counts():
-    """Interleaved disjoint tets: P2 row blocks with more node entries (520) than two per thread of the
-    192-thread kernel and more staged vertices (208) than threads."""
+    """P2 row blocks with more node entries than two per thread of the 192-thread kernel (interleaved
+    disjoint tets: 480; a star of 64 tets sharing one vertex: 577) and more staged vertices than threads
+    (the star: 193)."""
     d = special_meshes.disjoint_simplices(3, 120, 5)
     pat = tg.Pattern(d["conn"], len(d["coords"]), order=2, ncomp=3, host_only=True)
     rows, pairs, ents, verts = special_meshes.block_shapes(pat)
-    assert ents.max() > 2 * 192 - 1 and verts.max() > 192 and pairs.max() <= 64
+    assert ents.max() > 2 * 192 - 1 and pairs.max() <= 64
+    d = special_meshes.private_star(64, 6)
+    pat = tg.Pattern(d["conn"], len(d["coords"]), order=2, ncomp=3, host_only=True)
+    rows, pairs, ents, verts = special_meshes.block_shapes(pat)
+    assert ents.max() == 1 + 9 * 64 and verts.max() == 1 + 3 * 64 and pairs.max() == 64
 
 
 def test_sell_index_width():
