@@ -360,6 +360,8 @@ def main():
     gbs = balg64 / mean_asm / 1e9
     routing = "true" if pat.compact_routing() is not None else "false"  # the kernel instance the pattern selects
     traffic = stored_traffic(f"p1_assemble_kernel<3,double,0,true,false,{routing}>")
+    # the CG iteration instance the pattern selects (16-bit column offsets or 32-bit columns)
+    pcg_kernel = f"pcg_iter_kernel<double,false,true,{'short' if pat.sell_index_bytes == 2 else 'int'}>"
 
     out = {
         "metric": METRIC,
@@ -381,11 +383,11 @@ def main():
             "constrained_dofs": pat.n_constrained, "parallelism": "single GPU",
         },
         "roofline": {
-            "bound": "hbm", "kernel": "pcg_iter_kernel<double,false,true> (one CG iteration; the step's dominant "
-                                      "kernel: iterations x time per launch is most of ms_per_step)",
+            "bound": "hbm", "kernel": pcg_kernel + " (one CG iteration; the step's dominant "
+                                                   "kernel: iterations x time per launch is most of ms_per_step)",
             "achieved": PCG_ITER_BYTES_64 / t_iter / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": PCG_ITER_BYTES_64 / t_iter / 1e9 / HBM_PEAK_GBS,
-            "traffic": stored_traffic("pcg_iter_kernel<double,false,true>"),
+            "traffic": stored_traffic(pcg_kernel),
             "algorithmic_bytes_per_launch": PCG_ITER_BYTES_64, "us_per_launch": t_iter * 1e6,
             "launches_per_step": int(np.median(iters)),
             "attainable_gbs": attainable_gbs,
