@@ -203,11 +203,16 @@ __global__ __launch_bounds__(256) void spmv_kernel(int n, const int32_t *__restr
 // on the same pattern); blockIdx.x strides over the rows.  A slot's iteration
 // is step - start, so systems that joined at different steps share launches.
 // One iteration is one launch: the SpMV needs the new u at neighbouring rows,
-// which every block recomputes from the previous iteration's record
-// {r, w, s, dinv} of that row with the same expressions its owner uses, so the
-// values agree bitwise and no grid-wide barrier is needed.  Records are double
-// buffered by iteration parity (the owner writes the new record while
-// neighbours still read the old one).
+// which every block recomputes from the previous iteration's record of that
+// row with the same expressions its owner uses, so the values agree bitwise
+// and no grid-wide barrier is needed.  The record holds the row's r, w and s
+// scaled by D^{-1} (u = D^{-1} r, D^{-1} w, D^{-1} s): the recurrences are
+// linear, so they run unchanged on the scaled values, the new u is
+// u - alpha (D^{-1} w + beta D^{-1} s), and w's update needs D^{-1} K u, one
+// product by the row's own D^{-1}; the inner products use the diagonal K_ii
+// (r = K_ii u).  Three values per gathered record instead of four.  Records
+// are double buffered by iteration parity (the owner writes the new record
+// while neighbours still read the old one).
 
 // A slot's arrays are reached through pointers read from memory, which the
 // compiler cannot place in an address space; casting them to the global one
@@ -219,55 +224,72 @@ __device__ __forceinline__ TG_GLOBAL T *gl(T *p) {
 }
 
 template <typename T>
-struct Rec {  // the per-row record gathered by the SpMV
-    T r, w, s, d;
+struct Rec {  // the per-row record gathered by the SpMV: u = D^{-1} r, D^{-1} w, D^{-1} s
+    T u, w, s;
 };
 
+// The record in memory: 24 bytes (FP64) or 12 bytes (FP32).
+template <typename T>
+struct RecMem {
+    T u, w, s;
+};
+
+template <typename T>
+struct Diag {  // a row's D^{-1} = 1 / K_ii and K_ii
+    T d, k;
+};
+
+// A slot's workspace (kPcgWorkVectors vectors of n values): the records of even
+// and odd iterates (3 n each), p (n) and the diagonal pairs (2 n).
 template <typename T>
 struct SlotVecs {
-    TG_GLOBAL Rec<T> *rec0, *rec1;  // records of even and odd iterates
+    TG_GLOBAL RecMem<T> *rec0, *rec1;
     TG_GLOBAL T *p;
+    TG_GLOBAL Diag<T> *dk;
     __device__ __forceinline__ SlotVecs(const PcgSlot &S, int n) {
-        rec0 = gl((Rec<T> *)S.work);
+        rec0 = gl((RecMem<T> *)S.work);
         rec1 = rec0 + n;
         p = (TG_GLOBAL T *)(rec1 + n);
+        dk = (TG_GLOBAL Diag<T> *)(p + n);
     }
-    __device__ __forceinline__ TG_GLOBAL Rec<T> *rec(int parity) const { return parity ? rec1 : rec0; }
-};
-
-// One record as one aligned 32-byte (FP64) or 16-byte (FP32) access.
-template <typename T>
-struct alignas(4 * sizeof(T)) Rec4 {
-    T v[4];
+    __device__ __forceinline__ TG_GLOBAL RecMem<T> *rec(int parity) const { return parity ? rec1 : rec0; }
 };
 
 template <typename T>
-__device__ __forceinline__ Rec<T> load_rec(const TG_GLOBAL Rec<T> *__restrict__ a, int i) {
-    const TG_GLOBAL Rec4<T> *q = reinterpret_cast<const TG_GLOBAL Rec4<T> *>(a + i);
-    return Rec<T>{q->v[0], q->v[1], q->v[2], q->v[3]};
+__device__ __forceinline__ Rec<T> load_rec(const TG_GLOBAL RecMem<T> *__restrict__ a, int i) {
+    return Rec<T>{a[i].u, a[i].w, a[i].s};
 }
 
 template <typename T>
-__device__ __forceinline__ void store_rec(TG_GLOBAL Rec<T> *__restrict__ a, int i, T r, T w, T s, T d) {
-    TG_GLOBAL Rec4<T> *q = reinterpret_cast<TG_GLOBAL Rec4<T> *>(a + i);
-    q->v[0] = r;
-    q->v[1] = w;
-    q->v[2] = s;
-    q->v[3] = d;
+__device__ __forceinline__ void store_rec(TG_GLOBAL RecMem<T> *__restrict__ a, int i, T u, T w, T s) {
+    a[i].u = u;
+    a[i].w = w;
+    a[i].s = s;
 }
 
-// The recurrences of a row's s, r and u: the owner's update, and (FP32
+template <typename T>
+__device__ __forceinline__ Diag<T> load_dk(const TG_GLOBAL Diag<T> *__restrict__ a, int i) {
+    return Diag<T>{a[i].d, a[i].k};
+}
+
+template <typename T>
+__device__ __forceinline__ void store_dk(TG_GLOBAL Diag<T> *__restrict__ a, int i, T d, T k) {
+    a[i].d = d;
+    a[i].k = k;
+}
+
+// The recurrences of a row's scaled s and u: the owner's update, and (FP32
 // iterations) every neighbour's view of the row's new u as an SpMV column.
 template <typename T>
 __device__ __forceinline__ T next_s(const Rec<T> &o, T beta) { return o.w + beta * o.s; }
 template <typename T>
-__device__ __forceinline__ T next_r(const Rec<T> &o, T s_new, T alpha) { return o.r - alpha * s_new; }
+__device__ __forceinline__ T next_u_s(const Rec<T> &o, T s_new, T alpha) { return o.u - alpha * s_new; }
 template <typename T>
 __device__ __forceinline__ T next_u(const Rec<T> &o, T beta, T alpha) {
-    return o.d * next_r(o, next_s(o, beta), alpha);
+    return next_u_s(o, next_s(o, beta), alpha);
 }
 
-// x = 0, p = 0, r = b, s = 0, dinv = 1 / diag (record of parity 0; w follows).
+// x = 0, p = 0, u = D^{-1} b, s = 0, the diagonal pairs (record of parity 0; w follows).
 template <typename T>
 __global__ __launch_bounds__(kVecThreads) void pcg_init_kernel(int n, const PcgSlot *__restrict__ slots,
                                                                const int32_t *__restrict__ list,
@@ -280,12 +302,14 @@ __global__ __launch_bounds__(kVecThreads) void pcg_init_kernel(int n, const PcgS
     for (int i = blockIdx.x * kVecThreads + threadIdx.x; i < n; i += gridDim.x * kVecThreads) {
         x[i] = (T)0;
         v.p[i] = (T)0;
-        store_rec(v.rec0, i, b[i], (T)0, (T)0, (T)1 / values[diag_pos[i]]);
+        const T kii = values[diag_pos[i]], d = (T)1 / kii;
+        store_dk(v.dk, i, d, kii);
+        store_rec(v.rec0, i, d * b[i], (T)0, (T)0);
     }
 }
 
-// Warm start: r = b - K x for the given x, p = 0, s = 0, dinv = 1 / diag
-// (record of parity 0; w follows), and per-block partials of b.b at kResid.
+// Warm start: u = D^{-1} (b - K x) for the given x, p = 0, s = 0, the diagonal
+// pairs (record of parity 0; w follows), and per-block partials of b.b at kResid.
 template <typename T, int G>
 __global__ __launch_bounds__(kVecThreads, 8) void pcg_warm_init_kernel(int n, const int32_t *__restrict__ row_ptr,
                                                                     const int32_t *__restrict__ col_idx,
@@ -306,7 +330,9 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_warm_init_kernel(int n, co
         if (lane == 0) {
             const T bi = b[i];
             v.p[i] = (T)0;
-            store_rec(v.rec0, i, (T)((double)bi - kx), (T)0, (T)0, (T)1 / values[diag_pos[i]]);
+            const T kii = values[diag_pos[i]], d = (T)1 / kii;
+            store_dk(v.dk, i, d, kii);
+            store_rec(v.rec0, i, d * (T)((double)bi - kx), (T)0, (T)0);
             bb += (double)bi * (double)bi;
         }
     }
@@ -327,9 +353,9 @@ __global__ __launch_bounds__(kVecThreads) void pcg_warm_tol_kernel(const PcgSlot
     }
 }
 
-// w_0 = K u_0 with u_0 = dinv r_0, and partials of r.u, w.u, r.r (parity 0).
-// Reads the r and dinv fields of neighbouring records and writes only the w
-// field of its own rows.
+// w_0 = K u_0 (stored scaled by D^{-1}), and partials of r.u, w.u, r.r with
+// r = K_ii u (parity 0).  Reads the u field of neighbouring records and writes
+// only the w field of its own rows.
 template <typename T, int G>
 __global__ __launch_bounds__(kVecThreads, 8) void pcg_init_spmv_kernel(int n, const int32_t *__restrict__ row_ptr,
                                                                     const int32_t *__restrict__ col_idx,
@@ -338,7 +364,7 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_init_spmv_kernel(int n, co
     __shared__ double sh[3 * kWaves];
     const PcgSlot S = slots[list[blockIdx.y]];
     const SlotVecs<T> v(S, n);
-    TG_GLOBAL Rec<T> *__restrict__ rec = v.rec0;
+    TG_GLOBAL RecMem<T> *__restrict__ rec = v.rec0;
     const TG_GLOBAL T *__restrict__ values = gl((const T *)S.values);
     const int lane = threadIdx.x % G;
     const int rows_per_grid = gridDim.x * (kVecThreads / G);
@@ -349,15 +375,16 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_init_spmv_kernel(int n, co
 #pragma unroll 2
         for (int q = p0 + lane; q < p1; q += G) {
             const int j = col_idx[q];
-            acc += (double)values[q] * (double)(rec[j].d * rec[j].r);
+            acc += (double)values[q] * (double)rec[j].u;
         }
         acc = group_sum<G>(acc);
         if (lane == 0) {
-            const T ri = rec[i].r, ui = rec[i].d * ri, wi = (T)acc;
-            rec[i].w = wi;
-            gam += (double)ri * (double)ui;
-            del += (double)wi * (double)ui;
-            rr += (double)ri * (double)ri;
+            const Diag<T> dk = load_dk(v.dk, i);
+            const double ui = (double)rec[i].u, ri = (double)dk.k * ui;
+            rec[i].w = (T)((double)dk.d * acc);
+            gam += ri * ui;
+            del += acc * ui;
+            rr += ri * ri;
         }
     }
     block_sum3_first(gam, del, rr, sh);
@@ -398,16 +425,17 @@ constexpr int kIterRound = 3;
 constexpr int kIterRound32 = 4;
 
 // The three products of row i that give (K u_new)_i once alpha and beta are
-// known: with u_new = D r_new and r_new = r - alpha (w + beta s),
-//   K u_new = K D r - alpha (K D w + beta K D s),
-// and K D r, K D w, K D s need only the previous iterate's records.  Entries
+// known: with the scaled record (u, D^{-1} w, D^{-1} s) and
+// u_new = u - alpha (D^{-1} w + beta D^{-1} s),
+//   K u_new = K u - alpha (K D^{-1} w + beta K D^{-1} s),
+// and the three products need only the previous iterate's records.  Entries
 // [0, len) of the row start at q = e and stride 64 (sliced-ELL); each product
 // sums the row's terms in entry order.  The loop is software-pipelined: the
 // next round's columns and values are requested before this round's records
 // are consumed.
 template <typename T, typename CI>
 __device__ __forceinline__ void row_products(const TG_GLOBAL T *__restrict__ sv, const SellCols<CI> &cols, int rb,
-                                             const TG_GLOBAL Rec<T> *__restrict__ ra, int e, int len, double &A,
+                                             const TG_GLOBAL RecMem<T> *__restrict__ ra, int e, int len, double &A,
                                              double &B, double &C) {
     constexpr int R = kIterRound;
     int c[R];
@@ -433,8 +461,8 @@ __device__ __forceinline__ void row_products(const TG_GLOBAL T *__restrict__ sv,
 #pragma unroll
         for (int u = 0; u < R; ++u)
             if (k + u < len) {
-                const double vd = (double)val[u] * (double)rc[u].d;
-                A += vd * (double)rc[u].r;
+                const double vd = (double)val[u];
+                A += vd * (double)rc[u].u;
                 B += vd * (double)rc[u].w;
                 C += vd * (double)rc[u].s;
             }
@@ -451,7 +479,7 @@ __device__ __forceinline__ void row_products(const TG_GLOBAL T *__restrict__ sv,
 // iterations: u_new in FP32, products and sum in FP64).
 template <typename T, typename CI>
 __device__ __forceinline__ double row_tail_new_u(const TG_GLOBAL T *__restrict__ sv, const SellCols<CI> &cols, int rb,
-                                                 const TG_GLOBAL Rec<T> *__restrict__ ra, int e, int k0, int len,
+                                                 const TG_GLOBAL RecMem<T> *__restrict__ ra, int e, int k0, int len,
                                                  T alpha, T beta, double acc) {
     constexpr int R = kIterRound32;
     for (int k = k0; k < len; k += R) {
@@ -502,8 +530,8 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
     const int it = step - S.start;
     const int cur = 3 * (it & 1), nxt = 3 * ((it + 1) & 1);
     const SlotVecs<T> v(S, n);
-    const TG_GLOBAL Rec<T> *__restrict__ ra = v.rec(it & 1);
-    TG_GLOBAL Rec<T> *__restrict__ rb = v.rec((it + 1) & 1);
+    const TG_GLOBAL RecMem<T> *__restrict__ ra = v.rec(it & 1);
+    TG_GLOBAL RecMem<T> *__restrict__ rb = v.rec((it + 1) & 1);
     const TG_GLOBAL T *__restrict__ sv = gl((const T *)S.sell);
     TG_GLOBAL T *__restrict__ x = gl((T *)S.x);
     const int lane = threadIdx.x & 63;
@@ -539,6 +567,7 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
     const int s0 = min(sl0, nsl - 1);
     const int i0 = min(s0 * 64 + lane, n - 1);
     Rec<T> f_o{};
+    Diag<T> f_dk{};
     T f_pold = 0, f_xold = 0;
     double A = 0.0, B = 0.0, C = 0.0;
     int e0 = 0, len0 = 0;
@@ -558,6 +587,7 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
             }
         }
         f_o = load_rec(ra, i0);
+        f_dk = load_dk(v.dk, i0);
         f_pold = v.p[i0];
         f_xold = x[i0];
     }
@@ -596,19 +626,20 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
     }
     const T alpha = (T)alpha_d, beta = (T)beta_d;
     double gn = 0.0, dn = 0.0, rn = 0.0;
-    // row i's update from its own record, p, x and w = (K u_new)_i
-    auto update_row = [&](int i, double w, const Rec<T> &o, T p_old, T x_old) {
-        const T pi = o.d * o.r + beta * p_old;  // u_i + beta p
+    // row i's update from its own record, diagonal pair, p, x and w = (K u_new)_i;
+    // the inner products with r = K_ii u
+    auto update_row = [&](int i, double w, const Rec<T> &o, const Diag<T> &dk, T p_old, T x_old) {
+        const T pi = o.u + beta * p_old;  // u_i + beta p
         const T si = next_s(o, beta);
-        const T ri = next_r(o, si, alpha);
-        const T ui = o.d * ri;
+        const T ui = next_u_s(o, si, alpha);
         const T wi = (T)w;
         x[i] = x_old + alpha * pi;
         v.p[i] = pi;
-        store_rec(rb, i, ri, wi, si, o.d);
-        gn += (double)ri * (double)ui;
-        dn += (double)wi * (double)ui;
-        rn += (double)ri * (double)ri;
+        store_rec(rb, i, ui, (T)((double)dk.d * w), si);
+        const double ud = (double)ui, rd = (double)dk.k * ud;
+        gn += rd * ud;
+        dn += (double)wi * ud;
+        rn += rd * rd;
     };
     if (sl0 < nsl) {
         double w;
@@ -621,12 +652,13 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
                 if (u < len0) w += (double)f_val[u] * (double)next_u(f_rec[u], beta, alpha);
             w = row_tail_new_u(sv, cols, i0, ra, e0, R32, len0, alpha, beta, w);
         }
-        if (s0 * 64 + lane < n) update_row(s0 * 64 + lane, w, f_o, f_pold, f_xold);
+        if (s0 * 64 + lane < n) update_row(s0 * 64 + lane, w, f_o, f_dk, f_pold, f_xold);
     }
     for (int sl = sl0 + waves; sl < nsl; sl += waves) {  // systems with more slices than waves
         const int i = sl * 64 + lane;
         const int ic = min(i, n - 1);
         const Rec<T> o = load_rec(ra, ic);
+        const Diag<T> dk = load_dk(v.dk, ic);
         const T p_old = v.p[ic], x_old = x[ic];
         const int e = sell_ptr[sl] + lane, len = (sell_ptr[sl + 1] - sell_ptr[sl]) >> 6;
         double w;
@@ -637,7 +669,7 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
         } else {
             w = row_tail_new_u(sv, cols, ic, ra, e, 0, len, alpha, beta, 0.0);
         }
-        if (i < n) update_row(i, w, o, p_old, x_old);
+        if (i < n) update_row(i, w, o, dk, p_old, x_old);
     }
     block_sum3_first<W>(gn, dn, rn, sh2);
     if (threadIdx.x == 0) {
