@@ -224,13 +224,7 @@ __device__ __forceinline__ TG_GLOBAL T *gl(T *p) {
 }
 
 template <typename T>
-struct Rec {  // the per-row record gathered by the SpMV: u = D^{-1} r, D^{-1} w, D^{-1} s
-    T u, w, s;
-};
-
-// The record in memory: 24 bytes (FP64) or 12 bytes (FP32).
-template <typename T>
-struct RecMem {
+struct Rec {  // the per-row record gathered by the SpMV (24 / 12 bytes): u = D^{-1} r, D^{-1} w, D^{-1} s
     T u, w, s;
 };
 
@@ -243,25 +237,25 @@ struct Diag {  // a row's D^{-1} = 1 / K_ii and K_ii
 // and odd iterates (3 n each), p (n) and the diagonal pairs (2 n).
 template <typename T>
 struct SlotVecs {
-    TG_GLOBAL RecMem<T> *rec0, *rec1;
+    TG_GLOBAL Rec<T> *rec0, *rec1;
     TG_GLOBAL T *p;
     TG_GLOBAL Diag<T> *dk;
     __device__ __forceinline__ SlotVecs(const PcgSlot &S, int n) {
-        rec0 = gl((RecMem<T> *)S.work);
+        rec0 = gl((Rec<T> *)S.work);
         rec1 = rec0 + n;
         p = (TG_GLOBAL T *)(rec1 + n);
         dk = (TG_GLOBAL Diag<T> *)(p + n);
     }
-    __device__ __forceinline__ TG_GLOBAL RecMem<T> *rec(int parity) const { return parity ? rec1 : rec0; }
+    __device__ __forceinline__ TG_GLOBAL Rec<T> *rec(int parity) const { return parity ? rec1 : rec0; }
 };
 
 template <typename T>
-__device__ __forceinline__ Rec<T> load_rec(const TG_GLOBAL RecMem<T> *__restrict__ a, int i) {
+__device__ __forceinline__ Rec<T> load_rec(const TG_GLOBAL Rec<T> *__restrict__ a, int i) {
     return Rec<T>{a[i].u, a[i].w, a[i].s};
 }
 
 template <typename T>
-__device__ __forceinline__ void store_rec(TG_GLOBAL RecMem<T> *__restrict__ a, int i, T u, T w, T s) {
+__device__ __forceinline__ void store_rec(TG_GLOBAL Rec<T> *__restrict__ a, int i, T u, T w, T s) {
     a[i].u = u;
     a[i].w = w;
     a[i].s = s;
@@ -364,7 +358,7 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_init_spmv_kernel(int n, co
     __shared__ double sh[3 * kWaves];
     const PcgSlot S = slots[list[blockIdx.y]];
     const SlotVecs<T> v(S, n);
-    TG_GLOBAL RecMem<T> *__restrict__ rec = v.rec0;
+    TG_GLOBAL Rec<T> *__restrict__ rec = v.rec0;
     const TG_GLOBAL T *__restrict__ values = gl((const T *)S.values);
     const int lane = threadIdx.x % G;
     const int rows_per_grid = gridDim.x * (kVecThreads / G);
@@ -435,7 +429,7 @@ constexpr int kIterRound32 = 4;
 // are consumed.
 template <typename T, typename CI>
 __device__ __forceinline__ void row_products(const TG_GLOBAL T *__restrict__ sv, const SellCols<CI> &cols, int rb,
-                                             const TG_GLOBAL RecMem<T> *__restrict__ ra, int e, int len, double &A,
+                                             const TG_GLOBAL Rec<T> *__restrict__ ra, int e, int len, double &A,
                                              double &B, double &C) {
     constexpr int R = kIterRound;
     int c[R];
@@ -479,7 +473,7 @@ __device__ __forceinline__ void row_products(const TG_GLOBAL T *__restrict__ sv,
 // iterations: u_new in FP32, products and sum in FP64).
 template <typename T, typename CI>
 __device__ __forceinline__ double row_tail_new_u(const TG_GLOBAL T *__restrict__ sv, const SellCols<CI> &cols, int rb,
-                                                 const TG_GLOBAL RecMem<T> *__restrict__ ra, int e, int k0, int len,
+                                                 const TG_GLOBAL Rec<T> *__restrict__ ra, int e, int k0, int len,
                                                  T alpha, T beta, double acc) {
     constexpr int R = kIterRound32;
     for (int k = k0; k < len; k += R) {
@@ -530,8 +524,8 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
     const int it = step - S.start;
     const int cur = 3 * (it & 1), nxt = 3 * ((it + 1) & 1);
     const SlotVecs<T> v(S, n);
-    const TG_GLOBAL RecMem<T> *__restrict__ ra = v.rec(it & 1);
-    TG_GLOBAL RecMem<T> *__restrict__ rb = v.rec((it + 1) & 1);
+    const TG_GLOBAL Rec<T> *__restrict__ ra = v.rec(it & 1);
+    TG_GLOBAL Rec<T> *__restrict__ rb = v.rec((it + 1) & 1);
     const TG_GLOBAL T *__restrict__ sv = gl((const T *)S.sell);
     TG_GLOBAL T *__restrict__ x = gl((T *)S.x);
     const int lane = threadIdx.x & 63;
