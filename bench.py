@@ -106,11 +106,12 @@ def traffic_from_pmc(fetch_csv: str, write_csv: str, out_json: str, workload: st
                                  "fetch_scale": fs, "write_scale": ws,
                                  "bytes_per_launch": int(round((f * fs + w * ws) * 1024)),
                                  "dispatches": len(fetch[name])}
-    try:  # merge into the stored measurements (other workloads' kernels stay)
+    try:  # merge into the stored measurements (other workloads' kernels stay; this workload's are replaced)
         with open(out_json) as fh:
             old = json.load(fh)
     except (OSError, ValueError):
         old = {}
+    old = {k: v for k, v in old.items() if not k.startswith(workload + ":")}
     old.update(rec)
     with open(out_json, "w") as fh:
         json.dump(old, fh, indent=1, sort_keys=True)
