@@ -202,6 +202,20 @@ tg_status tg_pattern_copy_block_vertices(const tg_pattern *p, int64_t *n_vert, i
 tg_status tg_pattern_copy_routing(const tg_pattern *p, int32_t *h_inc_ptr, int32_t *h_inc, int32_t *h_blk_row,
                                   int32_t *h_node_rp, int32_t *h_seg_ptr, uint16_t *h_slot);
 
+/*
+ * The sliced-ELL pattern the CG iterations read: slice s holds the 64 scalar
+ * rows [64 s, 64 s + 64); entry k of row r sits at h_sell_ptr[s] + 64 k + r % 64
+ * (array [ceil(n_dofs / 64) + 1]); every row is padded to its slice's longest
+ * row with the column min(r, n_dofs - 1) (value 0).  h_cols [*n_entries]
+ * receives every entry's column (decoded); when sell_index_bytes
+ * (tg_pattern_info) is 2 the kernels read h_offsets [*n_entries] instead, the
+ * 16-bit offset of the column from min(r, n_dofs - 1) (not written otherwise).
+ * *n_entries receives h_sell_ptr's last value (call with NULL arrays first).
+ * Any pointer may be NULL.
+ */
+tg_status tg_pattern_copy_sell(const tg_pattern *p, int64_t *n_entries, int32_t *h_sell_ptr, int32_t *h_cols,
+                               int16_t *h_offsets);
+
 /* Free the pattern and its device memory.  Work using it must have completed. */
 void tg_pattern_destroy(tg_pattern *p);
 

@@ -83,6 +83,8 @@ _SIGS = {
                                                ctypes.POINTER(ctypes.c_uint16)]),
     "tg_pattern_copy_block_vertices": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), _i32p, _i32p,
                                                       ctypes.POINTER(ctypes.c_uint32)]),
+    "tg_pattern_copy_sell": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), _i32p, _i32p,
+                                            ctypes.POINTER(ctypes.c_int16)]),
     "tg_pattern_copy_compact_routing": (ctypes.c_int, [_vp, _i32p, ctypes.POINTER(ctypes.c_uint16),
                                                        ctypes.POINTER(ctypes.c_uint8)]),
     "tg_pattern_destroy": (None, [_vp]),
@@ -276,6 +278,19 @@ class Pattern:
             self._h, *(out[k].ctypes.data_as(_i32p) for k in ("inc_ptr", "inc", "blk_row", "node_rp", "seg_ptr")),
             out["slot"].ctypes.data_as(ctypes.POINTER(ctypes.c_uint16))))
         return out
+
+    def sell(self):
+        """(sell_ptr, cols, offsets) of the CG iterations' sliced-ELL pattern; offsets is None when the
+        kernels read 32-bit columns (see tg_pattern_copy_sell)."""
+        ne = ctypes.c_int64(0)
+        _check(_lib.tg_pattern_copy_sell(self._h, ctypes.byref(ne), None, None, None))
+        ptr = np.zeros((self.n_dofs + 63) // 64 + 1, np.int32)
+        cols = np.zeros(max(1, ne.value), np.int32)
+        off = np.zeros(max(1, ne.value), np.int16) if self.sell_index_bytes == 2 else None
+        _check(_lib.tg_pattern_copy_sell(self._h, ctypes.byref(ne), ptr.ctypes.data_as(_i32p),
+                                         cols.ctypes.data_as(_i32p),
+                                         None if off is None else off.ctypes.data_as(ctypes.POINTER(ctypes.c_int16))))
+        return ptr, cols[:ne.value], None if off is None else off[:ne.value]
 
     def compact_routing(self):
         """(ent16 [Z], slot8) of the P1 kernel's one-byte routing, or None when the pattern uses the wide form

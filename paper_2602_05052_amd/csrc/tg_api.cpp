@@ -266,6 +266,28 @@ tg_status tg_pattern_copy_routing(const tg_pattern *p, int32_t *h_inc_ptr, int32
     return ok();
 }
 
+tg_status tg_pattern_copy_sell(const tg_pattern *p, int64_t *n_entries, int32_t *h_sell_ptr, int32_t *h_cols,
+                               int16_t *h_offsets) {
+    if (!p) return fail(TG_E_ARG, "pattern is NULL");
+    const tg::HostPattern &h = p->host;
+    const int64_t ne = h.sell_ptr.empty() ? 0 : (int64_t)h.sell_ptr.back();
+    if (n_entries) *n_entries = ne;
+    if (h_sell_ptr) std::memcpy(h_sell_ptr, h.sell_ptr.data(), sizeof(int32_t) * h.sell_ptr.size());
+    if (h_cols) {
+        if (h.sell_off.empty()) {
+            std::memcpy(h_cols, h.sell_col.data(), sizeof(int32_t) * h.sell_col.size());
+        } else {
+            const int64_t nsl = (int64_t)h.sell_ptr.size() - 1;
+            for (int64_t s = 0; s < nsl; ++s)
+                for (int64_t q = h.sell_ptr[s]; q < h.sell_ptr[s + 1]; ++q)
+                    h_cols[q] = (int32_t)(std::min<int64_t>(s * tg::kSellRows + q % tg::kSellRows, h.n_dofs - 1) +
+                                          h.sell_off[q]);
+        }
+    }
+    if (h_offsets && !h.sell_off.empty()) std::memcpy(h_offsets, h.sell_off.data(), sizeof(int16_t) * ne);
+    return ok();
+}
+
 tg_status tg_pattern_copy_compact_routing(const tg_pattern *p, int32_t *compact, uint16_t *h_ent16,
                                           uint8_t *h_slot8) {
     if (!p) return fail(TG_E_ARG, "pattern is NULL");
