@@ -33,7 +33,7 @@ hipError_t upload(const std::vector<V> &h, V **d, size_t &bytes) {
 }
 
 void free_device(tg::DevicePattern &d) {
-    void *ptrs[] = {d.conn,    d.inc_ptr, d.inc,      d.blk_row,     d.blk_desc, d.node_rp, d.node_ci, d.seg_ptr,
+    void *ptrs[] = {d.conn,    d.inc_ptr, d.inc,      d.blk_row,     d.blk_desc, d.node_rp, d.node_ci, d.node_vp, d.seg_ptr,
                     d.blk_vert, d.pair_lv,
                     d.slot,    d.ent16,   d.slot8,    d.row_ptr,     d.col_idx, d.diag_pos, d.constrained,
                     d.work,    d.partials, d.state, d.dir_rows,  d.pcg_slot, d.pcg_list, d.sell_ptr,
@@ -52,7 +52,7 @@ void free_device(tg::DevicePattern &d) {
 // the upload and for the byte count the request server plans with.
 #define TG_PATTERN_ARRAYS(X)                                                                                   \
     X(conn, conn) X(inc_ptr, inc_ptr) X(inc, inc) X(blk_row, blk_row) X(blk_desc, blk_desc) X(blk_vert, blk_vert) \
-    X(pair_lv, pair_lv) X(node_rp, node_rp) X(node_ci, node_ci) X(seg_ptr, seg_ptr) X(slot, slot) X(ent16, ent16) \
+    X(pair_lv, pair_lv) X(node_rp, node_rp) X(node_ci, node_ci) X(node_vp, node_vp) X(seg_ptr, seg_ptr) X(slot, slot) X(ent16, ent16) \
     X(slot8, slot8) X(row_ptr, row_ptr) X(col_idx, col_idx) X(diag_pos, diag_pos) X(constrained, constrained)    \
     X(dirichlet_rows, dir_rows) X(sell_ptr, sell_ptr) X(sell_col, sell_col) X(sell_off, sell_off)
 

@@ -672,20 +672,26 @@ __device__ __forceinline__ double p2_ref_integral(int n) {
 // Reduce of one column class of a P2 block: one lane per node-level entry
 // whose column is an edge node (edge) or a vertex node (!edge) sums its routed
 // 3x3 blocks (ascending element order, components in parallel) and writes the
-// 9 scalars.  The class's blocks sit in LDS at (slot - first slot of the
-// class) * 9, slot = b np + pair.  Entry pe of row r, column position jpos,
-// lands at 9 sRp[r] + c (3 m) + 3 jpos + cc of the block's value range (the 3
-// DoF rows of a node share its columns).
+// 9 scalars.  A row's vertex-node columns precede its edge-node columns
+// (vertices are numbered first), so the class's entries of block row r are a
+// run of the row: cls[r] of them come before it in the block (cls = sVp or
+// sEp, block-relative prefixes), and lane t takes the class's t-th entry.
+// The class's blocks sit in LDS at (slot - first slot of the class) * 9, slot
+// = b np + pair.  Entry pe of row r, column position jpos, lands at 9 sRp[r]
+// + c (3 m) + 3 jpos + cc of the block's value range (the 3 DoF rows of a
+// node share its columns).  Diagonal entries (empty segments) are skipped.
 template <typename T>
-__device__ __forceinline__ void p2_reduce(const BlockLds<T> &L, const int *sRp, int np, int nent, bool edge,
-                                          T *__restrict__ out) {
+__device__ __forceinline__ void p2_reduce(const BlockLds<T> &L, const int *sRp, const int *sVp, const int *cls,
+                                          int ncls, int np, bool edge, T *__restrict__ out) {
     const int first = edge ? 4 * np : 0;
-    for (int pe = threadIdx.x; pe < nent; pe += kP2Threads) {
-        const int u0 = L.seg[pe], u1 = L.seg[pe + 1];
-        if (u0 == u1 || ((int)L.slot[u0] >= 4 * np) != edge) continue;
+    for (int t = threadIdx.x; t < ncls; t += kP2Threads) {
         int r = 0;
-        while (sRp[r + 1] <= pe) ++r;
-        const int m = sRp[r + 1] - sRp[r], jpos = pe - sRp[r];
+        while (cls[r + 1] <= t) ++r;
+        const int m = sRp[r + 1] - sRp[r];
+        const int jpos = (edge ? sVp[r + 1] - sVp[r] : 0) + (t - cls[r]);
+        const int pe = sRp[r] + jpos;
+        const int u0 = L.seg[pe], u1 = L.seg[pe + 1];
+        if (u0 == u1) continue;
         T acc[9];
 #pragma unroll
         for (int z = 0; z < 9; ++z) acc[z] = 0;
@@ -707,10 +713,11 @@ __device__ __forceinline__ void p2_reduce(const BlockLds<T> &L, const int *sRp, 
 // row r is the sum, over the row's pairs t in S_vec (ascending element) order,
 // of component z of the pair's block (a_t, a_t); nine lanes per row.  The
 // routing lists no slots for these entries.  Written at the scalar CSR
-// positions diag_pos[3 i + c] + (c' - c).
+// positions diag_pos[3 i] + c (3 m) + c' (m: node entries of the row; sDp[r]
+// = diag_pos[3 i] for the block's row r of node i).
 template <typename T>
 __device__ __forceinline__ void p2_reduce_diagonal(const BlockLds<T> &L, const int *sIp, const uint8_t *sA,
-                                                   const int *sDp, int nrows, int np, bool edge,
+                                                   const int *sDp, const int *sRp, int nrows, int np, bool edge,
                                                    T *__restrict__ values) {
     const int cs = np * 9, b0 = edge ? 4 : 0;
     for (int u = threadIdx.x; u < 9 * nrows; u += kP2Threads) {
@@ -720,17 +727,18 @@ __device__ __forceinline__ void p2_reduce_diagonal(const BlockLds<T> &L, const i
         T acc = 0;
         for (int t = t0; t < t1; ++t) acc += L.K[((int)sA[t] - b0) * cs + t * 9 + z];
         const int c = z / 3;
-        values[sDp[3 * r + c] + (z - 3 * c) - c] = acc;
+        values[sDp[r] + c * 3 * (sRp[r + 1] - sRp[r]) + (z - 3 * c)] = acc;
     }
 }
 
 template <typename T>
 __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     const int32_t *__restrict__ blk_desc, const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc,
-    const int32_t *__restrict__ node_rp, const int32_t *__restrict__ seg_ptr, const uint16_t *__restrict__ slot,
-    const int32_t *__restrict__ blk_vert, const uint32_t *__restrict__ pair_lv, const int32_t *__restrict__ diag_pos,
-    const double *__restrict__ coords, const T *__restrict__ coef, const T *__restrict__ load, T *__restrict__ values,
-    T *__restrict__ rhs, int32_t *__restrict__ status, int nblk, int E, int mp, int me) {
+    const int32_t *__restrict__ node_rp, const int32_t *__restrict__ node_vp, const int32_t *__restrict__ seg_ptr,
+    const uint16_t *__restrict__ slot, const int32_t *__restrict__ blk_vert, const uint32_t *__restrict__ pair_lv,
+    const int32_t *__restrict__ diag_pos, const double *__restrict__ coords, const T *__restrict__ coef,
+    const T *__restrict__ load, T *__restrict__ values, T *__restrict__ rhs, int32_t *__restrict__ status, int nblk,
+    int E, int mp, int me) {
     constexpr int K = 10;
     constexpr int VS = VertLds<3>::VS;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -738,8 +746,10 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     double *Lx =
         reinterpret_cast<double *>(smem + VertLds<3>::offset(BlockLds<T>::bytes(mp, me, 9 * kP2PhaseCols, 3, K)));
     __shared__ int sRp[kP2BlockCap + 1];  // row starts in the block's node-level entries
+    __shared__ int sVp[kP2BlockCap + 1];  // ... of the vertex-column entries only
+    __shared__ int sEp[kP2BlockCap + 1];  // ... of the edge-column entries only
     __shared__ int sIp[kP2BlockCap + 1];  // row starts in the block's pairs
-    __shared__ int sDp[3 * kP2BlockCap];  // diagonal positions of the block's DoF rows
+    __shared__ int sDp[kP2BlockCap];      // diagonal position of each row's first DoF row
     __shared__ uint8_t sA[kP2BlockCap];   // local node of every pair
 
     static_assert(kP2Threads == 3 * 64, "one wave per set of column nodes");
@@ -747,8 +757,10 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     const int blk = xcd_swizzle(blockIdx.x, nblk);
     const int4 dsc = ldg(reinterpret_cast<const int4 *>(blk_desc), 3u * blk);
     const int4 dsv = ldg(reinterpret_cast<const int4 *>(blk_desc), 3u * blk + 1u);
+    const int4 dsw = ldg(reinterpret_cast<const int4 *>(blk_desc), 3u * blk + 2u);
     const int r0 = dsc.x, r1 = dsc.y, q0 = dsc.z, q1 = dsc.w, rp0 = dsv.x, rp1 = dsv.y, w0 = dsv.z, w1 = dsv.w;
-    const int np = q1 - q0, nent = rp1 - rp0, nvb = w1 - w0;
+    const int vp0 = dsw.z, vp1 = dsw.w;
+    const int np = q1 - q0, nent = rp1 - rp0, nvb = w1 - w0, nvent = vp1 - vp0;
     const int nrows = r1 - r0;
     // the block's slots: K - 1 per pair (a diagonal block has none), from s0,
     // copied in 4-byte units of two from the even sb
@@ -774,13 +786,14 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     const int code = ldg(inc, (unsigned)(q0 + tp));
     const uint32_t lv = ldg(pair_lv, (unsigned)(q0 + tp));
     const int rp_reg = ldg(node_rp, (unsigned)(r0 + min(tid, nrows)));
+    const int vp_reg = ldg(node_vp, (unsigned)(r0 + min(tid, nrows)));
     const int ip_reg = ldg(inc_ptr, (unsigned)(r0 + min(tid, nrows)));
     const int sg_a = ldg(seg_ptr, (unsigned)(rp0 + min(tid, nent)));
     const int sg_b = ldg(seg_ptr, (unsigned)(rp0 + min(tid + kP2Threads, nent)));
     const uint32_t su_a = ldg(slot_u, (unsigned)min(tid, nsu - 1));
     const uint32_t su_b = ldg(slot_u, (unsigned)min(tid + kP2Threads, nsu - 1));
     const unsigned vid = (unsigned)ldg(blk_vert, (unsigned)(w0 + min(tid, nvb - 1)));
-    const int dp_reg = ldg(diag_pos, (unsigned)(3 * r0 + min(tid, 3 * nrows - 1)));
+    const int dp_reg = ldg(diag_pos, 3u * (unsigned)(r0 + min(tid, nrows - 1)));
     const int e = code / K, a = code - e * K;
     const T lam_t = ldg(coef, (unsigned)e), mu_t = ldg(coef, (unsigned)(E + e));
     // the body force of the pair's element (or, with no load, a valid dummy read)
@@ -801,10 +814,12 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     // writes the last element's value to the last element's place, the same
     // value its owner writes there.
     sRp[min(tid, nrows)] = rp_reg - rp0;
+    sVp[min(tid, nrows)] = vp_reg - vp0;
+    sEp[min(tid, nrows)] = (rp_reg - rp0) - (vp_reg - vp0);
     sIp[min(tid, nrows)] = ip_reg - q0;
     L.seg[min(tid, nent)] = sg_a - sb;
     L.seg[min(tid + kP2Threads, nent)] = sg_b - sb;
-    sDp[min(tid, 3 * nrows - 1)] = dp_reg;
+    sDp[min(tid, nrows - 1)] = dp_reg;
     reinterpret_cast<uint32_t *>(L.slot)[min(tid, nsu - 1)] = su_a;
     reinterpret_cast<uint32_t *>(L.slot)[min(tid + kP2Threads, nsu - 1)] = su_b;
 #pragma unroll
@@ -866,8 +881,8 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
         }
     }
     __syncthreads();
-    p2_reduce<T>(L, sRp, np, nent, false, values + 9 * (size_t)rp0);
-    p2_reduce_diagonal<T>(L, sIp, sA, sDp, nrows, np, false, values);
+    p2_reduce<T>(L, sRp, sVp, sVp, nvent, np, false, values + 9 * (size_t)rp0);
+    p2_reduce_diagonal<T>(L, sIp, sA, sDp, sRp, nrows, np, false, values);
     __syncthreads();  // the edge-column blocks reuse the LDS of the vertex-column ones
     if (own) {
         if (wave == 0) {
@@ -882,8 +897,8 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
         }
     }
     __syncthreads();
-    p2_reduce<T>(L, sRp, np, nent, true, values + 9 * (size_t)rp0);
-    p2_reduce_diagonal<T>(L, sIp, sA, sDp, nrows, np, true, values);
+    p2_reduce<T>(L, sRp, sVp, sEp, nent - nvent, np, true, values + 9 * (size_t)rp0);
+    p2_reduce_diagonal<T>(L, sIp, sA, sDp, sRp, nrows, np, true, values);
     if (rhs && load) {
         for (int u = threadIdx.x; u < 3 * nrows; u += kP2Threads) {
             const int r = u / 3, c = u - 3 * r;
@@ -965,13 +980,13 @@ hipError_t launch_assemble_p2(const tg_pattern &p, tg_dtype dtype, const double 
     if (dtype == TG_F64)
         hipLaunchKernelGGL(p2_elasticity_kernel<double>, dim3(nblk), dim3(kP2Threads),
                            VertLds<3>::offset(BlockLds<double>::bytes(mp, me, 9 * kP2PhaseCols, 3, 10)) + verts, s, d.blk_desc,
-                           d.inc_ptr, d.inc, d.node_rp, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, d.diag_pos, coords,
+                           d.inc_ptr, d.inc, d.node_rp, d.node_vp, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, d.diag_pos, coords,
                            (const double *)coef, (const double *)load, (double *)values, (double *)rhs, status, nblk,
                            E, mp, me);
     else
         hipLaunchKernelGGL(p2_elasticity_kernel<float>, dim3(nblk), dim3(kP2Threads),
                            VertLds<3>::offset(BlockLds<float>::bytes(mp, me, 9 * kP2PhaseCols, 3, 10)) + verts, s, d.blk_desc,
-                           d.inc_ptr, d.inc, d.node_rp, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, d.diag_pos, coords,
+                           d.inc_ptr, d.inc, d.node_rp, d.node_vp, d.seg_ptr, d.slot, d.blk_vert, d.pair_lv, d.diag_pos, coords,
                            (const float *)coef, (const float *)load, (float *)values, (float *)rhs, status, nblk, E,
                            mp, me);
     return hipGetLastError();

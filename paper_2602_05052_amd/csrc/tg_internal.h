@@ -44,14 +44,17 @@ struct HostPattern {
     std::vector<int32_t> elem_nodes;  // [E][k] global node ids
     std::vector<int32_t> node_rp;     // [n_nodes+1] node-level CSR rows
     std::vector<int32_t> node_ci;     // [nnz_nodes] node-level CSR columns (sorted)
+    // P2: node_vp[i] = vertex-node columns in rows 0 .. i-1 (a row's vertex-node
+    // columns come first: vertices are numbered before edges).  Empty for P1.
+    std::vector<int32_t> node_vp;     // [n_nodes+1]
     // S_vec routing: pairs (node i, element e, local node a) grouped by node,
     // ascending e inside a node.  pair code = e * k + a.
     std::vector<int32_t> inc_ptr;  // [n_nodes+1]
     std::vector<int32_t> inc;      // [n_pairs]
     // Row blocks for the fused kernels.
     std::vector<int32_t> blk_row;   // [n_blocks+1]
-    // [n_blocks][kBlkDesc]: r0, r1, q0, q1, v0, v1, w0, w1, s0, s1, 0, 0 (rows, pairs,
-    // node entries, vertices, routing slots)
+    // [n_blocks][kBlkDesc]: r0, r1, q0, q1, v0, v1, w0, w1, s0, s1, c0, c1 (rows, pairs,
+    // node entries, vertices, routing slots; P2: node_vp[r0], node_vp[r1], else 0)
     std::vector<int32_t> blk_desc;
     // The distinct vertices of each block's elements (ascending), and per pair
     // the block-local ids of its element's vertices, one byte each in local
@@ -156,11 +159,12 @@ struct DevicePattern {
     int32_t *inc_ptr = nullptr;   // [n_nodes+1]
     int32_t *inc = nullptr;       // [n_pairs]
     int32_t *blk_row = nullptr;   // [n_blocks+1]
-    int32_t *blk_desc = nullptr;  // [n_blocks][8]
+    int32_t *blk_desc = nullptr;  // [n_blocks][kBlkDesc]
     int32_t *blk_vert = nullptr;  // block vertex lists
     uint32_t *pair_lv = nullptr;  // [n_pairs] packed block-local vertex ids
     int32_t *node_rp = nullptr;   // [n_nodes+1]
     int32_t *node_ci = nullptr;   // [nnz_nodes]
+    int32_t *node_vp = nullptr;   // [n_nodes+1] (P2)
     int32_t *seg_ptr = nullptr;   // [nnz_nodes+1]
     uint16_t *slot = nullptr;     // [n_pairs*k]
     uint16_t *ent16 = nullptr;    // compact P1 routing (HostPattern::compact)

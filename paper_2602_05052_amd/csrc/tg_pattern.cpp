@@ -189,6 +189,18 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
         }
     }
 
+    // ---- P2: vertex-node columns per row, as a prefix (the Reduce handles a
+    // block's vertex-column and edge-column entries in separate passes)
+    hp.node_vp.clear();
+    if (p2) {
+        hp.node_vp.assign(N + 1, 0);
+        for (int64_t i = 0; i < N; ++i) {
+            int32_t c = 0;
+            for (int32_t z = hp.node_rp[i]; z < hp.node_rp[i + 1] && hp.node_ci[z] < hp.nv; ++z) ++c;
+            hp.node_vp[i + 1] = hp.node_vp[i] + c;
+        }
+    }
+
     // ---- row blocks: consecutive rows while the pairs fit the target (and, for
     // P1, the node-level entries fit one thread each); a single row may exceed
     // the target up to the capacity
@@ -299,6 +311,10 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
         dsc[5] = hp.node_rp[r1];
         dsc[8] = hp.seg_ptr[hp.node_rp[r0]];
         dsc[9] = hp.seg_ptr[hp.node_rp[r1]];
+        if (p2) {
+            dsc[10] = hp.node_vp[r0];
+            dsc[11] = hp.node_vp[r1];
+        }
         hp.max_block_pairs = std::max(hp.max_block_pairs, hp.inc_ptr[r1] - hp.inc_ptr[r0]);
         hp.max_block_entries = std::max(hp.max_block_entries, hp.node_rp[r1] - hp.node_rp[r0]);
         hp.max_block_rows = std::max(hp.max_block_rows, r1 - r0);
