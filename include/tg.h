@@ -167,7 +167,12 @@ tg_status tg_pattern_copy_element_nodes(const tg_pattern *p, int32_t *h_nodes);
  *       ascending element order; a slot is b * n + (pair - f), where f is the
  *       first pair and n the number of pairs of the entry's row block: local
  *       entry (a, b) of the pair's element.  For ncomp = 3 each slot is a 3x3
- *       block.  The diagonal entry (i, i) has an empty segment: its value
+ *       block, and b is the column node in the pair's frame: the element's
+ *       vertices reordered as the pair's node's vertex (or its edge's two
+ *       vertices, in local order), then the other vertices in local order, with
+ *       frame nodes 0..3 these vertices and 4..9 the edges (0,1), (0,2), (0,3),
+ *       (1,2), (1,3), (2,3) between them (the pair's node is frame node 0 or 4).
+ *       The diagonal entry (i, i) has an empty segment: its value
  *       (P2: 3x3 block) is the sum of K_e[a][a] over the pairs (i, e, a) of
  *       node i, in their S_vec (ascending element) order.  n_slot (tg_pattern_info) is
  *       h_seg_ptr[Z] rounded up to a multiple of 4; the tail is unused.
@@ -192,7 +197,8 @@ tg_status tg_pattern_copy_compact_routing(const tg_pattern *p, int32_t *compact,
  * h_blk_vert[h_blk_vptr[b] .. h_blk_vptr[b+1]) (ascending, at most 256) into
  * LDS once; pair t (in S_vec order) finds the vertices of its element at the
  * block-local positions (h_pair_lv[t] >> 8a) & 255, a = 0..dim (for P2 the
- * element's 4 vertex nodes).  *n_vert receives the length of h_blk_vert (call
+ * element's 4 vertex nodes in the pair's frame, see tg_pattern_copy_routing).
+ * *n_vert receives the length of h_blk_vert (call
  * with NULL arrays first).  Any array may be NULL; h_blk_vptr [B+1],
  * h_pair_lv [P].
  */

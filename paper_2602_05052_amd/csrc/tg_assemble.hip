@@ -537,117 +537,131 @@ void p1_assemble_kernel(
 
 // ---------------------------------------------------------------- P2 elasticity
 
-// Lanes per P2 pair: 5 lanes with two of the 10 column nodes each (every lane
-// repeats the pair's geometry, so fewer lanes with balanced work beat 8 or 10).
-// Vertices (i, j) of P2 local node n (vertices 0..3, then edges (0,1),(0,2),(0,3),
-// (1,2),(1,3),(2,3)); a vertex node has i = j = n.
-__device__ __forceinline__ void p2_node(int n, int &i, int &j) {
-    const bool vtx = n < 4;
-    i = vtx ? n : (n < 7 ? 0 : (n < 9 ? 1 : 2));
-    j = vtx ? n : (n == 4 ? 1 : (n == 5 || n == 7) ? 2 : 3);
+// The 3x3 block of Hooke's law (Sec. B.1.1), lam D + mu (D^T + tr(D) I), for a
+// rank-one D = u w^T, given L = lam u and M = mu u: L w^T + w M^T + (M . w) I.
+template <typename T>
+__device__ __forceinline__ void hooke_rank1(const T (&L)[3], const T (&M)[3], const T (&w)[3], T *o) {
+    const T tr = M[0] * w[0] + M[1] * w[1] + M[2] * w[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) o[c * 3 + cc] = L[c] * w[cc] + w[c] * M[cc] + (c == cc ? tr : (T)0);
 }
 
-// grad(phi_n) at the 4 Keast points: vertex p: (4 lambda_p - 1) grad(lambda_p);
-// edge (i,j): 4 (lambda_j grad(lambda_i) + lambda_i grad(lambda_j)), with
-// lambda_p = hi at point p and lo elsewhere.  g: the pair's grad(lambda_p), [4][3].
+// The same for D = u p^T + v q^T, given L = lam u, M = mu u, Lv = lam v, Mv = mu v.
 template <typename T>
-__device__ __forceinline__ void p2_node_grads(int n, const T (&g)[4][3], T (&out)[4][3]) {
-    using R = Deg2Rule<3>;
-    int i, j;
-    p2_node(n, i, j);
-    const bool vtx = n < 4;
-    // rows i and j of g, selected without a run-time index into the register array
-    T gi[3] = {}, gj[3] = {};
+__device__ __forceinline__ void hooke_rank2(const T (&L)[3], const T (&M)[3], const T (&p)[3], const T (&Lv)[3],
+                                            const T (&Mv)[3], const T (&q)[3], T *o) {
+    const T tr = M[0] * p[0] + M[1] * p[1] + M[2] * p[2] + Mv[0] * q[0] + Mv[1] * q[1] + Mv[2] * q[2];
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+            o[c * 3 + cc] = L[c] * p[cc] + Lv[c] * q[cc] + p[c] * M[cc] + q[c] * Mv[cc] + (c == cc ? tr : (T)0);
+}
+
+// The element row of one P2 pair, in the pair's frame: the routing and the
+// staged vertex ids order the element's vertices so that the pair's node is
+// vertex 0 (a vertex node) or edge (0, 1) (an edge node), the column nodes
+// numbered in the same frame (vertices 0..3, then edges (0,1),(0,2),(0,3),
+// (1,2),(1,3),(2,3)).  With V the element volume, g_v = grad(lambda_v) and the
+// exact integrals int lambda_p = V/4, int lambda_p lambda_q = V (1 + [p = q])/20
+// of the quadratic basis (vertex: lambda (2 lambda - 1); edge (i, j):
+// 4 lambda_i lambda_j), D = int grad(phi_a) grad(phi_b)^T is
+//   vertex node:  D = V g_0 w^T,  w = 3/5 g_0 (b = 0), -1/5 g_b (b = 1..3),
+//                 3/5 g_j - 1/5 g_0 (edge (0, j)), -1/5 (g_i + g_j) (edge (i, j), 0 < i);
+//   edge node:    vertex b: D = w g_b^T,  w = V (3/5 g_1 - 1/5 g_0) (b = 0),
+//                 V (3/5 g_0 - 1/5 g_1) (b = 1), -V/5 (g_0 + g_1) (b = 2, 3);
+//                 edge (k, l): D = 4/5 V (g_1 p^T + g_0 q^T) with
+//                 p = (1 + [k = 0]) g_l + (1 + [l = 0]) g_k, q = (1 + [k = 1]) g_l + (1 + [l = 1]) g_k,
+// then Hooke's law.  (The same integrals as the degree-2 rule of the
+// quadrature, which is exact for them.)
+template <typename T>
+struct P2Pair {
+    T g[4][3];  // grad(lambda_v) in the frame
+    // vertex node: L0 = lam V g_0, M0 = mu V g_0 (L1, M1 unused);
+    // edge node: L0, L1, M0, M1 = 4/5 V (lam g_0, lam g_1, mu g_0, mu g_1)
+    T L0[3], L1[3], M0[3], M1[3];
+
+    __device__ __forceinline__ void init(bool edge, T V, T lam, T mu) {
+        const T s = edge ? (T)0.8 * V : V, ls = lam * s, ms = mu * s;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            gi[c] = (p == i) ? g[p][c] : gi[c];
-            gj[c] = (p == j) ? g[p][c] : gj[c];
+            L0[c] = ls * g[0][c];
+            M0[c] = ms * g[0][c];
+            L1[c] = ls * g[1][c];
+            M1[c] = ms * g[1][c];
         }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const T li = (i == q) ? (T)R::hi : (T)R::lo;  // lambda_i at the point
-        const T lj = (j == q) ? (T)R::hi : (T)R::lo;
-        const T ci = vtx ? (T)4 * li - (T)1 : (T)4 * lj;  // coefficient of grad(lambda_i)
-        const T cj = vtx ? (T)0 : (T)4 * li;              // coefficient of grad(lambda_j)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) out[q][c] = ci * gi[c] + cj * gj[c];
     }
-}
 
-// The 3x3 blocks (a, b) of one pair's element row, Hooke's law (Sec. B.1.1):
-//   block[c][c'] = lam D[c][c'] + mu (D[c'][c] + delta_cc' tr D),
-//   D = sum_q w_q |det J| grad(phi_a)(x_q) grad(phi_b)(x_q)^T  (Keast 4-point rule).
-// grad(phi_b) is written through the barycentric gradients g_v: vertex b:
-// (4 lambda_b - 1) g_b; edge (i, j): 4 lambda_j g_i + 4 lambda_i g_j.  With
-// ga_q = w_q |det J| grad(phi_a)(x_q) and lambda_v(x_q) = lo + (hi - lo) [q == v],
-// sum_q lambda_v(x_q) ga_q = lo S + (hi - lo) ga_v with S = sum_q ga_q, so
-//   vertex b:   D = ((4 lo - 1) S + 4 (hi - lo) ga_b) g_b^T
-//   edge (i,j): D = (4 lo S + 4 (hi - lo) ga_j) g_i^T + (4 lo S + 4 (hi - lo) ga_i) g_j^T
-// (the same sums as sum_q ga_q gb_q^T, grouped by barycentric gradient).
-template <typename T>
-struct P2Row {
-    T g[4][3];        // grad(lambda_v), v = 0..3
-    T lam, mu;        // Lame coefficients of the element
-    T P[4][3];        // 4 (hi - lo) ga_v
-    T S0[3], S1[3];   // 4 lo S and (4 lo - 1) S
-
-    __device__ __forceinline__ void init(int a, T w) {
-        using R = Deg2Rule<3>;
-        T ga[4][3];
-        p2_node_grads<T>(a, g, ga);
-        T S[3];
+    // block (a, B) of a vertex node, written to o[0 .. 9) (row-major 3x3)
+    template <int B>
+    __device__ __forceinline__ void vertex_block(T *o) const {
+        T w[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            S[c] = (T)0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                ga[q][c] = w * ga[q][c];
-                S[c] += ga[q][c];
+            if constexpr (B == 0) {
+                w[c] = (T)0.6 * g[0][c];
+            } else if constexpr (B < 4) {
+                w[c] = (T)-0.2 * g[B][c];
+            } else if constexpr (B < 7) {
+                w[c] = (T)0.6 * g[B - 3][c] - (T)0.2 * g[0][c];
+            } else {
+                constexpr int i = B < 9 ? 1 : 2, j = B == 7 ? 2 : 3;
+                w[c] = (T)-0.2 * (g[i][c] + g[j][c]);
             }
         }
-        const T k4 = (T)(4.0 * (R::hi - R::lo)), l4 = (T)(4.0 * R::lo), l41 = (T)(4.0 * R::lo - 1.0);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) P[q][c] = k4 * ga[q][c];
-            S0[c] = l4 * S[c];
-            S1[c] = l41 * S[c];
-        }
+        hooke_rank1<T>(L0, M0, w, o);
     }
 
-    // Writes block (a, B) to o[0 .. 9) (row-major 3x3).
+    // block (a, B) of an edge node
     template <int B>
-    __device__ __forceinline__ void block(T *o) const {
-        T D[3][3];
-        if constexpr (B < 4) {
-            T h[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) h[c] = S1[c] + P[B][c];
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int cc = 0; cc < 3; ++cc) D[c][cc] = h[c] * g[B][cc];
-        } else {
-            constexpr int i = B < 7 ? 0 : (B < 9 ? 1 : 2);
-            constexpr int j = B == 4 ? 1 : ((B == 5 || B == 7) ? 2 : 3);
-            T hi[3], hj[3];
+    __device__ __forceinline__ void edge_block(T *o) const {
+        if constexpr (B < 4) {  // lam w and mu w from the stored 4/5 V lam g_0, ...
+            T Lw[3], Mw[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                hi[c] = S0[c] + P[j][c];
-                hj[c] = S0[c] + P[i][c];
+                if constexpr (B == 0) {
+                    Lw[c] = (T)0.75 * L1[c] - (T)0.25 * L0[c];
+                    Mw[c] = (T)0.75 * M1[c] - (T)0.25 * M0[c];
+                } else if constexpr (B == 1) {
+                    Lw[c] = (T)0.75 * L0[c] - (T)0.25 * L1[c];
+                    Mw[c] = (T)0.75 * M0[c] - (T)0.25 * M1[c];
+                } else {
+                    Lw[c] = (T)-0.25 * (L0[c] + L1[c]);
+                    Mw[c] = (T)-0.25 * (M0[c] + M1[c]);
+                }
             }
+            hooke_rank1<T>(Lw, Mw, g[B], o);
+        } else if constexpr (B == 9) {  // edge (2, 3): p = q = g_2 + g_3
+            T p[3], Ls[3], Ms[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
+            for (int c = 0; c < 3; ++c) {
+                p[c] = g[2][c] + g[3][c];
+                Ls[c] = L0[c] + L1[c];
+                Ms[c] = M0[c] + M1[c];
+            }
+            hooke_rank1<T>(Ls, Ms, p, o);
+        } else {
+            constexpr int k = B < 7 ? 0 : 1, l = B == 4 ? 1 : ((B == 5 || B == 7) ? 2 : 3);
+            constexpr T pk = (T)(1 + (l == 0)), pl = (T)(1 + (k == 0));  // p = pl g_l + pk g_k
+            constexpr T qk = (T)(1 + (l == 1)), ql = (T)(1 + (k == 1));  // q = ql g_l + qk g_k
+            T p[3], q[3];
 #pragma unroll
-                for (int cc = 0; cc < 3; ++cc) D[c][cc] = hi[c] * g[i][cc] + hj[c] * g[j][cc];
+            for (int c = 0; c < 3; ++c) {
+                p[c] = pl * g[l][c] + pk * g[k][c];
+                q[c] = ql * g[l][c] + qk * g[k][c];
+            }
+            hooke_rank2<T>(L1, M1, p, L0, M0, q, o);
         }
-        const T tr = D[0][0] + D[1][1] + D[2][2];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int cc = 0; cc < 3; ++cc) o[c * 3 + cc] = lam * D[c][cc] + mu * (D[cc][c] + (c == cc ? tr : (T)0));
+    }
+
+    template <int B>
+    __device__ __forceinline__ void block(bool edge, T *o) const {
+        if (edge)
+            edge_block<B>(o);
+        else
+            vertex_block<B>(o);
     }
 };
 
@@ -711,21 +725,21 @@ __device__ __forceinline__ void p2_reduce(const BlockLds<T> &L, const int *sRp, 
 // Diagonal blocks of the rows whose node is in this phase's class (vertex or
 // edge node: the class of its local index in every element): component z of
 // row r is the sum, over the row's pairs t in S_vec (ascending element) order,
-// of component z of the pair's block (a_t, a_t); nine lanes per row.  The
-// routing lists no slots for these entries.  Written at the scalar CSR
+// of component z of the pair's block (a_t, a_t) (column 0 or 4 of the pair's
+// frame: the first block of the phase); nine lanes per row.  The routing
+// lists no slots for these entries.  Written at the scalar CSR
 // positions diag_pos[3 i] + c (3 m) + c' (m: node entries of the row; sDp[r]
 // = diag_pos[3 i] for the block's row r of node i).
 template <typename T>
 __device__ __forceinline__ void p2_reduce_diagonal(const BlockLds<T> &L, const int *sIp, const uint8_t *sA,
-                                                   const int *sDp, const int *sRp, int nrows, int np, bool edge,
+                                                   const int *sDp, const int *sRp, int nrows, bool edge,
                                                    T *__restrict__ values) {
-    const int cs = np * 9, b0 = edge ? 4 : 0;
     for (int u = threadIdx.x; u < 9 * nrows; u += kP2Threads) {
         const int r = u / 9, z = u - 9 * r;
         const int t0 = sIp[r], t1 = sIp[r + 1];
         if (t0 == t1 || ((int)sA[t0] >= 4) != edge) continue;
         T acc = 0;
-        for (int t = t0; t < t1; ++t) acc += L.K[((int)sA[t] - b0) * cs + t * 9 + z];
+        for (int t = t0; t < t1; ++t) acc += L.K[t * 9 + z];
         const int c = z / 3;
         values[sDp[r] + c * 3 * (sRp[r + 1] - sRp[r]) + (z - 3 * c)] = acc;
     }
@@ -839,37 +853,36 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     // and written before the edge-column blocks take their place in LDS (LDS
     // for 6 blocks per pair instead of 10: more resident blocks per CU).
     // One lane per pair; in each phase wave w forms a fixed set of column nodes
-    // (compile-time constants), and each wave forms the pair's geometry once,
-    // kept in registers for both phases.
+    // of the pair's frame (compile-time constants), and each wave forms the
+    // pair's geometry once, kept in registers for both phases.
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const bool own = lane < np;
     const int cs = np * 9;  // LDS stride between column nodes
     T *dst = L.K + lane * 9;
-    P2Row<T> pr;
+    const bool edge_node = a >= 4;  // the pair's node: an edge node (frame edge (0, 1)) or a vertex node
+    P2Pair<T> pr;
     if (own) {
         double x[4][3], Gd[4][3];
-        lds_vertices<3>(Lx, lv, x);
+        lds_vertices<3>(Lx, lv, x);  // the element's vertices in the pair's frame
         const double det = p1_gradients<3>(x, Gd);
         const double adet = fabs(det);
 #pragma unroll
         for (int p = 0; p < 4; ++p)
 #pragma unroll
             for (int c = 0; c < 3; ++c) pr.g[p][c] = (T)Gd[p][c];
-        pr.lam = lam_t;
-        pr.mu = mu_t;
-        pr.init(a, (T)(adet * Deg2Rule<3>::w));
+        pr.init(edge_node, (T)(adet * (1.0 / 6.0)), lam_t, mu_t);
         if (wave == 0) {
             sA[lane] = (uint8_t)a;
-            pr.template block<0>(dst);
-            pr.template block<1>(dst + cs);
+            pr.template block<0>(edge_node, dst);
+            pr.template block<1>(edge_node, dst + cs);
         } else if (wave == 1) {
-            pr.template block<2>(dst + 2 * cs);
-            pr.template block<3>(dst + 3 * cs);
+            pr.template block<2>(edge_node, dst + 2 * cs);
+            pr.template block<3>(edge_node, dst + 3 * cs);
         } else {  // the local load and the checks
             const double lam_d = (double)lam_t, mu_d = (double)mu_t;
             bool bad = numerically_singular<3>(x, det) || !finite(lam_d) || !finite(mu_d);
             if (load) {
-                const double ia = adet * p2_ref_integral(a);
+                const double ia = adet * (edge_node ? p2_ref_integral(4) : p2_ref_integral(0));
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const double bc = (double)bf[c];
@@ -882,23 +895,23 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     }
     __syncthreads();
     p2_reduce<T>(L, sRp, sVp, sVp, nvent, np, false, values + 9 * (size_t)rp0);
-    p2_reduce_diagonal<T>(L, sIp, sA, sDp, sRp, nrows, np, false, values);
+    p2_reduce_diagonal<T>(L, sIp, sA, sDp, sRp, nrows, false, values);
     __syncthreads();  // the edge-column blocks reuse the LDS of the vertex-column ones
     if (own) {
         if (wave == 0) {
-            pr.template block<4>(dst);
-            pr.template block<5>(dst + cs);
+            pr.template block<4>(edge_node, dst);
+            pr.template block<5>(edge_node, dst + cs);
         } else if (wave == 1) {
-            pr.template block<6>(dst + 2 * cs);
-            pr.template block<7>(dst + 3 * cs);
+            pr.template block<6>(edge_node, dst + 2 * cs);
+            pr.template block<7>(edge_node, dst + 3 * cs);
         } else {
-            pr.template block<8>(dst + 4 * cs);
-            pr.template block<9>(dst + 5 * cs);
+            pr.template block<8>(edge_node, dst + 4 * cs);
+            pr.template block<9>(edge_node, dst + 5 * cs);
         }
     }
     __syncthreads();
     p2_reduce<T>(L, sRp, sVp, sEp, nent - nvent, np, true, values + 9 * (size_t)rp0);
-    p2_reduce_diagonal<T>(L, sIp, sA, sDp, sRp, nrows, np, true, values);
+    p2_reduce_diagonal<T>(L, sIp, sA, sDp, sRp, nrows, true, values);
     if (rhs && load) {
         for (int u = threadIdx.x; u < 3 * nrows; u += kP2Threads) {
             const int r = u / 3, c = u - 3 * r;

@@ -58,11 +58,13 @@ struct HostPattern {
     std::vector<int32_t> blk_desc;
     // The distinct vertices of each block's elements (ascending), and per pair
     // the block-local ids of its element's vertices, one byte each in local
-    // vertex order (the Map reads coordinates from a per-block LDS copy).
+    // vertex order (P2: in the pair's frame) (the Map reads coordinates from a
+    // per-block LDS copy).
     std::vector<int32_t> blk_vert;  // [sum of block vertex counts]
     std::vector<uint32_t> pair_lv;  // [n_pairs]
     // S_mat routing: node-level entry p sums slots slot[seg_ptr[p] .. seg_ptr[p+1]),
-    // ascending element order; slot = b * (pairs of the block) + (pair - first pair of the block).
+    // ascending element order; slot = b * (pairs of the block) + (pair - first pair of the block),
+    // b the column's local node (P2: in the pair's frame, tg_pattern.cpp p2_frame_order).
     // Diagonal entries have empty segments (the kernels sum them from the row's pairs).
     // P1: the diagonal entry of a row has an empty segment; its value is the sum over
     // the row's pairs (S_vec order) of the element's diagonal entry K_e[a][a].

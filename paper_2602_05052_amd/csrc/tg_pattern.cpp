@@ -27,6 +27,52 @@ namespace {
 
 constexpr int kP2Edge[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
 
+// The local frame of a P2 pair (node i, element e, local node a): the element's
+// vertices reordered so that i is vertex 0 (a vertex node) or edge (0, 1) (an
+// edge node): its vertex, or its edge's two vertices in local order, then the
+// element's other vertices in local order.  ord[k] = local vertex at frame
+// position k.
+void p2_frame_order(int a, int ord[4]) {
+    bool used[4] = {false, false, false, false};
+    int n = 0;
+    auto put = [&](int v) {
+        ord[n++] = v;
+        used[v] = true;
+    };
+    if (a < 4) {
+        put(a);
+    } else {
+        put(kP2Edge[a - 4][0]);
+        put(kP2Edge[a - 4][1]);
+    }
+    for (int v = 0; v < 4; ++v)
+        if (!used[v]) put(v);
+}
+
+// frame[a][b]: index in the frame of pair node a of the element's local node b
+// (vertices 0..3, then edges (0,1),(0,2),(0,3),(1,2),(1,3),(2,3) of the frame).
+struct P2FrameTable {
+    uint8_t frame[10][10];
+    P2FrameTable() {
+        for (int a = 0; a < 10; ++a) {
+            int ord[4], pos[4];
+            p2_frame_order(a, ord);
+            for (int k = 0; k < 4; ++k) pos[ord[k]] = k;
+            for (int b = 0; b < 10; ++b) {
+                if (b < 4) {
+                    frame[a][b] = (uint8_t)pos[b];
+                    continue;
+                }
+                int p = pos[kP2Edge[b - 4][0]], q = pos[kP2Edge[b - 4][1]];
+                if (p > q) std::swap(p, q);
+                for (int m = 0; m < 6; ++m)
+                    if (kP2Edge[m][0] == p && kP2Edge[m][1] == q) frame[a][b] = (uint8_t)(4 + m);
+            }
+        }
+    }
+};
+const P2FrameTable kP2Frame;
+
 struct FaceKey {
     int32_t v[3];
     bool operator<(const FaceKey &o) const {
@@ -287,9 +333,11 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
         for (int32_t c = 0; c < m; ++c) hp.seg_ptr.push_back((int32_t)(slot_fill + cnt[c]));
         for (int32_t t = hp.inc_ptr[i]; t < hp.inc_ptr[i + 1]; ++t) {
             const int64_t e = hp.inc[t] / k;
+            const int a = hp.inc[t] % k;
             for (int b = 0; b < k; ++b) {
                 const int c = pos[hp.elem_nodes[e * k + b]];
-                if (c != diag) hp.slot[slot_fill + cnt[c]++] = (uint16_t)(b * blk_pairs + (t - blk_first_pair));
+                const int bf = p2 ? kP2Frame.frame[a][b] : b;  // P2: the column in the pair's frame
+                if (c != diag) hp.slot[slot_fill + cnt[c]++] = (uint16_t)(bf * blk_pairs + (t - blk_first_pair));
             }
         }
         slot_fill += cnt[m];
@@ -379,8 +427,10 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
             hp.max_block_verts = std::max(hp.max_block_verts, (int32_t)verts.size());
             for (int32_t t = q0; t < q1; ++t) {
                 const int64_t e = hp.inc[t] / k;
+                int ord[4] = {0, 1, 2, 3};  // P1: local order; P2: the pair's frame
+                if (p2) p2_frame_order(hp.inc[t] % k, ord);
                 uint32_t w = 0;
-                for (int a = 0; a < kv; ++a) w |= (uint32_t)local[hp.elem_nodes[e * k + a]] << (8 * a);
+                for (int a = 0; a < kv; ++a) w |= (uint32_t)local[hp.elem_nodes[e * k + ord[a]]] << (8 * a);
                 hp.pair_lv[t] = w;
             }
             for (int32_t v : verts) local[v] = -1;

@@ -150,6 +150,33 @@ def tg_block_cap(order):
     return 512 if order == 1 else 64
 
 
+P2_EDGES = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+
+
+def _p2_frame(a):
+    """The P2 kernel's frame of a pair whose node is local node a: the element's vertices ordered as a's
+    vertex (or a's edge's two vertices), then the other vertices in local order; returns, for frame nodes
+    0..9 (vertices, then the edges of P2_EDGES between frame vertices), the element's local node."""
+    order = [a] if a < 4 else list(P2_EDGES[a - 4])
+    order += [v for v in range(4) if v not in order]
+    edges = [4 + P2_EDGES.index(tuple(sorted((order[i], order[j])))) for i, j in P2_EDGES]
+    return np.array(order + edges)
+
+
+P2_FRAME = np.stack([_p2_frame(a) for a in range(10)])
+
+
+def test_p2_frame_rule():
+    """Each frame is a permutation of the 10 local nodes that keeps vertex and edge nodes apart and puts
+    the pair's own node first (vertex 0, or edge (0, 1) = frame node 4)."""
+    for a in range(10):
+        f = P2_FRAME[a]
+        assert sorted(f) == list(range(10)) and np.all(f[:4] < 4)
+        assert f[0 if a < 4 else 4] == a
+    assert list(P2_FRAME[2]) == [2, 0, 1, 3, 5, 7, 9, 4, 6, 8]  # vertex 2: order (2, 0, 1, 3)
+    assert list(P2_FRAME[8]) == [1, 3, 0, 2, 8, 4, 7, 6, 9, 5]  # edge (1, 3): order (1, 3, 0, 2)
+
+
 def test_p2_pattern_routing_equals_oracle():
     d = meshgen.elasticity_inputs(2, seed=2)
     pat = tg.Pattern(d["conn"], len(d["coords"]), order=2, ncomp=3, host_only=True)
@@ -166,9 +193,10 @@ def test_p2_pattern_routing_equals_oracle():
     for e, g in enumerate(d["conn"]):
         Ke, Fe = oracle.p2_elasticity_element(d["coords"][g], d["lam"][e], d["mu"][e], d["b"][e])
         Kl[e], Fl[e] = Ke.reshape(10, 3, 10, 3), Fe.reshape(10, 3)
-    pair, b = _pair_of_slot(r, k)
+    pair, bf = _pair_of_slot(r, k)
     code = r["inc"][pair]
     e, a = code // k, code % k
+    b = P2_FRAME[a, bf]  # slots name the column in the pair's frame
     # diagonal entries carry no slots: each sums its row's pairs' blocks (a, a) in S_vec order
     node_rp = r["node_rp"]
     node_of_entry = np.repeat(np.arange(pat.n_nodes), np.diff(node_rp))
@@ -304,7 +332,7 @@ def test_block_vertex_staging_in_bounds(dim, n, shuffle):
 
 @pytest.mark.parametrize("n", [1, 3])
 def test_block_vertex_staging_p2(n):
-    """P2 blocks stage the 4 vertex nodes of their elements the same way."""
+    """P2 blocks stage the 4 vertex nodes of their elements the same way, each pair's in its frame."""
     d = meshgen.elasticity_inputs(n, seed=0)
     pat = tg.Pattern(d["conn"], len(d["coords"]), dim=3, order=2, ncomp=3, host_only=True)
     vptr, vert, lv = pat.block_vertices()
@@ -312,12 +340,12 @@ def test_block_vertex_staging_p2(n):
     nodes = pat.element_nodes()
     assert np.diff(vptr).max() <= 256 and np.all(np.diff(vptr) >= 1)
     pair_block = np.repeat(np.arange(pat.n_blocks), np.diff(r["inc_ptr"][r["blk_row"]]))
-    e = r["inc"] // 10
-    for a in range(4):
-        loc = (lv >> (8 * a)) & 255
+    e, a = r["inc"] // 10, r["inc"] % 10
+    np.testing.assert_array_equal(nodes[:, :4], d["conn"])
+    for kf in range(4):  # frame vertex kf of each pair
+        loc = (lv >> (8 * kf)) & 255
         assert np.all(loc < np.diff(vptr)[pair_block])
-        np.testing.assert_array_equal(vert[vptr[pair_block] + loc], nodes[e, a])
-        np.testing.assert_array_equal(nodes[e, a], d["conn"][e, a])
+        np.testing.assert_array_equal(vert[vptr[pair_block] + loc], nodes[e, P2_FRAME[a, kf]])
 
 
 def test_p1_wide_routing_for_a_high_valence_node():
