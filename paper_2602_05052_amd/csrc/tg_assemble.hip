@@ -303,6 +303,7 @@ struct P1Lds {
 constexpr int kP1DescAhead = 256;
 constexpr int kP2DescAhead = 128;  // about one round of P2 workgroups on an XCD
 constexpr int kP2PhaseCols = 6;     // column nodes of a P2 pair held in LDS at once (the edges)
+constexpr int kP2ClsLen = (kP2BlockCap + 1 + 3) & ~3;  // class prefixes of a P2 block, padded to int4s
 
 // Minimum waves per SIMD the register allocation must allow: 8 for the
 // single-set Laplace kernels (they fit in 64 VGPRs without spilling), 7 for the
@@ -694,13 +695,21 @@ __device__ __forceinline__ double p2_ref_integral(int n) {
 // = b np + pair.  Entry pe of row r, column position jpos, lands at 9 sRp[r]
 // + c (3 m) + 3 jpos + cc of the block's value range (the 3 DoF rows of a
 // node share its columns).  Diagonal entries (empty segments) are skipped.
+// cls holds kP2ClsLen values, INT_MAX past the block's last row, so the row
+// is found four prefix values (one 16-byte LDS read) at a time; slots are
+// taken two at a time (their indices, then their blocks, in one LDS round
+// trip each), the sum still in slot order.
 template <typename T>
 __device__ __forceinline__ void p2_reduce(const BlockLds<T> &L, const int *sRp, const int *sVp, const int *cls,
                                           int ncls, int np, bool edge, T *__restrict__ out) {
     const int first = edge ? 4 * np : 0;
     for (int t = threadIdx.x; t < ncls; t += kP2Threads) {
-        int r = 0;
-        while (cls[r + 1] <= t) ++r;
+        int j = 0, cnt;
+        do {  // rows r with cls[r] <= t (cls[0] = 0, non-decreasing): r = their count - 1
+            const int4 c = reinterpret_cast<const int4 *>(cls)[j++];
+            cnt = (c.x <= t) + (c.y <= t) + (c.z <= t) + (c.w <= t);
+        } while (cnt == 4);
+        const int r = 4 * (j - 1) + cnt - 1;
         const int m = sRp[r + 1] - sRp[r];
         const int jpos = (edge ? sVp[r + 1] - sVp[r] : 0) + (t - cls[r]);
         const int pe = sRp[r] + jpos;
@@ -709,10 +718,23 @@ __device__ __forceinline__ void p2_reduce(const BlockLds<T> &L, const int *sRp, 
         T acc[9];
 #pragma unroll
         for (int z = 0; z < 9; ++z) acc[z] = 0;
-        for (int u = u0; u < u1; ++u) {
-            const T *src = L.K + ((int)L.slot[u] - first) * 9;
+        int u = u0;
+        for (; u + 2 <= u1; u += 2) {  // two slots per round trip of slot reads, then of block reads
+            const T *s0 = L.K + ((int)L.slot[u] - first) * 9;
+            const T *s1 = L.K + ((int)L.slot[u + 1] - first) * 9;
+            T b0[9], b1[9];
 #pragma unroll
-            for (int z = 0; z < 9; ++z) acc[z] += src[z];
+            for (int z = 0; z < 9; ++z) {
+                b0[z] = s0[z];
+                b1[z] = s1[z];
+            }
+#pragma unroll
+            for (int z = 0; z < 9; ++z) acc[z] = (acc[z] + b0[z]) + b1[z];
+        }
+        if (u < u1) {
+            const T *s0 = L.K + ((int)L.slot[u] - first) * 9;
+#pragma unroll
+            for (int z = 0; z < 9; ++z) acc[z] += s0[z];
         }
         T *o = out + 9 * sRp[r] + 3 * jpos;
 #pragma unroll
@@ -720,6 +742,22 @@ __device__ __forceinline__ void p2_reduce(const BlockLds<T> &L, const int *sRp, 
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) o[c * 3 * m + cc] = acc[c * 3 + cc];
     }
+}
+
+// v[s t] summed left to right over t0 <= t < t1, four LDS reads per round trip.
+template <typename T>
+__device__ __forceinline__ T seq_sum(const T *v, int s, int t0, int t1) {
+    T acc = 0;
+    int t = t0;
+    for (; t + 4 <= t1; t += 4) {
+        const T a0 = v[s * t], a1 = v[s * (t + 1)], a2 = v[s * (t + 2)], a3 = v[s * (t + 3)];
+        acc += a0;
+        acc += a1;
+        acc += a2;
+        acc += a3;
+    }
+    for (; t < t1; ++t) acc += v[s * t];
+    return acc;
 }
 
 // Diagonal blocks of the rows whose node is in this phase's class (vertex or
@@ -738,8 +776,7 @@ __device__ __forceinline__ void p2_reduce_diagonal(const BlockLds<T> &L, const i
         const int r = u / 9, z = u - 9 * r;
         const int t0 = sIp[r], t1 = sIp[r + 1];
         if (t0 == t1 || ((int)sA[t0] >= 4) != edge) continue;
-        T acc = 0;
-        for (int t = t0; t < t1; ++t) acc += L.K[t * 9 + z];
+        const T acc = seq_sum<T>(L.K + z, 9, t0, t1);
         const int c = z / 3;
         values[sDp[r] + c * 3 * (sRp[r + 1] - sRp[r]) + (z - 3 * c)] = acc;
     }
@@ -760,8 +797,8 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     double *Lx =
         reinterpret_cast<double *>(smem + VertLds<3>::offset(BlockLds<T>::bytes(mp, me, 9 * kP2PhaseCols, 3, K)));
     __shared__ int sRp[kP2BlockCap + 1];  // row starts in the block's node-level entries
-    __shared__ int sVp[kP2BlockCap + 1];  // ... of the vertex-column entries only
-    __shared__ int sEp[kP2BlockCap + 1];  // ... of the edge-column entries only
+    __shared__ __align__(16) int sVp[kP2ClsLen];  // ... of the vertex-column entries only (then INT_MAX)
+    __shared__ __align__(16) int sEp[kP2ClsLen];  // ... of the edge-column entries only (then INT_MAX)
     __shared__ int sIp[kP2BlockCap + 1];  // row starts in the block's pairs
     __shared__ int sDp[kP2BlockCap];      // diagonal position of each row's first DoF row
     __shared__ uint8_t sA[kP2BlockCap];   // local node of every pair
@@ -828,8 +865,10 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     // writes the last element's value to the last element's place, the same
     // value its owner writes there.
     sRp[min(tid, nrows)] = rp_reg - rp0;
-    sVp[min(tid, nrows)] = vp_reg - vp0;
-    sEp[min(tid, nrows)] = (rp_reg - rp0) - (vp_reg - vp0);
+    if (tid < kP2ClsLen) {
+        sVp[tid] = tid <= nrows ? vp_reg - vp0 : INT_MAX;
+        sEp[tid] = tid <= nrows ? (rp_reg - rp0) - (vp_reg - vp0) : INT_MAX;
+    }
     sIp[min(tid, nrows)] = ip_reg - q0;
     L.seg[min(tid, nent)] = sg_a - sb;
     L.seg[min(tid + kP2Threads, nent)] = sg_b - sb;
@@ -915,9 +954,7 @@ __global__ __launch_bounds__(kP2Threads) void p2_elasticity_kernel(
     if (rhs && load) {
         for (int u = threadIdx.x; u < 3 * nrows; u += kP2Threads) {
             const int r = u / 3, c = u - 3 * r;
-            T acc = 0;
-            for (int s = sIp[r]; s < sIp[r + 1]; ++s) acc += L.F[s * 3 + c];
-            rhs[3 * (size_t)(r0 + r) + c] = acc;
+            rhs[3 * (size_t)(r0 + r) + c] = seq_sum<T>(L.F + c, 3, sIp[r], sIp[r + 1]);
         }
     }
     asm volatile("" ::"v"(pf_desc));  // keeps the prefetch (its value is not needed)
