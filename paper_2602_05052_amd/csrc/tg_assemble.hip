@@ -738,9 +738,21 @@ __device__ __forceinline__ void p2_reduce(const BlockLds<T> &L, const int *sRp, 
         }
         T *o = out + 9 * sRp[r] + 3 * jpos;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < 3; ++c) {
+            T *oc = o + c * 3 * m;
+            if constexpr (sizeof(T) == 8) {
+                // the three values as a 16-byte store at a 16-byte boundary and one 8-byte store
+                const bool odd = (reinterpret_cast<uintptr_t>(oc) & 8u) != 0;
+                double2 v2;
+                v2.x = odd ? acc[c * 3 + 1] : acc[c * 3];
+                v2.y = odd ? acc[c * 3 + 2] : acc[c * 3 + 1];
+                *reinterpret_cast<double2 *>(oc + (odd ? 1 : 0)) = v2;
+                oc[odd ? 0 : 2] = odd ? acc[c * 3] : acc[c * 3 + 2];
+            } else {
 #pragma unroll
-            for (int cc = 0; cc < 3; ++cc) o[c * 3 * m + cc] = acc[c * 3 + cc];
+                for (int cc = 0; cc < 3; ++cc) oc[cc] = acc[c * 3 + cc];
+            }
+        }
     }
 }
 
