@@ -736,21 +736,24 @@ __device__ __forceinline__ void p2_reduce(const BlockLds<T> &L, const int *sRp, 
 #pragma unroll
             for (int z = 0; z < 9; ++z) acc[z] += s0[z];
         }
-        T *o = out + 9 * sRp[r] + 3 * jpos;
+        // 32-bit offsets from the block's (uniform) output base
+        const unsigned ob = (unsigned)(9 * sRp[r] + 3 * jpos);
+        const unsigned base_odd = (unsigned)(reinterpret_cast<uintptr_t>(out) >> 3) & 1u;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            T *oc = o + c * 3 * m;
+            const unsigned oc = ob + (unsigned)(c * 3 * m);
             if constexpr (sizeof(T) == 8) {
                 // the three values as a 16-byte store at a 16-byte boundary and one 8-byte store
-                const bool odd = (reinterpret_cast<uintptr_t>(oc) & 8u) != 0;
+                const bool odd = ((oc + base_odd) & 1u) != 0;
                 double2 v2;
                 v2.x = odd ? acc[c * 3 + 1] : acc[c * 3];
                 v2.y = odd ? acc[c * 3 + 2] : acc[c * 3 + 1];
-                *reinterpret_cast<double2 *>(oc + (odd ? 1 : 0)) = v2;
-                oc[odd ? 0 : 2] = odd ? acc[c * 3] : acc[c * 3 + 2];
-            } else {
+                *reinterpret_cast<double2 *>(reinterpret_cast<char *>(out) + (oc + (odd ? 1u : 0u)) * 8u) = v2;
+                stg(out, oc + (odd ? 0u : 2u), odd ? acc[c * 3] : acc[c * 3 + 2]);
+            } else {  // one 12-byte store
+                T *o = out + oc;
 #pragma unroll
-                for (int cc = 0; cc < 3; ++cc) oc[cc] = acc[c * 3 + cc];
+                for (int cc = 0; cc < 3; ++cc) o[cc] = acc[c * 3 + cc];
             }
         }
     }
