@@ -102,6 +102,10 @@ typedef struct {
     int64_t sell_index_bytes;  /* bytes per column index of the CG iterations' sliced-ELL
                                   pattern: 2 (offsets from the row, when every column lies
                                   within 32767 of it) or 4 */
+    int64_t sell_uniform_len;  /* entries per row of every slice when all slices are padded
+                                  to the longest row (at most 1/32 more entries; the CG
+                                  iterations then locate slices without reading the slice
+                                  offsets), else 0 */
 } tg_pattern_info;
 
 /* Text of the last error on the calling thread; valid until its next tg_ call. */

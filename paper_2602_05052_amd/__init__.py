@@ -52,7 +52,7 @@ class _Info(ctypes.Structure):
                 ("n_blocks", ctypes.c_int64),
                 ("d_row_ptr", ctypes.c_void_p), ("d_col_idx", ctypes.c_void_p), ("device_bytes", ctypes.c_size_t),
                 ("n_slot", ctypes.c_int64), ("scratch_bytes", ctypes.c_size_t),
-                ("sell_index_bytes", ctypes.c_int64)]
+                ("sell_index_bytes", ctypes.c_int64), ("sell_uniform_len", ctypes.c_int64)]
 
 
 class ServerResult(ctypes.Structure):
@@ -232,6 +232,7 @@ class Pattern:
         self.device_bytes = info.device_bytes
         self.n_slot = info.n_slot
         self.sell_index_bytes = info.sell_index_bytes
+        self.sell_uniform_len = info.sell_uniform_len
         self.host_only = host_only
 
     def scratch_bytes(self) -> int:

@@ -84,6 +84,7 @@ tg_status create_device(tg_pattern &pt) {
     d.n_slices = h.sell_ptr.empty() ? 0 : (int64_t)h.sell_ptr.size() - 1;
     d.sell_nnz = h.sell_ptr.empty() ? 0 : (int64_t)h.sell_ptr.back();
     d.sell16 = !h.sell_off.empty();
+    d.sell_len = h.sell_len;
     if (e == hipSuccess) {
         const size_t sb = (size_t)std::max<int64_t>(1, d.sell_nnz) * sizeof(double);
         e = hipMalloc((void **)&d.sell_vals, sb);
@@ -228,6 +229,7 @@ tg_status tg_pattern_query(const tg_pattern *p, tg_pattern_info *info) {
     info->scratch_bytes = p->host_only ? 0 : p->dev.ws_bytes;
     info->n_slot = (int64_t)h.slot.size();
     info->sell_index_bytes = h.sell_off.empty() ? 4 : 2;
+    info->sell_uniform_len = h.sell_len;
     return ok();
 }
 

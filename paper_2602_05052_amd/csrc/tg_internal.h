@@ -90,6 +90,9 @@ struct HostPattern {
     std::vector<int32_t> sell_ptr;  // [n_slices+1]
     std::vector<int32_t> sell_col;  // [sell_ptr[n_slices]] or empty
     std::vector<int16_t> sell_off;  // [sell_ptr[n_slices]] or empty
+    // > 0 when every slice is padded to this many entries per row (sell_ptr[s] =
+    // 64 s sell_len): the CG iteration then locates a slice without reading sell_ptr
+    int32_t sell_len = 0;
     // Dirichlet.
     std::vector<uint8_t> constrained;  // [n_dofs] 0/1
     std::vector<int32_t> constrained_list;
@@ -179,6 +182,7 @@ struct DevicePattern {
     int32_t *sell_col = nullptr;     // [sell_nnz] 32-bit columns, or
     int16_t *sell_off = nullptr;     // [sell_nnz] 16-bit offsets from the row (sell16)
     bool sell16 = false;
+    int sell_len = 0;                // HostPattern::sell_len
     int64_t n_slices = 0, sell_nnz = 0;
     double *sell_vals = nullptr;     // the solo solver's sliced-ELL copy of the values (sell_nnz, used as T)
     // PCG workspace: kPcgWorkVectors vectors of n_dofs doubles (used as T), partials, state.

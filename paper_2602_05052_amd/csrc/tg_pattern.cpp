@@ -467,15 +467,29 @@ tg_status build_host_pattern(int dim, int order, int ncomp, int64_t nv, int64_t 
     // ---- sliced-ELL copy of the CSR pattern for the CG iterations: slice s holds
     // rows [64 s, 64 s + 64) (one row per lane of a wave); entry k of row r sits at
     // sell_ptr[s] + 64 k + (r - 64 s), and every row of a slice is padded to the
-    // slice's longest row (at least one entry) with its own index as column
+    // slice's longest row (at least one entry) with its own index as column; when
+    // padding every slice to the longest row of all adds at most 1/32 of the
+    // entries, every slice is (sell_len)
     {
         const int64_t nsl = (hp.n_dofs + kSellRows - 1) / kSellRows;
         hp.sell_ptr.assign(nsl + 1, 0);
+        std::vector<int32_t> slen(nsl, 1);
+        int64_t total = 0;
+        int32_t lmax = 1;
+        for (int64_t s = 0; s < nsl; ++s) {
+            for (int64_t r = s * kSellRows; r < std::min<int64_t>(hp.n_dofs, (s + 1) * kSellRows); ++r)
+                slen[s] = std::max(slen[s], hp.row_ptr[r + 1] - hp.row_ptr[r]);
+            total += slen[s];
+            lmax = std::max(lmax, slen[s]);
+        }
+        hp.sell_len = 0;
+        if (nsl > 0 && (int64_t)lmax * nsl * 32 <= total * 33) {
+            hp.sell_len = lmax;
+            std::fill(slen.begin(), slen.end(), lmax);
+        }
         int64_t off = 0;
         for (int64_t s = 0; s < nsl; ++s) {
-            int32_t len = 1;
-            for (int64_t r = s * kSellRows; r < std::min<int64_t>(hp.n_dofs, (s + 1) * kSellRows); ++r)
-                len = std::max(len, hp.row_ptr[r + 1] - hp.row_ptr[r]);
+            const int32_t len = slen[s];
             hp.sell_ptr[s] = (int32_t)off;
             off += (int64_t)len * kSellRows;
             if (off > INT32_MAX) {

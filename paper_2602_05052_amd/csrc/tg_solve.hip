@@ -512,7 +512,7 @@ __device__ __forceinline__ double row_tail_new_u(const TG_GLOBAL T *__restrict__
 // rows' records stay in one L2).
 template <typename T, bool CHECK_ONLY, bool SOLO, typename CI>
 __global__ __launch_bounds__(iter_threads<T>()) __attribute__((amdgpu_waves_per_eu(6)))
-void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const CI *__restrict__ sell_col,
+void pcg_iter_kernel(int n, int nsl, int ulen, const int32_t *__restrict__ sell_ptr, const CI *__restrict__ sell_col,
                      const PcgSlot *__restrict__ slots, const int32_t *__restrict__ list, PcgSlot solo, int step,
                      int n_prev_init, int n_prev) {
     constexpr int kThreads = iter_threads<T>(), W = kThreads / 64;
@@ -568,8 +568,8 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
     T f_val[kSplit ? 1 : R32];
     Rec<T> f_rec[kSplit ? 1 : R32];
     if constexpr (!CHECK_ONLY) {
-        e0 = sell_ptr[s0] + lane;
-        len0 = (sell_ptr[s0 + 1] - sell_ptr[s0]) >> 6;
+        e0 = ulen ? s0 * 64 * ulen + lane : sell_ptr[s0] + lane;
+        len0 = ulen ? ulen : (sell_ptr[s0 + 1] - sell_ptr[s0]) >> 6;
         if constexpr (kSplit) {
             if (sl0 < nsl && st->done == 0) row_products(sv, cols, i0, ra, e0, len0, A, B, C);
         } else {
@@ -654,7 +654,8 @@ void pcg_iter_kernel(int n, int nsl, const int32_t *__restrict__ sell_ptr, const
         const Rec<T> o = load_rec(ra, ic);
         const Diag<T> dk = load_dk(v.dk, ic);
         const T p_old = v.p[ic], x_old = x[ic];
-        const int e = sell_ptr[sl] + lane, len = (sell_ptr[sl + 1] - sell_ptr[sl]) >> 6;
+        const int e = ulen ? sl * 64 * ulen + lane : sell_ptr[sl] + lane;
+        const int len = ulen ? ulen : (sell_ptr[sl + 1] - sell_ptr[sl]) >> 6;
         double w;
         if constexpr (kSplit) {
             double a = 0.0, b = 0.0, c = 0.0;
@@ -794,10 +795,10 @@ void launch_step_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *li
         using CI = std::remove_const_t<std::remove_pointer_t<decltype(cols)>>;
         if (solo)
             hipLaunchKernelGGL((pcg_iter_kernel<T, false, true, CI>), dim3(ns, 1), dim3(iter_threads<T>()), 0, s, n,
-                               nsl, pt.dev.sell_ptr, cols, slots, list, *solo, step, ns0, ns);
+                               nsl, pt.dev.sell_len, pt.dev.sell_ptr, cols, slots, list, *solo, step, ns0, ns);
         else
             hipLaunchKernelGGL((pcg_iter_kernel<T, false, false, CI>), dim3(ns, count), dim3(iter_threads<T>()), 0, s,
-                               n, nsl, pt.dev.sell_ptr, cols, slots, list, PcgSlot{}, step, ns0, ns);
+                               n, nsl, pt.dev.sell_len, pt.dev.sell_ptr, cols, slots, list, PcgSlot{}, step, ns0, ns);
     };
     if (pt.dev.sell16)
         go((const int16_t *)pt.dev.sell_off);
@@ -810,7 +811,7 @@ void launch_check_t(const tg_pattern &pt, const PcgSlot *slots, const int32_t *l
                     hipStream_t s) {
     const int n = (int)pt.host.n_dofs;
     hipLaunchKernelGGL((pcg_iter_kernel<T, true, false, int32_t>), dim3(1, count), dim3(iter_threads<T>()), 0, s, n,
-                       (int)pt.dev.n_slices, pt.dev.sell_ptr, pt.dev.sell_col, slots, list, PcgSlot{}, step,
+                       (int)pt.dev.n_slices, 0, pt.dev.sell_ptr, pt.dev.sell_col, slots, list, PcgSlot{}, step,
                        spmv_blocks<G>(n), iter_blocks<T>(pt));
 }
 

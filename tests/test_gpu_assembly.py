@@ -234,6 +234,16 @@ def test_p2_elasticity_parity(n, dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_p2_shuffled_numbering_parity(dtype):
+    """Random vertex and element numbering and rotated local vertex lists: every pair frame (the
+    pair's node first) starts from an arbitrary local order."""
+    print(f"p2 shuffled dtype={dtype}", flush=True)
+    d = meshgen.elasticity_inputs(4, seed=3)
+    c2, t2, _, _, lam, mu, b = meshgen.shuffle_numbering(d["coords"], d["conn"], 7, d["lam"], d["mu"], d["b"])
+    _check_p2({"coords": c2, "conn": t2, "lam": lam, "mu": mu, "b": b}, dtype)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("m", [7, 40, 64])
 def test_p2_high_valence_parity(m, dtype):
     """Nodes shared by m tets (both apexes and their edge): 64 pairs in one row is the P2 block capacity."""

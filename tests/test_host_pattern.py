@@ -177,8 +177,12 @@ def test_p2_frame_rule():
     assert list(P2_FRAME[8]) == [1, 3, 0, 2, 8, 4, 7, 6, 9, 5]  # edge (1, 3): order (1, 3, 0, 2)
 
 
-def test_p2_pattern_routing_equals_oracle():
+@pytest.mark.parametrize("shuffle", [False, True])
+def test_p2_pattern_routing_equals_oracle(shuffle):
     d = meshgen.elasticity_inputs(2, seed=2)
+    if shuffle:  # arbitrary local vertex orders: every pair frame is a different permutation
+        c2, t2, _, _, lam, mu, b = meshgen.shuffle_numbering(d["coords"], d["conn"], 5, d["lam"], d["mu"], d["b"])
+        d = {"coords": c2, "conn": t2, "lam": lam, "mu": mu, "b": b}
     pat = tg.Pattern(d["conn"], len(d["coords"]), order=2, ncomp=3, host_only=True)
     A = oracle.assemble_p2_elasticity(d["coords"], d["conn"], d["lam"], d["mu"], d["b"])
     np.testing.assert_array_equal(pat.element_nodes(), A.nodes10)
@@ -438,6 +442,23 @@ def test_sell_index_width():
     small = meshgen.poisson_inputs(2, 12, seed=0)
     sp = np.random.default_rng(4).permutation(len(small["coords"])).astype(np.int32)
     assert tg.Pattern(sp[small["conn"]], len(small["coords"]), host_only=True).sell_index_bytes == 2
+
+
+def test_sell_uniform_slices():
+    """Slices are padded to one length when that adds at most 1/32 of the entries (the 64^3 structured
+    mesh: every slice 15 per row); a mesh with one long row keeps per-slice lengths."""
+    d = meshgen.poisson_inputs(3, 64, seed=0)
+    pat = tg.Pattern(d["conn"], len(d["coords"]), host_only=True)
+    ptr, _, _ = pat.sell()
+    assert pat.sell_uniform_len == 15 and np.all(np.diff(ptr) == 64 * 15)
+    m = 100  # fan of m triangles around vertex 0: row 0 has m + 1 entries
+    ang = np.linspace(0, 2 * np.pi, m, endpoint=False)
+    coords = np.concatenate([[[0.0, 0.0]], np.stack([np.cos(ang), np.sin(ang)], 1)])
+    conn = np.array([[0, 1 + i, 1 + (i + 1) % m] for i in range(m)], dtype=np.int32)
+    pat = tg.Pattern(conn, m + 1, host_only=True)
+    ptr, _, _ = pat.sell()
+    assert pat.sell_uniform_len == 0 and np.diff(ptr).max() == 64 * (m + 1) and np.diff(ptr).min() < 64 * (m + 1)
+    _check_sell(pat)
 
 
 def _check_sell(pat):
