@@ -4,18 +4,20 @@
 // One workgroup owns a block of consecutive CSR node rows.  Work inside it:
 //   Stage  : the distinct vertices of the block's elements (a list built with
 //            the pattern) are copied into LDS once.
-//   Map    : one lane (P1; 5 lanes for P2) per (row node i, element e, local
-//            node a) pair of the block.  It reads e's vertices from LDS, forms
-//            J, |det J| and the cofactors of J in FP64 (Alg. 1 Geometry),
-//            pushes the reference gradients forward (Push-forward), evaluates
-//            the per-element coefficients (Physics), and integrates row a of
-//            K_e and entry a of F_e with the quadrature rule (Integration,
-//            eq. kloc1).  The row goes to LDS.
+//   Map    : one lane per (row node i, element e, local node a) pair of the
+//            block (P2: in each of three waves, for a third of the column
+//            nodes).  It reads e's vertices from LDS, forms J, |det J| and the
+//            cofactors of J in FP64 (Alg. 1 Geometry), pushes the reference
+//            gradients forward (Push-forward), evaluates the per-element
+//            coefficients (Physics), and integrates row a of K_e and entry a
+//            of F_e (Integration, eq. kloc1: the quadrature rule, or for the
+//            P2 stiffness the exact integrals that rule gives).  The row goes
+//            to LDS.
 //   Reduce : one lane per CSR value (P1) or per 3x3 node block (P2) sums the
 //            element slots that the routing table maps to it (the S_mat
 //            projection of Alg. 2), in ascending element order, and writes it
 //            once; one lane per row sums its load contributions (the S_vec
-//            projection) and, for P1, the row's diagonal entry, whose terms
+//            projection) and the row's diagonal entry (block), whose terms
 //            are exactly the row's pairs in order, so it needs no slots.
 // K_local therefore never leaves the chip, every output is written exactly
 // once, and no atomics touch values: the result is bitwise reproducible and
