@@ -10,6 +10,9 @@
   vertices and node entries.
 - private_star: m tets that share one vertex and nothing else: the shared vertex's row (m pairs, one
   block of its own) stages 1 + 3 m distinct vertices and, in P2, holds 1 + 9 m node entries.
+- polar_disk: a 2D disk of `rings` rings of m vertices around a centre of valence m: one long CSR row
+  (m + 1 entries) among rows of about 7, so the CG iterations' sliced-ELL slices keep lengths of their
+  own (padding every slice to the longest would cost far more than 1/32).
 """
 import numpy as np
 
@@ -67,3 +70,20 @@ def private_star(m: int, seed: int):
         coords[1 + 3 * t:4 + 3 * t] = [2.0 * d, 2.0 * d + 0.5 * u, 2.0 * d + 0.5 * w]
         conn[t] = [0, 1 + 3 * t, 2 + 3 * t, 3 + 3 * t]
     return {"coords": coords, "conn": conn, **_coefficients(m, rng)}
+
+
+def polar_disk(m: int, rings: int, seed: int):
+    rng = np.random.default_rng(seed)
+    pts = [np.zeros(2)]
+    for k in range(1, rings + 1):
+        ang = 2 * np.pi * (np.arange(m) + 0.5 * (k % 2)) / m
+        pts.append(np.stack([np.cos(ang), np.sin(ang)], 1) * (k / rings))
+    coords = np.ascontiguousarray(np.vstack(pts))
+    ring = lambda k, j: 1 + (k - 1) * m + (j % m)  # noqa: E731
+    tri = [[0, ring(1, j), ring(1, j + 1)] for j in range(m)]
+    for k in range(1, rings):
+        for j in range(m):
+            tri.append([ring(k, j), ring(k + 1, j), ring(k + 1, j + 1)])
+            tri.append([ring(k, j), ring(k + 1, j + 1), ring(k, j + 1)])
+    conn = np.ascontiguousarray(np.array(tri, dtype=np.int32))
+    return {"coords": coords, "conn": conn, **_coefficients(len(conn), rng)}

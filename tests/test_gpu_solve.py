@@ -86,6 +86,26 @@ def test_pcg_32bit_and_16bit_columns_agree():
     assert np.linalg.norm(x32 - x16) <= 1e-8 * np.linalg.norm(x16)
 
 
+def test_pcg_with_per_slice_lengths():
+    """A pattern whose sliced-ELL slices keep lengths of their own (one row of 65 entries among rows of
+    about 7): the CG iterations read the slice offsets; the solve still meets the tolerance on the
+    oracle's condensed system and matches its direct solve."""
+    import special_meshes
+    d = special_meshes.polar_disk(64, 12, seed=4)
+    pat = tg.Pattern(d["conn"], len(d["coords"]))
+    assert pat.sell_uniform_len == 0
+    vals, rhs = tg.assemble(pat, tg.LAPLACE, torch.from_numpy(d["coords"]).cuda(), torch.from_numpy(d["a"]).cuda(),
+                            torch.from_numpy(d["f"]).cuda())
+    tg.apply_dirichlet(pat, vals, rhs)
+    x, iters, relres = tg.pcg(pat, vals, rhs, rtol=1e-10, max_iter=10000)
+    x = x.cpu().numpy()
+    A = oracle.assemble_p1(d["coords"], d["conn"], d["a"], d["f"])
+    bnd = np.sort(pat.constrained_dofs())
+    assert len(bnd) == 64 and relres <= 1e-10  # the outer ring
+    assert oracle.relres_lin(A, x, bnd) <= 2e-10
+    assert oracle.relerr(x, oracle.condensed_solve(A, bnd)) <= 1e-6
+
+
 def test_pcg_fp32():
     d, pat, vals, rhs = _setup(3, 12, dtype=torch.float32)
     tg.apply_dirichlet(pat, vals, rhs)
