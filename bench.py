@@ -389,6 +389,7 @@ def main():
             "achieved": PCG_ITER_BYTES_64 / t_iter / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": PCG_ITER_BYTES_64 / t_iter / 1e9 / HBM_PEAK_GBS,
             "traffic": stored_traffic(pcg_kernel),
+            "traffic_gbs": (stored_traffic(pcg_kernel) / t_iter / 1e9) if stored_traffic(pcg_kernel) else None,
             "algorithmic_bytes_per_launch": PCG_ITER_BYTES_64, "us_per_launch": t_iter * 1e6,
             "launches_per_step": int(np.median(iters)),
             "attainable_gbs": attainable_gbs,
@@ -396,7 +397,7 @@ def main():
         "roofline_assembly": {
             "bound": "hbm", "kernel": "p1_assemble_kernel<3,double,laplace> (the assembly: value = its elements/s)",
             "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-            "traffic": traffic,
+            "traffic": traffic, "traffic_gbs": (traffic / mean_asm / 1e9) if traffic else None,
             "algorithmic_bytes_per_launch": balg64, "bytes_per_element": balg64 / E,
             "b_min_bytes_per_launch": bmin64,
             "attainable_gbs": attainable_gbs, "frac_of_attainable": gbs / attainable_gbs,
