@@ -132,7 +132,7 @@ struct PcgSlot {
     const void *sell;    // T[sell_nnz]: the same values in the sliced-ELL layout (the iterations' SpMV)
     const void *b;       // T[n]
     void *x;             // T[n], the iterate (output)
-    void *work;          // T[kPcgWorkVectors n]: records {u, w/K_ii, s/K_ii} x 2 (by parity), p, {1/K_ii, K_ii}
+    void *work;          // T[kPcgWorkVectors n]: records {u, w/K_ii, s/K_ii} x 2 (by parity), p, 1/K_ii
     double *partials;    // [kNumPartials][kMaxGrid]
     PcgState *state;
     double rtol2;
@@ -156,8 +156,8 @@ constexpr int kFillThreads = 512;  // threads per block of the sliced-ELL fill: 
 // of an iterate at kGam/kDel/kRr + 3 (iteration & 1), and the true residual at kResid.
 constexpr int kGam = 0, kDel = 1, kRr = 2, kResid = 6, kNumPartials = 7;
 // Krylov workspace of one system, in vectors of n values of the dtype: two
-// records of 3 values per row (by iteration parity), p and two diagonal values.
-constexpr int kPcgWorkVectors = 9;
+// records of 3 values per row (by iteration parity), p and the Jacobi factor.
+constexpr int kPcgWorkVectors = 8;
 
 struct DevicePattern {
     int32_t *conn = nullptr;      // [E][dim+1]

@@ -228,23 +228,19 @@ struct Rec {  // the per-row record gathered by the SpMV (24 / 12 bytes): u = D^
     T u, w, s;
 };
 
-template <typename T>
-struct Diag {  // a row's D^{-1} = 1 / K_ii and K_ii
-    T d, k;
-};
-
 // A slot's workspace (kPcgWorkVectors vectors of n values): the records of even
-// and odd iterates (3 n each), p (n) and the diagonal pairs (2 n).
+// and odd iterates (3 n each), p (n) and the Jacobi factors D^{-1} = 1 / K_ii
+// (n; K_ii itself is recovered as 1 / D^{-1} where the inner products need it).
 template <typename T>
 struct SlotVecs {
     TG_GLOBAL Rec<T> *rec0, *rec1;
     TG_GLOBAL T *p;
-    TG_GLOBAL Diag<T> *dk;
+    TG_GLOBAL T *dinv;
     __device__ __forceinline__ SlotVecs(const PcgSlot &S, int n) {
         rec0 = gl((Rec<T> *)S.work);
         rec1 = rec0 + n;
         p = (TG_GLOBAL T *)(rec1 + n);
-        dk = (TG_GLOBAL Diag<T> *)(p + n);
+        dinv = p + n;
     }
     __device__ __forceinline__ TG_GLOBAL Rec<T> *rec(int parity) const { return parity ? rec1 : rec0; }
 };
@@ -261,17 +257,6 @@ __device__ __forceinline__ void store_rec(TG_GLOBAL Rec<T> *__restrict__ a, int 
     a[i].s = s;
 }
 
-template <typename T>
-__device__ __forceinline__ Diag<T> load_dk(const TG_GLOBAL Diag<T> *__restrict__ a, int i) {
-    return Diag<T>{a[i].d, a[i].k};
-}
-
-template <typename T>
-__device__ __forceinline__ void store_dk(TG_GLOBAL Diag<T> *__restrict__ a, int i, T d, T k) {
-    a[i].d = d;
-    a[i].k = k;
-}
-
 // The recurrences of a row's scaled s and u: the owner's update, and (FP32
 // iterations) every neighbour's view of the row's new u as an SpMV column.
 template <typename T>
@@ -283,7 +268,7 @@ __device__ __forceinline__ T next_u(const Rec<T> &o, T beta, T alpha) {
     return next_u_s(o, next_s(o, beta), alpha);
 }
 
-// x = 0, p = 0, u = D^{-1} b, s = 0, the diagonal pairs (record of parity 0; w follows).
+// x = 0, p = 0, u = D^{-1} b, s = 0, the Jacobi factors (record of parity 0; w follows).
 template <typename T>
 __global__ __launch_bounds__(kVecThreads) void pcg_init_kernel(int n, const PcgSlot *__restrict__ slots,
                                                                const int32_t *__restrict__ list,
@@ -297,13 +282,13 @@ __global__ __launch_bounds__(kVecThreads) void pcg_init_kernel(int n, const PcgS
         x[i] = (T)0;
         v.p[i] = (T)0;
         const T kii = values[diag_pos[i]], d = (T)1 / kii;
-        store_dk(v.dk, i, d, kii);
+        v.dinv[i] = d;
         store_rec(v.rec0, i, d * b[i], (T)0, (T)0);
     }
 }
 
-// Warm start: u = D^{-1} (b - K x) for the given x, p = 0, s = 0, the diagonal
-// pairs (record of parity 0; w follows), and per-block partials of b.b at kResid.
+// Warm start: u = D^{-1} (b - K x) for the given x, p = 0, s = 0, the Jacobi
+// factors (record of parity 0; w follows), and per-block partials of b.b at kResid.
 template <typename T, int G>
 __global__ __launch_bounds__(kVecThreads, 8) void pcg_warm_init_kernel(int n, const int32_t *__restrict__ row_ptr,
                                                                     const int32_t *__restrict__ col_idx,
@@ -325,7 +310,7 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_warm_init_kernel(int n, co
             const T bi = b[i];
             v.p[i] = (T)0;
             const T kii = values[diag_pos[i]], d = (T)1 / kii;
-            store_dk(v.dk, i, d, kii);
+            v.dinv[i] = d;
             store_rec(v.rec0, i, d * (T)((double)bi - kx), (T)0, (T)0);
             bb += (double)bi * (double)bi;
         }
@@ -373,9 +358,9 @@ __global__ __launch_bounds__(kVecThreads, 8) void pcg_init_spmv_kernel(int n, co
         }
         acc = group_sum<G>(acc);
         if (lane == 0) {
-            const Diag<T> dk = load_dk(v.dk, i);
-            const double ui = (double)rec[i].u, ri = (double)dk.k * ui;
-            rec[i].w = (T)((double)dk.d * acc);
+            const T d = v.dinv[i];
+            const double ui = (double)rec[i].u, ri = (double)((T)1 / d) * ui;
+            rec[i].w = (T)((double)d * acc);
             gam += ri * ui;
             del += acc * ui;
             rr += ri * ri;
@@ -561,7 +546,7 @@ void pcg_iter_kernel(int n, int nsl, int ulen, const int32_t *__restrict__ sell_
     const int s0 = min(sl0, nsl - 1);
     const int i0 = min(s0 * 64 + lane, n - 1);
     Rec<T> f_o{};
-    Diag<T> f_dk{};
+    T f_d = 0;
     T f_pold = 0, f_xold = 0;
     double A = 0.0, B = 0.0, C = 0.0;
     int e0 = 0, len0 = 0;
@@ -581,7 +566,7 @@ void pcg_iter_kernel(int n, int nsl, int ulen, const int32_t *__restrict__ sell_
             }
         }
         f_o = load_rec(ra, i0);
-        f_dk = load_dk(v.dk, i0);
+        f_d = v.dinv[i0];
         f_pold = v.p[i0];
         f_xold = x[i0];
     }
@@ -620,17 +605,17 @@ void pcg_iter_kernel(int n, int nsl, int ulen, const int32_t *__restrict__ sell_
     }
     const T alpha = (T)alpha_d, beta = (T)beta_d;
     double gn = 0.0, dn = 0.0, rn = 0.0;
-    // row i's update from its own record, diagonal pair, p, x and w = (K u_new)_i;
+    // row i's update from its own record, Jacobi factor d, p, x and w = (K u_new)_i;
     // the inner products with r = K_ii u
-    auto update_row = [&](int i, double w, const Rec<T> &o, const Diag<T> &dk, T p_old, T x_old) {
+    auto update_row = [&](int i, double w, const Rec<T> &o, T d, T p_old, T x_old) {
         const T pi = o.u + beta * p_old;  // u_i + beta p
         const T si = next_s(o, beta);
         const T ui = next_u_s(o, si, alpha);
         const T wi = (T)w;
         x[i] = x_old + alpha * pi;
         v.p[i] = pi;
-        store_rec(rb, i, ui, (T)((double)dk.d * w), si);
-        const double ud = (double)ui, rd = (double)dk.k * ud;
+        store_rec(rb, i, ui, (T)((double)d * w), si);
+        const double ud = (double)ui, rd = (double)((T)1 / d) * ud;
         gn += rd * ud;
         dn += (double)wi * ud;
         rn += rd * rd;
@@ -646,13 +631,13 @@ void pcg_iter_kernel(int n, int nsl, int ulen, const int32_t *__restrict__ sell_
                 if (u < len0) w += (double)f_val[u] * (double)next_u(f_rec[u], beta, alpha);
             w = row_tail_new_u(sv, cols, i0, ra, e0, R32, len0, alpha, beta, w);
         }
-        if (s0 * 64 + lane < n) update_row(s0 * 64 + lane, w, f_o, f_dk, f_pold, f_xold);
+        if (s0 * 64 + lane < n) update_row(s0 * 64 + lane, w, f_o, f_d, f_pold, f_xold);
     }
     for (int sl = sl0 + waves; sl < nsl; sl += waves) {  // systems with more slices than waves
         const int i = sl * 64 + lane;
         const int ic = min(i, n - 1);
         const Rec<T> o = load_rec(ra, ic);
-        const Diag<T> dk = load_dk(v.dk, ic);
+        const T dd = v.dinv[ic];
         const T p_old = v.p[ic], x_old = x[ic];
         const int e = ulen ? sl * 64 * ulen + lane : sell_ptr[sl] + lane;
         const int len = ulen ? ulen : (sell_ptr[sl + 1] - sell_ptr[sl]) >> 6;
@@ -664,7 +649,7 @@ void pcg_iter_kernel(int n, int nsl, int ulen, const int32_t *__restrict__ sell_
         } else {
             w = row_tail_new_u(sv, cols, ic, ra, e, 0, len, alpha, beta, 0.0);
         }
-        if (i < n) update_row(i, w, o, dk, p_old, x_old);
+        if (i < n) update_row(i, w, o, dd, p_old, x_old);
     }
     block_sum3_first<W>(gn, dn, rn, sh2);
     if (threadIdx.x == 0) {
